@@ -1,0 +1,107 @@
+"""The colour-code workload: code parameters fixed by the paper (Sec. II.A,
+App. A.1) and the circuit structure of Sec. III / Fig. 1."""
+import itertools
+
+import numpy as np
+import pytest
+
+from workload import (build_color_code, build_circuit, gf2_rank, edge_colouring,
+                      OP_CNOT, OP_INIT, OP_MEAS, OP_SRX, OP_AD, OP_PAULI,
+                      C_OP, C_Q0, C_Q1, C_TICK, C_LOC, C_DRAW, C_REC)
+
+
+@pytest.mark.parametrize("d,n,P,N", [(3, 7, 3, 13), (5, 19, 9, 37), (7, 37, 18, 73)])
+def test_code_counts(d, n, P, N):
+    # [[(3d^2+1)/4, 1, d]] and two ancillas per plaquette (Sec. II.A)
+    c = build_color_code(d)
+    assert c.n == n == (3 * d * d + 1) // 4
+    assert c.n_plaq == P
+    assert c.n_qubits == N
+    w = c.checks.sum(1)
+    assert set(w.tolist()) <= {4, 6}             # weight 4 on the boundary, 6 in the bulk
+    assert (c.checks.sum(0) <= 3).all()
+    # X and Z checks on the same supports commute iff every overlap is even
+    assert not ((c.checks.astype(int) @ c.checks.T.astype(int)) % 2).any()
+    # k = n - rank(H_X) - rank(H_Z) = 1
+    assert c.n - 2 * gf2_rank(c.checks) == 1
+    # three-colourable faces: touching faces differ in colour
+    for a, b in itertools.combinations(range(P), 2):
+        if (c.checks[a] & c.checks[b]).any():
+            assert c.colour[a] != c.colour[b]
+
+
+def _min_logical_weight(checks, max_w):
+    n = checks.shape[1]
+    rank = gf2_rank(checks)
+    for w in range(1, max_w + 1):
+        for sup in itertools.combinations(range(n), w):
+            v = np.zeros(n, dtype=np.uint8)
+            v[list(sup)] = 1
+            if ((checks.astype(int) @ v) % 2).any():
+                continue
+            # commutes with every check; logical iff not in the check row space
+            if gf2_rank(np.vstack([checks, v])) > rank:
+                return w
+    return None
+
+
+@pytest.mark.parametrize("d", [3, 5])
+def test_code_distance(d):
+    c = build_color_code(d)
+    assert _min_logical_weight(c.checks, d) == d
+
+
+@pytest.mark.parametrize("d,C,ch,ops,cnot,loc", [
+    (3, 1, "srx", 143, 24, 93), (3, 3, "ad", 387, 72, 265),
+    (5, 5, "srx", 2427, 420, 1789), (5, 3, "srx+ad", 2560, 252, 1081)])
+def test_op_counts(d, C, ch, ops, cnot, loc):
+    circ = build_circuit(d, C, ch)
+    c = circ.code
+    T = 4 if d == 3 else 6
+    n, P = c.n, c.n_plaq
+    assert circ.n_loc == 2 * C * (T * (n + P) + P) + n == loc
+    assert circ.count(OP_CNOT) == 2 * C * int(c.checks.sum()) == cnot
+    assert circ.count(OP_INIT) == circ.count(OP_MEAS) == 2 * P * C + n
+    assert circ.n_ops == ops
+    assert circ.n_rec == 2 * P * C + n
+
+
+def test_schedule_is_proper_and_complete():
+    for d in (3, 5, 7):
+        circ = build_circuit(d, 2, "srx")
+        ops = circ.ops
+        for t in np.unique(ops[:, C_TICK]):
+            sel = ops[(ops[:, C_TICK] == t) & (ops[:, C_OP] == OP_CNOT)]
+            qs = np.concatenate([sel[:, C_Q0], sel[:, C_Q1]])
+            assert len(qs) == len(set(qs.tolist()))          # one gate per qubit per tick
+        # every face/data edge appears once per phase, in both phases of every round
+        c = circ.code
+        cn = ops[ops[:, C_OP] == OP_CNOT]
+        assert len(cn) == 2 * circ.rounds * int(c.checks.sum())
+        col = edge_colouring(c.checks)
+        assert col.max() + 1 == (4 if d == 3 else 6)
+
+
+def test_noise_every_live_qubit_every_cnot_tick():
+    circ = build_circuit(5, 1, "srx")
+    ops = circ.ops
+    c = circ.code
+    for t in np.unique(ops[:, C_TICK]):
+        sel = ops[ops[:, C_TICK] == t]
+        if (sel[:, C_OP] == OP_CNOT).any():
+            noisy = sel[sel[:, C_OP] == OP_SRX][:, C_Q0]
+            assert len(noisy) == c.n + c.n_plaq == len(set(noisy.tolist()))
+        if (sel[:, C_OP] == OP_MEAS).any():
+            assert not (sel[:, C_OP] == OP_SRX).any()       # measurements are noiseless
+
+
+def test_indices_dense():
+    circ = build_circuit(3, 3, "srx+ad")
+    ops = circ.ops
+    locs = ops[ops[:, C_LOC] >= 0][:, C_LOC]
+    assert set(locs.tolist()) == set(range(circ.n_loc))
+    draws = ops[ops[:, C_DRAW] >= 0][:, C_DRAW]
+    assert sorted(draws.tolist()) == list(range(circ.n_draws))
+    recs = ops[ops[:, C_OP] == OP_MEAS][:, C_REC]
+    assert sorted(recs.tolist()) == list(range(circ.n_rec))
+    assert circ.n_ad == circ.count(OP_AD) == circ.n_loc
