@@ -1,0 +1,238 @@
+/*
+ * ttn.h -- C ABI of the MI355X (gfx950) tree-tensor-network trajectory engine.
+ *
+ * The engine simulates Monte Carlo quantum trajectories (Sec. III.C of
+ * Barone, Jaschke, Siloi, Montangero, "Color code thresholds under
+ * circuit-level noise beyond the Pauli framework") of a batch of B
+ * independent pure states, each stored as a binary tree tensor network
+ * (Sec. III.B, App. B / Fig. 7): a complete binary tree over L = 2^D leaves,
+ * one qubit per leaf (unused leaves allowed), 3-leg node tensors
+ * T[a][b][u] (left child, right child, parent), kept in canonical form around
+ * an isometry centre.  Gates act along the tree path between the two leaves;
+ * bonds are truncated to chi_max by dropping the smallest Schmidt values
+ * (Sec. IV.A).  Noise channels are the systematic X rotation (SRX, Eq. 1) and
+ * amplitude damping unravelled by its Kraus operators (Eq. 2-3), plus their
+ * Pauli twirls (Eq. 9).
+ *
+ * Conventions common to every entry point
+ *  - Every function returns ttn_status: TTN_OK (0) or a negative error code.
+ *    No C++ exception crosses the ABI.  ttn_last_error(ctx) returns the last
+ *    message for that context (valid until the next call on it).
+ *  - Device pointers are plain HIP device addresses (e.g. torch tensor
+ *    data_ptr()); host pointers are marked "host".  The caller owns every
+ *    input/output buffer; the context owns its tensor pool and workspaces.
+ *  - Work is enqueued on the context's HIP stream and is asynchronous unless
+ *    marked [sync].  One context = one stream; a context is not thread-safe.
+ *  - Trajectory row r of a batch uses the random stream keyed by
+ *    (seed, traj_offset + r): Philox4x64-10, draw k = 64-bit word k mod 4 of
+ *    the block at counter (k/4 + 1, 0, 0, 0), u = (w >> 11) * 2^-53.  Results
+ *    therefore do not depend on B or on how rows are split into batches.
+ *  - Precision: dtype TTN_C64 stores tensors in complex64 and contracts on
+ *    FP32 MFMA with FP32 accumulation; Gram matrices, eigen-decompositions,
+ *    norms and Born/Kraus probabilities are FP64.  TTN_C128 is FP64
+ *    throughout.
+ *
+ * Error codes
+ *  TTN_EINVAL     bad argument (qubit out of range, q0 == q1, non-finite or
+ *                 unsupported matrix, chi_max < 1, unknown dtype/basis,
+ *                 bad sizes); nothing was enqueued.
+ *  TTN_ENOMEM     device allocation failed (reduce the batch).
+ *  TTN_EDEVICE    a HIP runtime call failed.
+ *  TTN_ENONFINITE a trajectory's norm became zero or non-finite; the row is
+ *                 flagged (ttn_stats.flagged_rows) and the others continue.
+ *  TTN_EPROB      a forced outcome had probability < 1e-300; log P = -inf is
+ *                 written for that row.
+ */
+#ifndef TTN_H_
+#define TTN_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ttn_status;
+enum {
+  TTN_OK = 0,
+  TTN_EINVAL = -1,
+  TTN_ENOMEM = -2,
+  TTN_EDEVICE = -3,
+  TTN_ENONFINITE = -4,
+  TTN_EPROB = -5
+};
+
+enum { TTN_C64 = 0, TTN_C128 = 1 };
+
+/* op-list record: 9 int32 per op (see ttn_oplist_upload) */
+enum { TTN_OP_INIT = 0, TTN_OP_CNOT = 1, TTN_OP_SRX = 2, TTN_OP_AD = 3, TTN_OP_PAULI = 4, TTN_OP_MEAS = 5 };
+
+typedef struct ttn_ctx ttn_ctx;
+typedef struct ttn_oplist ttn_oplist;
+
+typedef struct {
+  int32_t n_qubits;              /* N >= 1 */
+  const int32_t* leaf_of_qubit;  /* host [n_qubits], injective into [0, L), L = smallest power of 2 >= N (>= 2) */
+  int32_t chi_max;               /* bond-dimension cap (>= 1) */
+  double cutoff;                 /* keep Schmidt values with s^2 / sum s^2 > cutoff (>= 0) */
+  int32_t dtype;                 /* TTN_C64 or TTN_C128 */
+  int32_t batch;                 /* B trajectories held by the context (>= 1) */
+  uint64_t seed;                 /* random stream key, first word */
+  void* stream;                  /* hipStream_t, NULL = default stream */
+} ttn_config;
+
+typedef struct {
+  int32_t max_rank;          /* largest bond dimension over rows and bonds at the end */
+  double discarded_weight;   /* sum over rows and truncations of the discarded fraction */
+  int64_t degenerate_cuts;   /* cuts that fell inside a near-degenerate cluster */
+  int32_t flagged_rows;      /* rows with a non-finite/zero norm or an impossible forced outcome */
+  int64_t hops;              /* isometry-centre moves per row */
+  int64_t launches;          /* kernel launches enqueued */
+  double gemm_flops;         /* real flops of the contraction GEMMs, padded shapes, whole batch */
+  double gram_flops;         /* real flops of the FP64 Gram GEMMs, padded shapes, whole batch */
+} ttn_stats;
+
+/* [sync] Validates the configuration and allocates the tensor pool and
+ * workspaces for `batch` rows.  The state is the product |0...0>. */
+ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out);
+
+/* [sync] Frees everything the context owns (waits for its stream). */
+ttn_status ttn_destroy(ttn_ctx* ctx);
+
+const char* ttn_last_error(const ttn_ctx* ctx);
+
+/* Product state (Sec. III: data start in |0>): qubit q in |0> (basis[q] = 0)
+ * or |+> (basis[q] = 1), all bonds of dimension 1, centre at the root.
+ * basis: host [n_qubits] or NULL (all |0>). */
+ttn_status ttn_init_product(ttn_ctx* ctx, const uint8_t* basis);
+
+/* Apply a 2x2 matrix to qubit q of every row.  u: device float64
+ * [rows][2][2][2] = (row-major matrix, re/im); row stride 8 doubles, or 0 to
+ * broadcast one matrix.  A unitary on a physical leg keeps the canonical
+ * form, so no centre move is made; a non-unitary matrix must be followed by
+ * a measurement or explicit renormalisation by the caller. */
+ttn_status ttn_apply_1q(ttn_ctx* ctx, int32_t q, const double* u, int64_t row_stride);
+
+/* Apply a 4x4 gate (host float64 [4][4][2], row-major, q0 the high bit) to
+ * qubits q0 != q1.  Sibling leaves: applied on their shared node.  Otherwise
+ * the gate must be controlled on one of the two qubits (block diagonal in
+ * its index, e.g. CNOT, CZ): it is split as sum_k |k><k| (x) B_k, the index
+ * k is carried along the tree path from one leaf to the other while the
+ * centre moves (exact, only numerically zero Schmidt values dropped), and a
+ * sweep back truncates every bond of the path to chi_max / cutoff.
+ * Returns TTN_EINVAL for a non-controlled gate between non-siblings. */
+ttn_status ttn_apply_2q(ttn_ctx* ctx, int32_t q0, int32_t q1, const double* g);
+
+/* Born-rule measurement of qubit q in basis 0 (Z) or 1 (X), outcome 0 = the
+ * +1 eigenvector.  Moves the isometry centre to q's node, computes
+ * p0 = |Pi_0 psi|^2 / |psi|^2 in FP64, takes outcome 0 iff u < p0 with
+ * u = draw `draw` of the row's stream (or the forced outcome), projects and
+ * rescales to unit norm, and adds log p(outcome) to logp.
+ * forced: device uint8 [rows] or NULL; bits: device uint8 [rows] (out);
+ * logp: device float64 [rows] (accumulated). */
+ttn_status ttn_measure_project(ttn_ctx* ctx, int32_t q, int32_t basis, const uint8_t* forced,
+                               uint8_t* bits, double* logp, uint64_t traj_offset, int32_t draw);
+
+/* Quantum jump of a two-outcome Kraus channel {K0, K1} on qubit q (Eq. 2-3
+ * for amplitude damping): p1 = |K1 psi|^2 / |psi|^2 (FP64, centre at q),
+ * branch 1 iff u < p1 (or forced), psi -> K_branch psi / sqrt(p_branch),
+ * logp += log p_branch.  k: device float64 [rows][2][2][2][2] =
+ * (K0, K1; row-major; re/im), row stride 16 doubles or 0 to broadcast.
+ * forced: device int8 [rows] or NULL; branch: device int8 [rows] (out). */
+ttn_status ttn_kraus_jump(ttn_ctx* ctx, int32_t q, const double* k, int64_t row_stride,
+                          const int8_t* forced, int8_t* branch, double* logp,
+                          uint64_t traj_offset, int32_t draw);
+
+/* [sync] Upload an op list: host int32 [n_ops][9] with columns
+ *   op, q0, q1, arg, loc, draw, rec, prev, tick
+ * op: TTN_OP_INIT (q0 prepared in basis arg = 0 |0> / 1 |+> from its known
+ *     previous state: never measured (prev = -1) or measured in basis prev
+ *     with the outcome in record column rec -- the reset),
+ *     TTN_OP_CNOT (control q0, target q1), TTN_OP_SRX (exp(-i theta X/2),
+ *     theta = theta[row][loc]), TTN_OP_AD (amplitude damping, gamma[row][loc],
+ *     draw), TTN_OP_PAULI (twirled channel: arg 0 = SRX twirl, 1 = AD twirl,
+ *     draw), TTN_OP_MEAS (basis arg, record column rec, draw).
+ * n_loc / n_rec / n_draws: parameter columns, record bits, draws per row. */
+ttn_status ttn_oplist_upload(ttn_ctx* ctx, const int32_t* ops, int32_t n_ops, int32_t n_loc,
+                             int32_t n_rec, int32_t n_draws, ttn_oplist** out);
+ttn_status ttn_oplist_free(ttn_oplist* ol);
+
+/* Run the whole op list on every row, starting from the product state
+ * (ttn_init_product is called internally with every qubit in |0>).
+ * theta, gamma: device float64 [rows][n_loc] with row stride params_stride
+ * (0 = broadcast one row); may be NULL when the op list has no such op.
+ * records: device uint8 [rows][n_rec]; branches: device int8 [rows][n_ad]
+ * (n_ad = number of AD ops; may be NULL if none); logp: device float64
+ * [rows] (overwritten with sum log p).  st: host, may be NULL; filling it
+ * synchronises the stream. */
+ttn_status ttn_batch_run_circuit(ttn_ctx* ctx, const ttn_oplist* ol, const double* theta,
+                                 const double* gamma, int64_t params_stride, uint64_t traj_offset,
+                                 uint8_t* records, int8_t* branches, double* logp, ttn_stats* st);
+
+/* log P(record) of given records and Kraus branches (the sampled events are
+ * forced instead of drawn): same op list and parameters as above; records
+ * device uint8 [rows][n_rec], branches device int8 [rows][n_ad] (NULL if
+ * no AD op); logp device float64 [rows] (out). */
+ttn_status ttn_log_prob(ttn_ctx* ctx, const ttn_oplist* ol, const uint8_t* records,
+                        const int8_t* branches, const double* theta, const double* gamma,
+                        int64_t params_stride, double* logp, ttn_stats* st);
+
+/* Logical readout (final-data lookup decoder): fail[row] = parity of the
+ * data bits XOR parity of the minimum-weight correction of their Z-check
+ * syndrome.  data_rec: host int32 [n_data] record columns of the final data
+ * bits (n_data <= 64); checks: host uint8 [n_checks][n_data] incidence
+ * (n_checks <= 24).  records: device uint8 [rows][n_rec]; fail: device uint8
+ * [rows].  Builds the leader table on the host (breadth-first search over
+ * single flips, qubits in ascending order) and decodes on the device. */
+ttn_status ttn_decode(ttn_ctx* ctx, const uint8_t* records, int32_t n_rec, const int32_t* data_rec,
+                      int32_t n_data, const uint8_t* checks, int32_t n_checks, uint8_t* fail);
+
+/* Move the isometry centre through every node (depth-first) so each bond is
+ * re-decomposed and truncated with the context's rule; afterwards the bond
+ * dimensions are the Schmidt ranks above the cutoff. */
+ttn_status ttn_compress(ttn_ctx* ctx);
+
+/* [sync] Test exports.  ttn_to_statevector contracts row `row` into all
+ * 2^N amplitudes (qubit 0 the most significant bit), amp: device float64
+ * [2^N][2], N <= 26.  ttn_bond_dims writes the current dimension of the
+ * bond above every node 1..L-1 of row `row` (node 1 = root, children 2i,
+ * 2i+1) to dims: host int32 [L] (dims[0] unused). */
+ttn_status ttn_to_statevector(ttn_ctx* ctx, int32_t row, double* amp);
+ttn_status ttn_bond_dims(ttn_ctx* ctx, int32_t row, int32_t* dims);
+
+/* [sync] Uniforms of the rows' streams: out device float64 [rows][n_draws]
+ * for rows traj_offset .. traj_offset + rows - 1. */
+ttn_status ttn_uniforms(ttn_ctx* ctx, uint64_t traj_offset, int32_t rows, int32_t n_draws, double* out);
+
+/* Host-side evaluation of the same counter-based generator (no GPU needed). */
+double ttn_philox_uniform_host(uint64_t seed, uint64_t traj, uint64_t draw);
+
+/* [sync] Kernel-level test exports (not part of the simulation path; the
+ * same kernels the engine launches).  Buffers are device memory of the
+ * context's dtype (complex64 = 2 floats, complex128 = 2 doubles per
+ * element); *_elems give their sizes in complex elements and the call fails
+ * with TTN_EINVAL if the operation would reach past them.
+ *  ttn_test_leg_apply: out[t][..a..] = sum_i W[t][a][i] T[t][..i..] on leg
+ *    `leg` (0, 1, 2) of T [rows][d0][d1][d2]; W [rows][newd][n], n = d[leg].
+ *  ttn_test_gram: G[t][i][j] = sum over the other legs of
+ *    conj(T[..i..]) T[..j..], G float64 [rows][n][n][2] (FP64 accumulation).
+ *  ttn_test_eigh: the factors of a centre move computed from G (as in
+ *    ttn_ctx's hops): W_iso[t][a][i] = V[i][a] / s_a, W_abs[t][a][i] =
+ *    conj(V[i][a]) s_a / |s_kept|, a < rank[t] in descending s, zero beyond;
+ *    rows <= batch, n <= 2 * min(chi_max, ...) of the context. */
+ttn_status ttn_test_leg_apply(ttn_ctx* ctx, int32_t rows, const int32_t* dims3, int32_t leg, const void* T,
+                              int64_t t_elems, const void* W, int64_t w_elems, int32_t newd, void* out,
+                              int64_t out_elems);
+ttn_status ttn_test_gram(ttn_ctx* ctx, int32_t rows, const int32_t* dims3, int32_t leg, const void* T,
+                         int64_t t_elems, double* G, int64_t g_elems);
+ttn_status ttn_test_eigh(ttn_ctx* ctx, int32_t rows, int32_t n, int32_t new_pad, int32_t cap, double cutoff,
+                         const double* G, int64_t g_elems, void* W_iso, void* W_abs, int64_t w_elems,
+                         int32_t* rank);
+
+/* Library build identification (no GPU needed). */
+const char* ttn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TTN_H_ */

@@ -1,0 +1,343 @@
+// FP64 Hermitian eigen-decomposition of the per-trajectory bond Gram matrix
+// by cyclic two-sided Jacobi, and the factors of the isometry-centre move.
+//
+// The Gram matrix G = M^H M of the node reshaped with the bond as its column
+// index has eigenvalues s_a^2 (the squared singular values of M, i.e. the
+// squared Schmidt values when the rest of the network is an isometry) and
+// eigenvectors V (the right singular vectors).  The centre moves across the
+// bond by M = (M V S^-1) (S V^H): the first factor stays behind as the new
+// isometry, the second is absorbed by the neighbour.  Truncation keeps the
+// largest s_a with s_a^2 / sum s^2 > cutoff, at most `cap` of them, and
+// renormalises the kept part (the paper truncates the smallest Schmidt
+// coefficients, Sec. IV.A).
+//
+// One 256-thread workgroup per trajectory.  G lives in LDS as its packed
+// upper triangle (<= 132 KB at n = 128).  Each Jacobi step rotates n/2
+// disjoint index pairs chosen by the round-robin (circle) schedule, so every
+// pair is visited once per sweep; a step updates every 2 x 2 block
+// (P, Q) of G by J_P^H G_PQ J_Q.  For n <= 64 the eigenvectors are
+// accumulated in LDS next to G; for larger n each step's rotations are
+// written to a log that a second kernel replays onto row blocks of V.
+#include "ttn_device.h"
+#include "ttn_kernels.h"
+
+namespace ttn {
+
+constexpr int kMaxSweeps = 24;
+constexpr int kVLdsMax = 64;
+int eigh_max_sweeps() { return kMaxSweeps; }
+
+__device__ inline int pidx(int i, int j, int n) {   // packed upper triangle, i <= j
+  return i * (2 * n - i + 1) / 2 + (j - i);
+}
+__device__ inline double2 gget(const double2* Gp, int i, int j, int n) {
+  return (i <= j) ? Gp[pidx(i, j, n)] : cconj(Gp[pidx(j, i, n)]);
+}
+__device__ inline void gset(double2* Gp, int i, int j, int n, double2 v) {
+  if (i <= j) Gp[pidx(i, j, n)] = v;
+  else Gp[pidx(j, i, n)] = cconj(v);
+}
+__device__ inline void pair_of(int n, int s, int j, int* p, int* q) {
+  int a, b;
+  if (j == 0) { a = n - 1; b = s; }
+  else { a = (s + j) % (n - 1); b = (s - j + n - 1) % (n - 1); }
+  *p = a < b ? a : b;
+  *q = a < b ? b : a;
+}
+
+struct Rot { double c; double2 s; double delta; };
+
+template <typename S>
+__device__ void write_factors(const EighDesc& d, long long t, int row_lo, int row_hi,
+                              const double2* Vrows /* rows [row_lo,row_hi) x n2 */, int n2,
+                              const int* order, const double* lam_sorted, int k, double scale_abs) {
+  S* Wi = (S*)d.W_iso + t * (long long)d.new_pad * d.n;
+  S* Wa = (S*)d.W_abs + t * (long long)d.new_pad * d.n;
+  const int nrows = row_hi - row_lo;
+  for (int idx = threadIdx.x; idx < d.new_pad * nrows; idx += blockDim.x) {
+    const int a = idx / nrows;
+    const int i = row_lo + idx % nrows;
+    double2 wi = make_double2(0.0, 0.0), wa = make_double2(0.0, 0.0);
+    if (a < k) {
+      const double2 v = Vrows[(long long)(i - row_lo) * n2 + order[a]];
+      const double s = sqrt(lam_sorted[a]);
+      wi = cscale(v, 1.0 / s);
+      wa = cscale(cconj(v), s * scale_abs);
+    }
+    Wi[(long long)a * d.n + i] = from_d2<S>(wi);
+    Wa[(long long)a * d.n + i] = from_d2<S>(wa);
+  }
+}
+
+template <bool kVinLds>
+__global__ void __launch_bounds__(256) k_jacobi(EighDesc d) {
+  extern __shared__ double2 smem[];
+  const long long t = blockIdx.x;
+  const int n = d.n;
+  const int n2 = n + (n & 1);          // even size, a zero dummy index if odd
+  const int h = n2 / 2;
+  const int npk = n2 * (n2 + 1) / 2;
+  double2* Gp = smem;                                  // packed G
+  double2* V = smem + npk;                             // [n2][n2] if kVinLds
+  __shared__ Rot rot[64];
+  __shared__ double lam[128];
+  __shared__ int order_s[128];
+  __shared__ double red[256];
+  __shared__ int any_rot;
+  __shared__ double trace_s;
+  const double2* G = d.G + t * (long long)n * n;
+
+  for (int idx = threadIdx.x; idx < npk; idx += blockDim.x) {
+    // decode packed index -> (i, j)
+    int i = 0, rem = idx;
+    while (rem >= n2 - i) { rem -= n2 - i; ++i; }
+    const int j = i + rem;
+    Gp[idx] = (i < n && j < n) ? G[(long long)i * n + j] : make_double2(0.0, 0.0);
+  }
+  if (kVinLds)
+    for (int idx = threadIdx.x; idx < n2 * n2; idx += blockDim.x)
+      V[idx] = make_double2((idx / n2 == idx % n2) ? 1.0 : 0.0, 0.0);
+  __syncthreads();
+  // trace (for the absolute rotation floor)
+  double part = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) part += Gp[pidx(i, i, n2)].x;
+  red[threadIdx.x] = part;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) trace_s = red[0];
+  __syncthreads();
+  const double tr = trace_s;
+  const bool finite = isfinite(tr) && tr > 0.0;
+
+  int step_count = 0;
+  double* log = d.rot_log ? d.rot_log + t * (long long)d.max_steps * h * 3 : nullptr;
+  if (n2 >= 2 && finite) {
+    for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+      if (threadIdx.x == 0) any_rot = 0;
+      __syncthreads();
+      for (int s = 0; s < n2 - 1; ++s) {
+        // -- rotation parameters of the n2/2 pairs --
+        if (threadIdx.x < h) {
+          int p, q;
+          pair_of(n2, s, threadIdx.x, &p, &q);
+          const double a = Gp[pidx(p, p, n2)].x, dd = Gp[pidx(q, q, n2)].x;
+          const double2 b = Gp[pidx(p, q, n2)];
+          const double ab = sqrt(cabs2(b));
+          Rot r;
+          r.c = 1.0; r.s = make_double2(0.0, 0.0); r.delta = 0.0;
+          if (ab > 1e-15 * sqrt(fabs(a * dd)) && ab > 1e-16 * tr && ab > 0.0) {
+            const double th = (dd - a) / (2.0 * ab);
+            const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+            const double c = 1.0 / sqrt(1.0 + tt * tt);
+            const double sn = tt * c;
+            r.c = c;
+            r.s = make_double2(sn * b.x / ab, sn * b.y / ab);
+            r.delta = tt * ab;
+            any_rot = 1;
+          }
+          rot[threadIdx.x] = r;
+          if (!kVinLds && log) {
+            double* e = log + ((long long)step_count * h + threadIdx.x) * 3;
+            e[0] = r.c; e[1] = r.s.x; e[2] = r.s.y;
+          }
+        }
+        __syncthreads();
+        // -- G <- J^H G J, block by block --
+        for (int idx = threadIdx.x; idx < h * h; idx += blockDim.x) {
+          const int P = idx / h, Q = idx % h;
+          if (P > Q) continue;
+          int p, q, pp, qq;
+          pair_of(n2, s, P, &p, &q);
+          const Rot rP = rot[P];
+          if (P == Q) {
+            if (rP.delta != 0.0) {
+              double2 gpp = Gp[pidx(p, p, n2)], gqq = Gp[pidx(q, q, n2)];
+              gpp.x -= rP.delta; gpp.y = 0.0;
+              gqq.x += rP.delta; gqq.y = 0.0;
+              Gp[pidx(p, p, n2)] = gpp;
+              Gp[pidx(q, q, n2)] = gqq;
+              Gp[pidx(p, q, n2)] = make_double2(0.0, 0.0);
+            }
+            continue;
+          }
+          pair_of(n2, s, Q, &pp, &qq);
+          const Rot rQ = rot[Q];
+          if (rP.delta == 0.0 && rQ.delta == 0.0) continue;
+          const double2 g00 = gget(Gp, p, pp, n2), g01 = gget(Gp, p, qq, n2);
+          const double2 g10 = gget(Gp, q, pp, n2), g11 = gget(Gp, q, qq, n2);
+          // X = G_PQ J_Q,  J = [[c, s], [-conj(s), c]]
+          const double2 sQc = cconj(rQ.s);
+          const double2 x00 = csub(cscale(g00, rQ.c), cmul(g01, sQc));
+          const double2 x01 = cadd(cmul(g00, rQ.s), cscale(g01, rQ.c));
+          const double2 x10 = csub(cscale(g10, rQ.c), cmul(g11, sQc));
+          const double2 x11 = cadd(cmul(g10, rQ.s), cscale(g11, rQ.c));
+          // Y = J_P^H X,  J^H = [[c, -s], [conj(s), c]]
+          const double2 sPc = cconj(rP.s);
+          gset(Gp, p, pp, n2, csub(cscale(x00, rP.c), cmul(rP.s, x10)));
+          gset(Gp, p, qq, n2, csub(cscale(x01, rP.c), cmul(rP.s, x11)));
+          gset(Gp, q, pp, n2, cadd(cmul(sPc, x00), cscale(x10, rP.c)));
+          gset(Gp, q, qq, n2, cadd(cmul(sPc, x01), cscale(x11, rP.c)));
+        }
+        if (kVinLds) {
+          // V <- V J (columns p, q of every row)
+          for (int idx = threadIdx.x; idx < n2 * h; idx += blockDim.x) {
+            const int r = idx / h, P = idx % h;
+            const Rot rP = rot[P];
+            if (rP.delta == 0.0) continue;
+            int p, q;
+            pair_of(n2, s, P, &p, &q);
+            const double2 vp = V[r * n2 + p], vq = V[r * n2 + q];
+            V[r * n2 + p] = csub(cscale(vp, rP.c), cmul(cconj(rP.s), vq));
+            V[r * n2 + q] = cadd(cmul(rP.s, vp), cscale(vq, rP.c));
+          }
+        }
+        ++step_count;
+        __syncthreads();
+      }
+      if (any_rot == 0) break;
+      __syncthreads();
+    }
+  }
+  // -- eigenvalues, descending order, truncation --
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double l = Gp[pidx(i, i, n2)].x;
+    lam[i] = (isfinite(l) && l > 0.0) ? l : 0.0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    int rk = 0;
+    const double li = lam[i];
+    for (int j = 0; j < n; ++j) rk += (lam[j] > li) || (lam[j] == li && j < i);
+    order_s[rk] = i;
+  }
+  __syncthreads();
+  __shared__ int k_s;
+  __shared__ double scale_s;
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int i = 0; i < n; ++i) tot += lam[i];
+    int k = 0;
+    double kept = 0.0;
+    const int lim = min(min(d.cap, d.new_pad), n);
+    if (finite && tot > 0.0) {
+      while (k < lim && lam[order_s[k]] > d.cutoff * tot) { kept += lam[order_s[k]]; ++k; }
+    }
+    if (!(kept > 0.0) || !isfinite(kept)) {
+      k = 0;
+      if (d.flags) d.flags[t] |= 1;
+      scale_s = 0.0;
+    } else {
+      scale_s = 1.0 / sqrt(kept);
+    }
+    if (d.disc_acc && tot > 0.0) d.disc_acc[t] += (tot - kept) / tot;
+    if (d.degen_acc && k > 0 && k < n) {
+      const double lk1 = lam[order_s[k - 1]], lk = lam[order_s[k]];
+      if (lk > d.cutoff * tot && lk1 - lk <= 1e-6 * lk1) d.degen_acc[t] += 1;
+    }
+    if (d.rank_out) d.rank_out[t * d.rank_stride] = k;
+    k_s = k;
+    if (!kVinLds) {
+      d.kept[t] = k;
+      d.scale_abs[t] = scale_s;
+      d.nsteps[t] = step_count;
+    }
+  }
+  __syncthreads();
+  if (kVinLds) {
+    __shared__ double lam_sorted[128];
+    for (int a = threadIdx.x; a < n; a += blockDim.x) lam_sorted[a] = lam[order_s[a]];
+    __syncthreads();
+    if (d.out_c128)
+      write_factors<double2>(d, t, 0, n, V, n2, order_s, lam_sorted, k_s, scale_s);
+    else
+      write_factors<float2>(d, t, 0, n, V, n2, order_s, lam_sorted, k_s, scale_s);
+  } else {
+    for (int a = threadIdx.x; a < n; a += blockDim.x) {
+      d.order[t * n + a] = order_s[a];
+      d.lam_sorted[t * n + a] = lam[order_s[a]];
+    }
+  }
+}
+
+// Replay the rotation log onto a block of rows of V = I and write the factors.
+constexpr int kRowsPerBlock = 32;
+__global__ void __launch_bounds__(256) k_jacobi_vectors(EighDesc d) {
+  extern __shared__ double2 smem[];
+  const int n = d.n;
+  const int n2 = n + (n & 1);
+  const int h = n2 / 2;
+  const int nblk = (n + kRowsPerBlock - 1) / kRowsPerBlock;
+  const long long t = blockIdx.x / nblk;
+  const int row_lo = (blockIdx.x % nblk) * kRowsPerBlock;
+  const int row_hi = min(n, row_lo + kRowsPerBlock);
+  const int nr = row_hi - row_lo;
+  double2* V = smem;                              // [nr][n2]
+  __shared__ double rc[64], rsx[64], rsy[64];
+  __shared__ int order_s[128];
+  __shared__ double lam_s[128];
+  for (int idx = threadIdx.x; idx < nr * n2; idx += blockDim.x) {
+    const int r = idx / n2, c = idx % n2;
+    V[idx] = make_double2((row_lo + r == c) ? 1.0 : 0.0, 0.0);
+  }
+  const int steps = d.nsteps[t];
+  const double* log = d.rot_log + t * (long long)d.max_steps * h * 3;
+  __syncthreads();
+  for (int st = 0; st < steps; ++st) {
+    const int s = st % (n2 - 1);
+    if (threadIdx.x < h) {
+      const double* e = log + ((long long)st * h + threadIdx.x) * 3;
+      rc[threadIdx.x] = e[0]; rsx[threadIdx.x] = e[1]; rsy[threadIdx.x] = e[2];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nr * h; idx += blockDim.x) {
+      const int r = idx / h, P = idx % h;
+      const double c = rc[P];
+      const double2 sv = make_double2(rsx[P], rsy[P]);
+      if (c == 1.0 && sv.x == 0.0 && sv.y == 0.0) continue;
+      int p, q;
+      pair_of(n2, s, P, &p, &q);
+      const double2 vp = V[r * n2 + p], vq = V[r * n2 + q];
+      V[r * n2 + p] = csub(cscale(vp, c), cmul(cconj(sv), vq));
+      V[r * n2 + q] = cadd(cmul(sv, vp), cscale(vq, c));
+    }
+    __syncthreads();
+  }
+  for (int a = threadIdx.x; a < n; a += blockDim.x) {
+    order_s[a] = d.order[t * n + a];
+    lam_s[a] = d.lam_sorted[t * n + a];
+  }
+  __syncthreads();
+  const int k = d.kept[t];
+  const double sc = d.scale_abs[t];
+  if (d.out_c128)
+    write_factors<double2>(d, t, row_lo, row_hi, V, n2, order_s, lam_s, k, sc);
+  else
+    write_factors<float2>(d, t, row_lo, row_hi, V, n2, order_s, lam_s, k, sc);
+}
+
+hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st) {
+  if (batch <= 0) return hipSuccess;
+  if (d.n < 1 || d.n > 128 || d.new_pad < 1) return hipErrorInvalidValue;
+  const int n2 = d.n + (d.n & 1);
+  const size_t gbytes = (size_t)n2 * (n2 + 1) / 2 * sizeof(double2);
+  if (n2 <= kVLdsMax) {
+    const size_t bytes = gbytes + (size_t)n2 * n2 * sizeof(double2);
+    hipLaunchKernelGGL(k_jacobi<true>, dim3(batch), dim3(256), bytes, st, d);
+    return hipGetLastError();
+  }
+  if (!d.rot_log || !d.order || !d.lam_sorted || !d.kept || !d.scale_abs || !d.nsteps)
+    return hipErrorInvalidValue;
+  if ((long long)d.max_steps < (long long)kMaxSweeps * (n2 - 1)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_jacobi<false>, dim3(batch), dim3(256), gbytes, st, d);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nblk = (d.n + kRowsPerBlock - 1) / kRowsPerBlock;
+  const size_t vbytes = (size_t)kRowsPerBlock * n2 * sizeof(double2);
+  hipLaunchKernelGGL(k_jacobi_vectors, dim3((unsigned)((long long)batch * nblk)), dim3(256), vbytes, st, d);
+  return hipGetLastError();
+}
+
+}  // namespace ttn

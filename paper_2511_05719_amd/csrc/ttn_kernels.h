@@ -1,0 +1,147 @@
+// Internal launch interface of the TTN engine's HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ttn {
+
+// ---------------------------------------------------------------- GEMM ----
+enum GemmKind { GEMM_C64 = 0, GEMM_C128 = 1, GEMM_GRAM_C64 = 2, GEMM_GRAM_C128 = 3 };
+
+struct GemmDesc {
+  const void* A;
+  const void* B;
+  void* C;
+  int M, N, K, Kin;   // K index l = (l / Kin, l % Kin) with strides (l1, l2)
+  int H;              // inner batch size (>= 1)
+  long long sAt, sAh, sAi, sAl1, sAl2;
+  long long sBt, sBh, sBl1, sBl2, sBj;
+  long long sCt, sCh, sCi, sCj;
+  int conjA, conjB;
+  int a_m_fast, b_n_fast;   // operand dimension that is unit-stride on load
+  int tilesN;               // filled by the launcher
+};
+
+hipError_t launch_zgemm(const GemmDesc& d, int batch, int kind, hipStream_t st);
+
+// ---------------------------------------------------------------- EIGH ----
+// Hermitian eigen-decomposition of the per-trajectory Gram matrix of one
+// bond (FP64 Jacobi), truncation, and the two factor matrices of the centre
+// move:  W_iso[a][i] = V[i][a] / s_a  and  W_abs[a][i] = conj(V[i][a]) s_a / |s_kept|
+// for the kept a (descending eigenvalue order), zero rows beyond.
+struct EighDesc {
+  const double2* G;     // [batch][n][n]
+  int n;                // matrix size (bond dimension before the move)
+  int new_pad;          // rows of the W outputs (padded bond dimension after)
+  int cap;              // at most this many kept values (chi cap)
+  double cutoff;        // keep lambda_a > cutoff * sum(lambda)
+  void* W_iso;          // [batch][new_pad][n]  (float2 or double2)
+  void* W_abs;          // [batch][new_pad][n]
+  int out_c128;         // 1: W in double2, 0: float2
+  int* rank_out;        // [batch] stride rank_stride (may be null)
+  long long rank_stride;
+  double* disc_acc;     // [batch] += discarded weight fraction
+  int* flags;           // [batch] |= 1 on non-finite / zero norm
+  int* degen_acc;       // [batch] += 1 on a cut inside a near-degenerate cluster
+  // workspace for n > 64
+  double* rot_log;      // [batch][max_steps][n/2][3]
+  int max_steps;
+  double* lam_sorted;   // [batch][n]
+  int* order;           // [batch][n]
+  int* kept;            // [batch]
+  double* scale_abs;    // [batch]
+  int* nsteps;          // [batch]
+};
+hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st);
+int eigh_max_sweeps();
+
+// ----------------------------------------------------------- LEAF OPS ----
+// One op on one or both physical legs of a bottom node, for every trajectory.
+enum LeafOpKind {
+  LOP_MATRIX = 0,     // explicit 2x2 per trajectory or broadcast (mat)
+  LOP_SRX = 1,        // exp(-i theta X / 2), theta = params[row][loc]
+  LOP_PAULI_SRX = 2,  // twirled SRX: X with p = sin^2(theta/2), draw
+  LOP_PAULI_AD = 3,   // twirled AD: I/X/Y/Z, draw
+  LOP_INIT = 4,       // prepare basis state from the known previous state
+  LOP_CNOT = 5,       // both legs: control leg `leg`, target the other
+  LOP_GATE4 = 6,      // both legs: explicit 4x4 (leg 0 = high bit)
+  LOP_MEAS = 7,       // Born measurement (centre here), draw or forced
+  LOP_KRAUS_AD = 8,   // amplitude-damping jump (centre here), draw or forced
+  LOP_KRAUS_MAT = 9,  // two explicit Kraus matrices (centre here)
+};
+
+struct LeafOp {
+  int kind;
+  int leg;           // physical leg (0 = a, 1 = b) of the qubit
+  int arg;           // INIT: target basis; MEAS: basis; PAULI: unused
+  int prev;          // INIT: previous measurement basis (-1 none)
+  int rec;           // MEAS: record index; INIT: previous record index
+  int loc;           // parameter column
+  int draw;          // RNG draw index
+  int branch;        // KRAUS: branch column
+};
+
+constexpr int kMaxLeafOps = 40;
+struct LeafBatch {
+  LeafOp ops[kMaxLeafOps];      // executed in order by every row
+  void* node_ptr[kMaxLeafOps];  // per op: base pointer of its bottom node tensor
+  int node_u[kMaxLeafOps];      // per op: padded up-leg dimension of that node
+  int n_ops;
+  int n_rows;          // trajectories in this batch
+  int c128;
+  const double* theta; long long theta_row_stride;   // [rows][n_loc] (row stride 0 = broadcast)
+  const double* gamma; long long gamma_row_stride;
+  const double* mat;   long long mat_row_stride;     // LOP_MATRIX / GATE4 / KRAUS_MAT data
+  uint8_t* records; long long rec_stride;
+  const uint8_t* forced_rec; long long forced_rec_stride;
+  int8_t* branches; long long br_stride;
+  const int8_t* forced_br; long long forced_br_stride;
+  double* logp;
+  int* flags;
+  uint64_t seed;
+  uint64_t traj_offset;
+};
+hipError_t launch_leaf_ops(const LeafBatch& b, hipStream_t st);
+
+// ------------------------------------------------------ DATA MOVEMENT ----
+// Copy a node into a larger zeroed buffer with one or two legs doubled
+// (the operator-Schmidt index k of a controlled gate rides on those legs).
+struct ExtendDesc {
+  const void* src; void* dst;
+  int d0, d1, d2;          // source dims
+  int leg_in, leg_out;     // legs doubled (leg_out = -1: none)
+  int mode;                // 0: delta-thread (block k on both legs)
+                           // 1: leg_in doubled, block k = bmat[k] applied on the
+                           //    physical leg ctrl_leg (start or end of the gate)
+  int ctrl_leg;            // mode 1: physical leg the 2x2 blocks act on
+  double bmat[2][2][2][2]; // mode 1: (k, row, col, re/im)
+  long long src_stride, dst_stride;   // per trajectory
+  int c128;
+};
+hipError_t launch_extend(const ExtendDesc& d, int batch, hipStream_t st);
+
+hipError_t launch_fill_zero(void* p, long long bytes, hipStream_t st);
+
+// product state of one node for every row: a bottom node holds |s0>|s1>
+// (s = 0 -> |0>, 1 -> |+>) with up dimension 1; an internal node is the 1x1x1
+// tensor 1.
+struct InitDesc {
+  void* ptr;
+  int bottom;
+  int basis0, basis1;
+  int c128;
+};
+hipError_t launch_init_product(const InitDesc& d, int batch, hipStream_t st);
+hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t st);
+hipError_t launch_fill_f64(double* p, double value, long long n, hipStream_t st);
+
+// logical readout: fail[t] = parity(data) ^ parity(leader(syndrome(data)))
+hipError_t launch_decode(const uint8_t* records, long long rec_stride, const int* data_rec, int n_data,
+                         const uint32_t* check_masks /*[P] bitmask over data index*/, int n_checks,
+                         const uint8_t* leader_parity /*[2^P]*/, uint8_t* fail, int batch, hipStream_t st);
+
+// uniform draws for tests
+hipError_t launch_philox_uniforms(uint64_t seed, uint64_t traj_offset, int n_draws, double* out, int batch,
+                                  hipStream_t st);
+
+}  // namespace ttn

@@ -1,0 +1,402 @@
+// Bottom-node kernels: single-qubit gates and channels, CNOTs between
+// sibling leaves, Born measurements and Kraus jumps; plus the data movement
+// of the controlled-gate zip, product-state initialisation and the logical
+// readout.
+//
+// A bottom node holds two physical legs (dims 2 x 2) and its up bond U:
+// T[t][a][b][u].  One thread owns one trajectory's node and executes the
+// op list in order; probabilities and rescalings are FP64 whatever the
+// storage precision.
+#include "ttn_device.h"
+#include "ttn_kernels.h"
+
+namespace ttn {
+
+template <typename S>
+__device__ inline double2 ld(const S* p, int i) { return to_d2(p[i]); }
+
+// apply M (2x2) to physical leg `leg` of T[2][2][U]
+template <typename S>
+__device__ inline void apply2(S* T, int U, int leg, const double2 m[2][2]) {
+  for (int o = 0; o < 2; ++o)
+    for (int u = 0; u < U; ++u) {
+      const int i0 = (leg == 0 ? (0 * 2 + o) : (o * 2 + 0)) * U + u;
+      const int i1 = (leg == 0 ? (1 * 2 + o) : (o * 2 + 1)) * U + u;
+      const double2 v0 = ld(T, i0), v1 = ld(T, i1);
+      T[i0] = from_d2<S>(cadd(cmul(m[0][0], v0), cmul(m[0][1], v1)));
+      T[i1] = from_d2<S>(cadd(cmul(m[1][0], v0), cmul(m[1][1], v1)));
+    }
+}
+
+// squared norms of the two halves of leg `leg`, in basis Z (xb = 0) or X (xb = 1)
+template <typename S>
+__device__ inline void half_norms(const S* T, int U, int leg, int xb, double* n0, double* n1) {
+  double a = 0.0, b = 0.0;
+  const double r = 0.70710678118654752440;
+  for (int o = 0; o < 2; ++o)
+    for (int u = 0; u < U; ++u) {
+      const int i0 = (leg == 0 ? (0 * 2 + o) : (o * 2 + 0)) * U + u;
+      const int i1 = (leg == 0 ? (1 * 2 + o) : (o * 2 + 1)) * U + u;
+      double2 v0 = ld(T, i0), v1 = ld(T, i1);
+      if (xb) {
+        const double2 w0 = cscale(cadd(v0, v1), r), w1 = cscale(csub(v0, v1), r);
+        v0 = w0; v1 = w1;
+      }
+      a += cabs2(v0);
+      b += cabs2(v1);
+    }
+  *n0 = a;
+  *n1 = b;
+}
+
+__device__ inline void set_m(double2 m[2][2], double a, double b, double c, double d) {
+  m[0][0] = make_double2(a, 0); m[0][1] = make_double2(b, 0);
+  m[1][0] = make_double2(c, 0); m[1][1] = make_double2(d, 0);
+}
+__device__ inline void matmul2(double2 r[2][2], const double2 a[2][2], const double2 b[2][2]) {
+  double2 t[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) t[i][j] = cadd(cmul(a[i][0], b[0][j]), cmul(a[i][1], b[1][j]));
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) r[i][j] = t[i][j];
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_leaf_ops(LeafBatch b) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= b.n_rows) return;
+  const double r2 = 0.70710678118654752440;
+  const uint64_t traj = b.traj_offset + (uint64_t)row;
+  for (int k = 0; k < b.n_ops; ++k) {
+    const LeafOp op = b.ops[k];
+    const int U = b.node_u[k];
+    S* T = (S*)b.node_ptr[k] + (long long)row * 4 * U;
+    double2 m[2][2];
+    switch (op.kind) {
+      case LOP_MATRIX: {
+        const double* p = b.mat + (long long)row * b.mat_row_stride + (long long)op.loc * 8;
+        for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < 2; ++j) m[i][j] = make_double2(p[(i * 2 + j) * 2], p[(i * 2 + j) * 2 + 1]);
+        apply2(T, U, op.leg, m);
+        break;
+      }
+      case LOP_SRX: {
+        const double th = b.theta[(long long)row * b.theta_row_stride + op.loc];
+        const double c = cos(0.5 * th), s = sin(0.5 * th);
+        m[0][0] = make_double2(c, 0); m[0][1] = make_double2(0, -s);
+        m[1][0] = make_double2(0, -s); m[1][1] = make_double2(c, 0);
+        apply2(T, U, op.leg, m);
+        break;
+      }
+      case LOP_PAULI_SRX:
+      case LOP_PAULI_AD: {
+        double pI, pX, pY;
+        if (op.kind == LOP_PAULI_SRX) {
+          const double th = b.theta[(long long)row * b.theta_row_stride + op.loc];
+          const double c = cos(0.5 * th), s = sin(0.5 * th);
+          pI = c * c; pX = s * s; pY = 0.0;
+        } else {
+          const double g = b.gamma[(long long)row * b.gamma_row_stride + op.loc];
+          const double sq = sqrt(1.0 - g);
+          pI = 0.25 * (1.0 + sq) * (1.0 + sq); pX = 0.25 * g; pY = 0.25 * g;
+        }
+        const double u = philox_uniform(b.seed, traj, (uint64_t)op.draw);
+        int which = 3;
+        if (u < pI) which = 0;
+        else if (u < pI + pX) which = 1;
+        else if (u < pI + pX + pY) which = 2;
+        if (which == 0) break;
+        if (which == 1) set_m(m, 0, 1, 1, 0);
+        else if (which == 3) set_m(m, 1, 0, 0, -1);
+        else { m[0][0] = make_double2(0, 0); m[0][1] = make_double2(0, -1);
+               m[1][0] = make_double2(0, 1); m[1][1] = make_double2(0, 0); }
+        apply2(T, U, op.leg, m);
+        break;
+      }
+      case LOP_INIT: {
+        double2 prep[2][2], undo[2][2];
+        set_m(undo, 1, 0, 0, 1);
+        const int mbit = (op.prev >= 0) ? (int)b.records[(long long)row * b.rec_stride + op.rec] : 0;
+        if (op.prev == 0 && mbit) set_m(undo, 0, 1, 1, 0);          // |1> -> |0>
+        if (op.prev == 1 && mbit) set_m(undo, 1, 0, 0, -1);         // |-> -> |+>
+        const bool had_x = (op.prev == 1);
+        // from |0> (prev none / Z) or |+> (prev X) to the requested basis state
+        if ((op.arg == 1) != had_x) set_m(prep, r2, r2, r2, -r2);
+        else set_m(prep, 1, 0, 0, 1);
+        matmul2(m, prep, undo);
+        apply2(T, U, op.leg, m);
+        break;
+      }
+      case LOP_CNOT: {
+        // control on leg `leg`, target on the other physical leg
+        for (int u = 0; u < U; ++u) {
+          const int i0 = (op.leg == 0 ? (1 * 2 + 0) : (0 * 2 + 1)) * U + u;
+          const int i1 = (1 * 2 + 1) * U + u;
+          const S a = T[i0];
+          T[i0] = T[i1];
+          T[i1] = a;
+        }
+        break;
+      }
+      case LOP_GATE4: {
+        const double* p = b.mat + (long long)row * b.mat_row_stride + (long long)op.loc * 32;
+        for (int u = 0; u < U; ++u) {
+          double2 v[4], w[4];
+          for (int i = 0; i < 4; ++i) v[i] = ld(T, i * U + u);
+          for (int i = 0; i < 4; ++i) {
+            w[i] = make_double2(0, 0);
+            for (int j = 0; j < 4; ++j)
+              w[i] = cadd(w[i], cmul(make_double2(p[(i * 4 + j) * 2], p[(i * 4 + j) * 2 + 1]), v[j]));
+          }
+          for (int i = 0; i < 4; ++i) T[i * U + u] = from_d2<S>(w[i]);
+        }
+        break;
+      }
+      case LOP_MEAS: {
+        double n0, n1;
+        half_norms(T, U, op.leg, op.arg, &n0, &n1);
+        const double tot = n0 + n1;
+        if (!(tot > 0.0) || !isfinite(tot)) { b.flags[row] |= 1; break; }
+        double p0 = n0 / tot;
+        p0 = p0 < 0.0 ? 0.0 : (p0 > 1.0 ? 1.0 : p0);
+        int mres;
+        if (b.forced_rec) mres = b.forced_rec[(long long)row * b.forced_rec_stride + op.rec] ? 1 : 0;
+        else mres = (philox_uniform(b.seed, traj, (uint64_t)op.draw) >= p0) ? 1 : 0;
+        const double p = mres ? 1.0 - p0 : p0;
+        if (p < 1e-300) { b.flags[row] |= 2; b.logp[row] = -INFINITY; }
+        else b.logp[row] += log(p);
+        const double sc = (p > 0.0) ? 1.0 / sqrt(p * tot) : 0.0;
+        // projector onto the outcome, rescaled to unit norm
+        if (op.arg == 0) {
+          if (mres == 0) set_m(m, sc, 0, 0, 0); else set_m(m, 0, 0, 0, sc);
+        } else {
+          const double hs = 0.5 * sc;
+          if (mres == 0) set_m(m, hs, hs, hs, hs); else set_m(m, hs, -hs, -hs, hs);
+        }
+        apply2(T, U, op.leg, m);
+        if (b.records) b.records[(long long)row * b.rec_stride + op.rec] = (uint8_t)mres;
+        break;
+      }
+      case LOP_KRAUS_AD:
+      case LOP_KRAUS_MAT: {
+        double2 K0[2][2], K1[2][2];
+        if (op.kind == LOP_KRAUS_AD) {
+          const double g = b.gamma[(long long)row * b.gamma_row_stride + op.loc];
+          set_m(K0, 1, 0, 0, sqrt(1.0 - g));
+          set_m(K1, 0, sqrt(g), 0, 0);
+        } else {
+          const double* p = b.mat + (long long)row * b.mat_row_stride + (long long)op.loc * 16;
+          for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+              K0[i][j] = make_double2(p[(i * 2 + j) * 2], p[(i * 2 + j) * 2 + 1]);
+              K1[i][j] = make_double2(p[8 + (i * 2 + j) * 2], p[8 + (i * 2 + j) * 2 + 1]);
+            }
+        }
+        // p1 = |K1 v|^2 / |v|^2
+        double tot = 0.0, j1 = 0.0;
+        for (int o = 0; o < 2; ++o)
+          for (int u = 0; u < U; ++u) {
+            const int i0 = (op.leg == 0 ? (0 * 2 + o) : (o * 2 + 0)) * U + u;
+            const int i1 = (op.leg == 0 ? (1 * 2 + o) : (o * 2 + 1)) * U + u;
+            const double2 v0 = ld(T, i0), v1 = ld(T, i1);
+            tot += cabs2(v0) + cabs2(v1);
+            j1 += cabs2(cadd(cmul(K1[0][0], v0), cmul(K1[0][1], v1))) +
+                  cabs2(cadd(cmul(K1[1][0], v0), cmul(K1[1][1], v1)));
+          }
+        if (!(tot > 0.0) || !isfinite(tot)) { b.flags[row] |= 1; break; }
+        double p1 = j1 / tot;
+        p1 = p1 < 0.0 ? 0.0 : (p1 > 1.0 ? 1.0 : p1);
+        int jump;
+        if (b.forced_br) jump = b.forced_br[(long long)row * b.forced_br_stride + op.branch] ? 1 : 0;
+        else jump = (philox_uniform(b.seed, traj, (uint64_t)op.draw) < p1) ? 1 : 0;
+        const double p = jump ? p1 : 1.0 - p1;
+        if (p < 1e-300) { b.flags[row] |= 2; b.logp[row] = -INFINITY; }
+        else b.logp[row] += log(p);
+        const double sc = (p > 0.0) ? 1.0 / sqrt(p * tot) : 0.0;
+        for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < 2; ++j) m[i][j] = cscale(jump ? K1[i][j] : K0[i][j], sc);
+        apply2(T, U, op.leg, m);
+        if (b.branches) b.branches[(long long)row * b.br_stride + op.branch] = (int8_t)jump;
+        break;
+      }
+      default:
+        b.flags[row] |= 4;
+    }
+  }
+}
+
+hipError_t launch_leaf_ops(const LeafBatch& b, hipStream_t st) {
+  if (b.n_rows <= 0 || b.n_ops <= 0) return hipSuccess;
+  dim3 grid((b.n_rows + 255) / 256);
+  if (b.c128) hipLaunchKernelGGL(k_leaf_ops<double2>, grid, dim3(256), 0, st, b);
+  else hipLaunchKernelGGL(k_leaf_ops<float2>, grid, dim3(256), 0, st, b);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ void __launch_bounds__(256) k_extend(ExtendDesc d, long long total) {
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  int D[3] = {d.d0, d.d1, d.d2};
+  int E[3] = {d.d0, d.d1, d.d2};
+  E[d.leg_in] *= 2;
+  if (d.leg_out >= 0) E[d.leg_out] *= 2;
+  const long long per = (long long)E[0] * E[1] * E[2];
+  const long long t = gid / per;
+  const long long rr = gid % per;
+  long long r = rr;
+  int idx[3];
+  idx[2] = (int)(r % E[2]); r /= E[2];
+  idx[1] = (int)(r % E[1]);
+  idx[0] = (int)(r / E[1]);
+  const S* src = (const S*)d.src + t * d.src_stride;
+  S* dst = (S*)d.dst + t * d.dst_stride;
+  double2 v = make_double2(0.0, 0.0);
+  if (d.mode == 0) {
+    const int kin = idx[d.leg_in] / D[d.leg_in];
+    const int kout = idx[d.leg_out] / D[d.leg_out];
+    if (kin == kout) {
+      int j[3] = {idx[0], idx[1], idx[2]};
+      j[d.leg_in] %= D[d.leg_in];
+      j[d.leg_out] %= D[d.leg_out];
+      v = to_d2(src[((long long)j[0] * D[1] + j[1]) * D[2] + j[2]]);
+    }
+  } else {
+    // doubled leg_in = (k, u); block k = bmat[k] applied on physical leg ctrl_leg
+    // (the projector at the start of a controlled gate, or B_k at its end)
+    const int k = idx[d.leg_in] / D[d.leg_in];
+    int j[3] = {idx[0], idx[1], idx[2]};
+    j[d.leg_in] %= D[d.leg_in];
+    const int row = j[d.ctrl_leg];
+    for (int c = 0; c < 2; ++c) {
+      int jj[3] = {j[0], j[1], j[2]};
+      jj[d.ctrl_leg] = c;
+      const double2 bm = make_double2(d.bmat[k][row][c][0], d.bmat[k][row][c][1]);
+      v = cadd(v, cmul(bm, to_d2(src[((long long)jj[0] * D[1] + jj[1]) * D[2] + jj[2]])));
+    }
+  }
+  dst[rr] = from_d2<S>(v);
+}
+
+hipError_t launch_extend(const ExtendDesc& d, int batch, hipStream_t st) {
+  int E[3] = {d.d0, d.d1, d.d2};
+  E[d.leg_in] *= 2;
+  if (d.leg_out >= 0) E[d.leg_out] *= 2;
+  const long long total = (long long)batch * E[0] * E[1] * E[2];
+  if (total <= 0) return hipSuccess;
+  dim3 grid((unsigned)((total + 255) / 256));
+  if (d.c128) hipLaunchKernelGGL(k_extend<double2>, grid, dim3(256), 0, st, d, total);
+  else hipLaunchKernelGGL(k_extend<float2>, grid, dim3(256), 0, st, d, total);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_zero(uint4* p, long long n16) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n16) p[i] = make_uint4(0, 0, 0, 0);
+}
+
+hipError_t launch_fill_zero(void* p, long long bytes, hipStream_t st) {
+  if (bytes <= 0) return hipSuccess;
+  if (bytes % 16) return hipErrorInvalidValue;
+  const long long n16 = bytes / 16;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n16 + 255) / 256)), dim3(256), 0, st, (uint4*)p, n16);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ void k_init_product(InitDesc d, int batch) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= batch) return;
+  if (!d.bottom) {
+    ((S*)d.ptr)[t] = from_d2<S>(make_double2(1.0, 0.0));
+    return;
+  }
+  S* T = (S*)d.ptr + (long long)t * 4;
+  const double r = 0.70710678118654752440;
+  const double a0 = d.basis0 ? r : 1.0, a1 = d.basis0 ? r : 0.0;
+  const double b0 = d.basis1 ? r : 1.0, b1 = d.basis1 ? r : 0.0;
+  T[0] = from_d2<S>(make_double2(a0 * b0, 0.0));
+  T[1] = from_d2<S>(make_double2(a0 * b1, 0.0));
+  T[2] = from_d2<S>(make_double2(a1 * b0, 0.0));
+  T[3] = from_d2<S>(make_double2(a1 * b1, 0.0));
+}
+
+hipError_t launch_init_product(const InitDesc& d, int batch, hipStream_t st) {
+  if (batch <= 0) return hipSuccess;
+  dim3 grid((batch + 255) / 256);
+  if (d.c128) hipLaunchKernelGGL(k_init_product<double2>, grid, dim3(256), 0, st, d, batch);
+  else hipLaunchKernelGGL(k_init_product<float2>, grid, dim3(256), 0, st, d, batch);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_i32(int* p, int v, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_f64(double* p, double v, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, value, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f64(double* p, double value, long long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, value, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_decode(const uint8_t* records, long long rec_stride, const int* data_rec, int n_data,
+                         const uint32_t* check_masks, int n_checks, const uint8_t* leader_parity,
+                         uint8_t* fail, int batch) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= batch) return;
+  const uint8_t* r = records + (long long)t * rec_stride;
+  // check_masks: n_checks x 2 words (data index < 64)
+  uint64_t bits = 0;
+  int par = 0;
+  for (int k = 0; k < n_data; ++k) {
+    const int v = r[data_rec[k]] & 1;
+    bits |= (uint64_t)v << k;
+    par ^= v;
+  }
+  uint32_t syn = 0;
+  for (int p = 0; p < n_checks; ++p) {
+    const uint64_t m = (uint64_t)check_masks[2 * p] | ((uint64_t)check_masks[2 * p + 1] << 32);
+    syn |= (uint32_t)(__popcll(bits & m) & 1) << p;
+  }
+  fail[t] = (uint8_t)(par ^ leader_parity[syn]);
+}
+
+hipError_t launch_decode(const uint8_t* records, long long rec_stride, const int* data_rec, int n_data,
+                         const uint32_t* check_masks, int n_checks, const uint8_t* leader_parity,
+                         uint8_t* fail, int batch, hipStream_t st) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_decode, dim3((batch + 255) / 256), dim3(256), 0, st, records, rec_stride, data_rec,
+                     n_data, check_masks, n_checks, leader_parity, fail, batch);
+  return hipGetLastError();
+}
+
+__global__ void k_philox(uint64_t seed, uint64_t off, int n_draws, double* out, int batch) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)batch * n_draws) return;
+  const long long t = i / n_draws;
+  const int k = (int)(i % n_draws);
+  out[i] = philox_uniform(seed, off + (uint64_t)t, (uint64_t)k);
+}
+
+hipError_t launch_philox_uniforms(uint64_t seed, uint64_t traj_offset, int n_draws, double* out, int batch,
+                                  hipStream_t st) {
+  const long long total = (long long)batch * n_draws;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_philox, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, seed, traj_offset,
+                     n_draws, out, batch);
+  return hipGetLastError();
+}
+
+}  // namespace ttn

@@ -1,0 +1,1178 @@
+// Host runtime of the TTN trajectory engine: tree metadata, tensor pool,
+// isometry-centre moves, the controlled-gate zip, the op-list runner and the
+// C ABI declared in include/ttn.h.
+//
+// Layout.  The tree is heap-numbered: node 1 is the root, node i has
+// children 2i (leg a) and 2i+1 (leg b) and parent i/2 (leg u); nodes
+// L/2 .. L-1 are bottom nodes whose legs a, b are the physical legs of leaves
+// 2(i - L/2) and 2(i - L/2) + 1.  The root keeps an up leg of dimension 1
+// (instead of being absorbed into a child, Fig. 7), so every node is 3-leg.
+// All B rows of a node live in one buffer, row-major [B][a][b][u]; the leg
+// dimensions are padded to values known on the host (the per-row Schmidt
+// ranks are <= the padding and the padding is zero), so every launch has a
+// static shape and no device-to-host read-back is needed.
+//
+// Pool.  A node's buffer must hold its largest shape: two legs doubled while
+// a controlled gate's index rides on them.  Nodes with equal capacity share
+// a size class with two spare buffers; a contraction writes into a spare of
+// the node's class and the old buffer becomes the spare.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <string>
+#include <vector>
+
+#include "ttn.h"
+#include "ttn_device.h"
+#include "ttn_kernels.h"
+
+using namespace ttn;
+
+namespace {
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int cls = -1;
+  bool used = false;
+};
+
+inline int ilog2(int x) { int r = 0; while ((1 << r) < x) ++r; return r; }
+
+}  // namespace
+
+struct ttn_oplist {
+  ttn_ctx* ctx = nullptr;
+  std::vector<int32_t> ops;
+  int n_ops = 0, n_loc = 0, n_rec = 0, n_draws = 0, n_ad = 0;
+};
+
+struct ttn_ctx {
+  // configuration
+  int N = 0, L = 0, B = 0, c128 = 0, chi = 1;
+  double cutoff = 0.0;
+  uint64_t seed = 0;
+  hipStream_t st = nullptr;
+  size_t es = 8;
+  std::vector<int> leaf_of_qubit, qubit_at_leaf, nq_below;
+  // state
+  std::vector<std::array<int, 3>> dims;
+  std::vector<int> node_buf, node_cls;
+  std::vector<size_t> cls_elems;
+  std::vector<Buf> bufs;
+  int centre = 1;
+  int nmax = 2;        // largest bond dimension a Gram can have
+  // workspaces
+  double2* G = nullptr;
+  void* Wi = nullptr;
+  void* Wa = nullptr;
+  double* rot_log = nullptr;
+  int max_steps = 0;
+  double* lam_sorted = nullptr;
+  int* order = nullptr;
+  int* kept = nullptr;
+  double* scale_abs = nullptr;
+  int* nsteps = nullptr;
+  int* rank_table = nullptr;   // [B][L] bond above node e
+  double* disc_acc = nullptr;  // [B]
+  int* flags = nullptr;        // [B]
+  int* degen_acc = nullptr;    // [B]
+  uint8_t* leader = nullptr;   // decoder table (device)
+  size_t leader_bytes = 0;
+  int* dec_datarec = nullptr;
+  uint32_t* dec_masks = nullptr;
+  // pending bottom-node ops
+  std::vector<LeafOp> pend_ops;
+  std::vector<int> pend_node;
+  LeafBatch run{};             // run-level pointers of the pending ops
+  // stats
+  int64_t hops = 0, launches = 0;
+  double gemm_flops = 0.0, gram_flops = 0.0;
+  std::string err;
+};
+
+#define TTN_CHECK_HIP(expr)                                                        \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);                \
+      return TTN_EDEVICE;                                                          \
+    }                                                                              \
+  } while (0)
+
+#define TTN_TRY(expr)                 \
+  do {                                \
+    ttn_status s_ = (expr);           \
+    if (s_ != TTN_OK) return s_;      \
+  } while (0)
+
+static ttn_status fail(ttn_ctx* ctx, ttn_status code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+// ------------------------------------------------------------- tree info ----
+static inline bool is_bottom(const ttn_ctx* c, int node) { return node >= c->L / 2; }
+static inline int bottom_of(const ttn_ctx* c, int q, int* leg) {
+  const int l = c->leaf_of_qubit[q];
+  *leg = l & 1;
+  return c->L / 2 + l / 2;
+}
+static inline int leg_toward(int x, int y) {
+  if (y == x / 2) return 2;
+  if (y == 2 * x) return 0;
+  return 1;   // y == 2x + 1
+}
+static inline int bond_node(int x, int y) { return (y == x / 2) ? x : y; }
+// Schmidt-rank bound of the bond above node e (qubits on either side)
+static inline long long phys_bound(const ttn_ctx* c, int e) {
+  const int a = c->nq_below[e], b = c->N - a;
+  const int m = std::min(a, b);
+  return m >= 40 ? (1ll << 40) : (1ll << m);
+}
+static inline int bond_cap(const ttn_ctx* c, int e) {
+  return (int)std::min<long long>((long long)c->chi, phys_bound(c, e));
+}
+static inline long long elems(const std::array<int, 3>& d) { return (long long)d[0] * d[1] * d[2]; }
+
+static std::vector<int> tree_path(int a, int b) {
+  std::vector<int> pa{a}, pb{b};
+  while (pa.back() != pb.back()) {
+    if (pa.back() > pb.back()) pa.push_back(pa.back() / 2);
+    else pb.push_back(pb.back() / 2);
+  }
+  for (int i = (int)pb.size() - 2; i >= 0; --i) pa.push_back(pb[i]);
+  return pa;
+}
+
+// ---------------------------------------------------------------- pool ----
+static int acquire(ttn_ctx* c, int cls) {
+  for (size_t i = 0; i < c->bufs.size(); ++i)
+    if (c->bufs[i].cls == cls && !c->bufs[i].used) {
+      c->bufs[i].used = true;
+      return (int)i;
+    }
+  return -1;
+}
+static void adopt(ttn_ctx* c, int node, int buf) {
+  c->bufs[c->node_buf[node]].used = false;
+  c->node_buf[node] = buf;
+}
+static inline void* node_ptr(ttn_ctx* c, int node) { return c->bufs[c->node_buf[node]].p; }
+
+// -------------------------------------------------------- contractions ----
+// Largest element offset a GEMM operand can touch (host-side bounds check:
+// no launch is made whose indexing could leave its buffer).
+static long long extent(long long batch, long long sT, int H, long long sH, int M, long long sM, int K, int Kin,
+                        long long s1, long long s2) {
+  const long long kq = (K - 1) / Kin, kr = (K >= Kin) ? Kin - 1 : K - 1;
+  return (batch - 1) * sT + (long long)(H - 1) * sH + (long long)(M - 1) * sM + kq * s1 + kr * s2 + 1;
+}
+static bool gemm_fits(const GemmDesc& g, int batch, long long capA, long long capB, long long capC) {
+  if (g.M < 1 || g.N < 1 || g.K < 1 || g.H < 1 || g.Kin < 1) return false;
+  const long long eA = extent(batch, g.sAt, g.H, g.sAh, g.M, g.sAi, g.K, g.Kin, g.sAl1, g.sAl2);
+  const long long eB = extent(batch, g.sBt, g.H, g.sBh, g.N, g.sBj, g.K, g.Kin, g.sBl1, g.sBl2);
+  const long long eC = (long long)(batch - 1) * g.sCt + (long long)(g.H - 1) * g.sCh +
+                       (long long)(g.M - 1) * g.sCi + (long long)(g.N - 1) * g.sCj + 1;
+  return eA <= capA && eB <= capB && eC <= capC;
+}
+
+// T'[.., a, ..] = sum_i W[a][i] T[.., i, ..] on leg `leg`, W: [rows][newd][n]
+static GemmDesc leg_desc(const void* T, std::array<int, 3> d, int leg, const void* W, int newd, void* out) {
+  const int n = d[leg];
+  GemmDesc g{};
+  g.H = 1;
+  const long long sT = elems(d);
+  std::array<int, 3> e = d;
+  e[leg] = newd;
+  const long long sO = elems(e);
+  if (leg == 0) {
+    const long long R = (long long)d[1] * d[2];
+    g.A = W; g.sAt = (long long)newd * n; g.sAi = n; g.sAl2 = 1; g.a_m_fast = 0;
+    g.B = T; g.sBt = sT; g.sBl2 = R; g.sBj = 1; g.b_n_fast = 1;
+    g.C = out; g.sCt = sO; g.sCi = R; g.sCj = 1;
+    g.M = newd; g.N = (int)R; g.K = n;
+  } else if (leg == 2) {
+    const long long R = (long long)d[0] * d[1];
+    g.A = T; g.sAt = sT; g.sAi = n; g.sAl2 = 1; g.a_m_fast = 0;
+    g.B = W; g.sBt = (long long)newd * n; g.sBl2 = 1; g.sBj = n; g.b_n_fast = 0;
+    g.C = out; g.sCt = sO; g.sCi = newd; g.sCj = 1;
+    g.M = (int)R; g.N = newd; g.K = n;
+  } else {
+    g.H = d[0];
+    g.A = W; g.sAt = (long long)newd * n; g.sAh = 0; g.sAi = n; g.sAl2 = 1; g.a_m_fast = 0;
+    g.B = T; g.sBt = sT; g.sBh = (long long)n * d[2]; g.sBl2 = d[2]; g.sBj = 1; g.b_n_fast = 1;
+    g.C = out; g.sCt = sO; g.sCh = (long long)newd * d[2]; g.sCi = d[2]; g.sCj = 1;
+    g.M = newd; g.N = d[2]; g.K = n;
+  }
+  g.Kin = g.K;
+  return g;
+}
+
+// G[t][i][j] = sum_rest conj(T[..i..]) T[..j..] on leg `leg` (FP64 result)
+static GemmDesc gram_desc(const void* T, std::array<int, 3> d, int leg, double2* G) {
+  const int n = d[leg];
+  GemmDesc g{};
+  g.H = 1;
+  const long long sT = elems(d);
+  g.conjA = 1;
+  g.A = T; g.B = T; g.sAt = sT; g.sBt = sT;
+  g.C = G; g.sCt = (long long)n * n; g.sCi = n; g.sCj = 1;
+  g.M = n; g.N = n;
+  if (leg == 0) {
+    const long long R = (long long)d[1] * d[2];
+    g.sAi = R; g.sAl2 = 1; g.a_m_fast = 0;
+    g.sBl2 = 1; g.sBj = R; g.b_n_fast = 0;
+    g.K = (int)R; g.Kin = g.K;
+  } else if (leg == 2) {
+    const long long R = (long long)d[0] * d[1];
+    g.sAi = 1; g.sAl2 = n; g.a_m_fast = 1;
+    g.sBl2 = n; g.sBj = 1; g.b_n_fast = 1;
+    g.K = (int)R; g.Kin = g.K;
+  } else {
+    g.sAi = d[2]; g.sAl1 = (long long)n * d[2]; g.sAl2 = 1; g.a_m_fast = 0;
+    g.sBl1 = (long long)n * d[2]; g.sBl2 = 1; g.sBj = d[2]; g.b_n_fast = 0;
+    g.K = d[0] * d[2]; g.Kin = d[2];
+  }
+  return g;
+}
+
+static long long buf_elems(const ttn_ctx* ctx, int b) { return (long long)(ctx->bufs[b].bytes / ctx->es); }
+static long long ws_elems(const ttn_ctx* ctx) { return (long long)ctx->B * ctx->nmax * ctx->nmax; }
+
+static ttn_status leg_apply(ttn_ctx* ctx, int src_buf, std::array<int, 3> d, int leg, const void* W, int newd,
+                            int dst_buf) {
+  GemmDesc g = leg_desc(ctx->bufs[src_buf].p, d, leg, W, newd, ctx->bufs[dst_buf].p);
+  const bool wA = (leg != 2);
+  if (!gemm_fits(g, ctx->B, wA ? ws_elems(ctx) : buf_elems(ctx, src_buf), wA ? buf_elems(ctx, src_buf) : ws_elems(ctx),
+                 buf_elems(ctx, dst_buf)))
+    return fail(ctx, TTN_EINVAL, "internal: contraction exceeds its buffers");
+  ctx->gemm_flops += 8.0 * (double)g.M * g.N * g.K * g.H * ctx->B;
+  ++ctx->launches;
+  TTN_CHECK_HIP(launch_zgemm(g, ctx->B, ctx->c128 ? GEMM_C128 : GEMM_C64, ctx->st));
+  return TTN_OK;
+}
+
+static ttn_status gram(ttn_ctx* ctx, int src_buf, std::array<int, 3> d, int leg) {
+  GemmDesc g = gram_desc(ctx->bufs[src_buf].p, d, leg, ctx->G);
+  if (!gemm_fits(g, ctx->B, buf_elems(ctx, src_buf), buf_elems(ctx, src_buf), ws_elems(ctx)))
+    return fail(ctx, TTN_EINVAL, "internal: Gram exceeds its buffers");
+  ctx->gram_flops += 8.0 * (double)g.M * g.N * g.K * ctx->B;
+  ++ctx->launches;
+  TTN_CHECK_HIP(launch_zgemm(g, ctx->B, ctx->c128 ? GEMM_GRAM_C128 : GEMM_GRAM_C64, ctx->st));
+  return TTN_OK;
+}
+
+// Move the isometry centre from x to its neighbour y (Sec. III.B: the
+// canonical form that makes local Schmidt values and Born probabilities
+// local): factor x = (x V S^-1)(S V^H) across the bond, keep the first factor
+// in x, absorb the second into y, truncating to `cap` values above `cutoff`.
+static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int new_pad) {
+  const int lx = leg_toward(x, y), ly = leg_toward(y, x);
+  const int e = bond_node(x, y);
+  std::array<int, 3> dx = ctx->dims[x], dy = ctx->dims[y];
+  const int n = dx[lx];
+  if (n != dy[ly]) return fail(ctx, TTN_EINVAL, "internal: bond dimension mismatch");
+  if (n > ctx->nmax || new_pad > ctx->nmax)
+    return fail(ctx, TTN_EINVAL, "internal: bond dimension exceeds workspace");
+  TTN_TRY(gram(ctx, ctx->node_buf[x], dx, lx));
+  EighDesc ed{};
+  ed.G = ctx->G; ed.n = n; ed.new_pad = new_pad; ed.cap = cap; ed.cutoff = cutoff;
+  ed.W_iso = ctx->Wi; ed.W_abs = ctx->Wa; ed.out_c128 = ctx->c128;
+  ed.rank_out = ctx->rank_table + e; ed.rank_stride = ctx->L;
+  ed.disc_acc = ctx->disc_acc; ed.flags = ctx->flags; ed.degen_acc = ctx->degen_acc;
+  ed.rot_log = ctx->rot_log; ed.max_steps = ctx->max_steps; ed.lam_sorted = ctx->lam_sorted;
+  ed.order = ctx->order; ed.kept = ctx->kept; ed.scale_abs = ctx->scale_abs; ed.nsteps = ctx->nsteps;
+  ctx->launches += (n + (n & 1)) > 64 ? 2 : 1;
+  TTN_CHECK_HIP(launch_eigh(ed, ctx->B, ctx->st));
+  const int bx = acquire(ctx, ctx->node_cls[x]);
+  if (bx < 0) return fail(ctx, TTN_EINVAL, "internal: pool exhausted");
+  TTN_TRY(leg_apply(ctx, ctx->node_buf[x], dx, lx, ctx->Wi, new_pad, bx));
+  adopt(ctx, x, bx);
+  const int by = acquire(ctx, ctx->node_cls[y]);
+  if (by < 0) return fail(ctx, TTN_EINVAL, "internal: pool exhausted");
+  TTN_TRY(leg_apply(ctx, ctx->node_buf[y], dy, ly, ctx->Wa, new_pad, by));
+  adopt(ctx, y, by);
+  ctx->dims[x][lx] = new_pad;
+  ctx->dims[y][ly] = new_pad;
+  ctx->centre = y;
+  ++ctx->hops;
+  return TTN_OK;
+}
+
+static ttn_status hop_truncating(ttn_ctx* ctx, int x, int y) {
+  const int e = bond_node(x, y);
+  const int n = ctx->dims[x][leg_toward(x, y)];
+  const int cap = bond_cap(ctx, e);
+  return hop(ctx, x, y, ctx->cutoff, cap, std::min(n, cap));
+}
+
+static ttn_status flush_leaf(ttn_ctx* ctx);
+
+static ttn_status move_centre(ttn_ctx* ctx, int target) {
+  if (ctx->centre == target) return TTN_OK;
+  TTN_TRY(flush_leaf(ctx));
+  std::vector<int> p = tree_path(ctx->centre, target);
+  for (size_t i = 0; i + 1 < p.size(); ++i) TTN_TRY(hop_truncating(ctx, p[i], p[i + 1]));
+  return TTN_OK;
+}
+
+// --------------------------------------------------------- bottom ops ----
+static ttn_status flush_leaf(ttn_ctx* ctx) {
+  size_t i = 0;
+  while (i < ctx->pend_ops.size()) {
+    LeafBatch b = ctx->run;
+    b.n_ops = 0;
+    for (; i < ctx->pend_ops.size() && b.n_ops < kMaxLeafOps; ++i) {
+      const int node = ctx->pend_node[i];
+      if (!is_bottom(ctx, node) || ctx->dims[node][0] != 2 || ctx->dims[node][1] != 2 ||
+          4ll * ctx->dims[node][2] * ctx->B > buf_elems(ctx, ctx->node_buf[node]))
+        return fail(ctx, TTN_EINVAL, "internal: bottom-node op on a malformed node");
+      b.ops[b.n_ops] = ctx->pend_ops[i];
+      b.node_ptr[b.n_ops] = node_ptr(ctx, node);
+      b.node_u[b.n_ops] = ctx->dims[node][2];
+      ++b.n_ops;
+    }
+    b.n_rows = ctx->B;
+    b.c128 = ctx->c128;
+    b.flags = ctx->flags;
+    b.seed = ctx->seed;
+    ++ctx->launches;
+    TTN_CHECK_HIP(launch_leaf_ops(b, ctx->st));
+  }
+  ctx->pend_ops.clear();
+  ctx->pend_node.clear();
+  return TTN_OK;
+}
+
+static void push_leaf(ttn_ctx* ctx, int node, const LeafOp& op) {
+  ctx->pend_ops.push_back(op);
+  ctx->pend_node.push_back(node);
+}
+
+static LeafOp leaf_op(int kind, int leg) {
+  LeafOp o{};
+  o.kind = kind; o.leg = leg; o.prev = -1; o.rec = -1; o.loc = 0; o.draw = 0; o.branch = 0; o.arg = 0;
+  return o;
+}
+
+// ----------------------------------------------------- controlled gate ----
+// g = sum_k P_k (x) B_k with P_k = |v_k><v_k| orthogonal projectors on the
+// `start` qubit.  The start node gets its up bond doubled into (k, u) with
+// block k = P_k applied; the index k then rides along the tree path
+// (delta-copied on both path legs of every node it passes) while the centre
+// moves one node at a time toward the other end, where block k receives B_k.
+// Because the P_k project onto orthogonal subspaces of a qubit on the near
+// side, every Gram matrix on the way is that of the exact state, so only
+// numerically zero values are dropped.  A sweep back to the start then
+// truncates every path bond with the context's rule (Sec. IV.A).
+static ttn_status controlled_gate(ttn_ctx* ctx, int qs, const double P[2][2][2][2], int qe,
+                                  const double Bm[2][2][2][2]) {
+  int ls, le;
+  const int ns = bottom_of(ctx, qs, &ls), ne = bottom_of(ctx, qe, &le);
+  TTN_TRY(move_centre(ctx, ns));
+  TTN_TRY(flush_leaf(ctx));
+  const std::vector<int> path = tree_path(ns, ne);
+  const int m = (int)path.size() - 1;
+  // split at the start
+  {
+    ExtendDesc x{};
+    const std::array<int, 3> d = ctx->dims[ns];
+    x.src = node_ptr(ctx, ns);
+    x.d0 = d[0]; x.d1 = d[1]; x.d2 = d[2];
+    x.leg_in = 2; x.leg_out = -1; x.mode = 1; x.ctrl_leg = ls;
+    std::memcpy(x.bmat, P, sizeof(x.bmat));
+    x.src_stride = elems(d);
+    x.dst_stride = elems(d) * 2;
+    x.c128 = ctx->c128;
+    const int b = acquire(ctx, ctx->node_cls[ns]);
+    if (b < 0) return fail(ctx, TTN_EINVAL, "internal: pool exhausted");
+    if (elems(d) * 2 * ctx->B > buf_elems(ctx, b)) return fail(ctx, TTN_EINVAL, "internal: split exceeds buffer");
+    x.dst = ctx->bufs[b].p;
+    ++ctx->launches;
+    TTN_CHECK_HIP(launch_extend(x, ctx->B, ctx->st));
+    adopt(ctx, ns, b);
+    ctx->dims[ns][2] *= 2;
+  }
+  for (int i = 0; i < m; ++i) {
+    const int x = path[i], y = path[i + 1];
+    const int ly = leg_toward(y, x);
+    ExtendDesc ex{};
+    const std::array<int, 3> d = ctx->dims[y];
+    ex.src = node_ptr(ctx, y);
+    ex.d0 = d[0]; ex.d1 = d[1]; ex.d2 = d[2];
+    ex.c128 = ctx->c128;
+    ex.src_stride = elems(d);
+    std::array<int, 3> e = d;
+    if (y == ne) {
+      ex.mode = 1; ex.leg_in = 2; ex.leg_out = -1; ex.ctrl_leg = le;
+      std::memcpy(ex.bmat, Bm, sizeof(ex.bmat));
+      e[2] *= 2;
+    } else {
+      const int lo = leg_toward(y, path[i + 2]);
+      ex.mode = 0; ex.leg_in = ly; ex.leg_out = lo;
+      e[ly] *= 2;
+      e[lo] *= 2;
+    }
+    ex.dst_stride = elems(e);
+    const int b = acquire(ctx, ctx->node_cls[y]);
+    if (b < 0) return fail(ctx, TTN_EINVAL, "internal: pool exhausted");
+    if (elems(e) * ctx->B > buf_elems(ctx, b)) return fail(ctx, TTN_EINVAL, "internal: extension exceeds buffer");
+    ex.dst = ctx->bufs[b].p;
+    ++ctx->launches;
+    TTN_CHECK_HIP(launch_extend(ex, ctx->B, ctx->st));
+    adopt(ctx, y, b);
+    ctx->dims[y] = e;
+    // exact move across (x, y): the bond can hold the near side's full space
+    const int n = ctx->dims[x][leg_toward(x, y)];
+    const int qnear = (y == x / 2) ? ctx->nq_below[x] : ctx->N - ctx->nq_below[y];
+    const long long near_dim = qnear >= 30 ? (1ll << 30) : (1ll << qnear);
+    const int pad = (int)std::min<long long>(n, near_dim);
+    TTN_TRY(hop(ctx, x, y, ctx->cutoff, pad, pad));
+  }
+  for (int i = m; i > 0; --i) TTN_TRY(hop_truncating(ctx, path[i], path[i - 1]));
+  return TTN_OK;
+}
+
+static void proj(double P[2][2][2][2], int basis) {
+  std::memset(P, 0, sizeof(double) * 16);
+  if (basis == 0) {            // |0><0|, |1><1|
+    P[0][0][0][0] = 1.0;
+    P[1][1][1][0] = 1.0;
+  } else {                     // |+><+|, |-><-|
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) {
+        P[0][i][j][0] = 0.5;
+        P[1][i][j][0] = (i == j) ? 0.5 : -0.5;
+      }
+  }
+}
+
+static ttn_status cnot(ttn_ctx* ctx, int c, int t) {
+  int lc, lt;
+  const int nc = bottom_of(ctx, c, &lc), nt = bottom_of(ctx, t, &lt);
+  if (nc == nt) {
+    push_leaf(ctx, nc, leaf_op(LOP_CNOT, lc));
+    return TTN_OK;
+  }
+  // CNOT = |0><0| (x) I + |1><1| (x) X  =  I (x) |+><+| + Z (x) |-><-|:
+  // start the zip at whichever end is nearer the current centre
+  const int dc = (int)tree_path(ctx->centre, nc).size();
+  const int dt = (int)tree_path(ctx->centre, nt).size();
+  double P[2][2][2][2], Bm[2][2][2][2];
+  std::memset(Bm, 0, sizeof(Bm));
+  if (dc <= dt) {
+    proj(P, 0);
+    Bm[0][0][0][0] = 1; Bm[0][1][1][0] = 1;        // I
+    Bm[1][0][1][0] = 1; Bm[1][1][0][0] = 1;        // X
+    return controlled_gate(ctx, c, P, t, Bm);
+  }
+  proj(P, 1);
+  Bm[0][0][0][0] = 1; Bm[0][1][1][0] = 1;          // I
+  Bm[1][0][0][0] = 1; Bm[1][1][1][0] = -1;         // Z
+  return controlled_gate(ctx, t, P, c, Bm);
+}
+
+// ----------------------------------------------------------- run setup ----
+static ttn_status reset_state(ttn_ctx* ctx, const uint8_t* basis) {
+  TTN_TRY(flush_leaf(ctx));
+  for (int node = 1; node < ctx->L; ++node) {
+    ctx->dims[node] = is_bottom(ctx, node) ? std::array<int, 3>{2, 2, 1} : std::array<int, 3>{1, 1, 1};
+    InitDesc d{};
+    d.ptr = node_ptr(ctx, node);
+    d.bottom = is_bottom(ctx, node);
+    d.c128 = ctx->c128;
+    if (d.bottom) {
+      const int l0 = 2 * (node - ctx->L / 2);
+      const int q0 = ctx->qubit_at_leaf[l0], q1 = ctx->qubit_at_leaf[l0 + 1];
+      d.basis0 = (basis && q0 >= 0) ? basis[q0] : 0;
+      d.basis1 = (basis && q1 >= 0) ? basis[q1] : 0;
+    }
+    ++ctx->launches;
+    TTN_CHECK_HIP(launch_init_product(d, ctx->B, ctx->st));
+  }
+  ctx->centre = 1;
+  TTN_CHECK_HIP(launch_fill_i32(ctx->rank_table, 1, (long long)ctx->B * ctx->L, ctx->st));
+  TTN_CHECK_HIP(launch_fill_i32(ctx->flags, 0, ctx->B, ctx->st));
+  TTN_CHECK_HIP(launch_fill_i32(ctx->degen_acc, 0, ctx->B, ctx->st));
+  TTN_CHECK_HIP(launch_fill_f64(ctx->disc_acc, 0.0, ctx->B, ctx->st));
+  ctx->launches += 5;
+  return TTN_OK;
+}
+
+static ttn_status fill_stats(ttn_ctx* ctx, ttn_stats* st) {
+  if (!st) return TTN_OK;
+  TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
+  std::vector<int> ranks((size_t)ctx->B * ctx->L), flags(ctx->B), degen(ctx->B);
+  std::vector<double> disc(ctx->B);
+  TTN_CHECK_HIP(hipMemcpy(ranks.data(), ctx->rank_table, ranks.size() * 4, hipMemcpyDeviceToHost));
+  TTN_CHECK_HIP(hipMemcpy(flags.data(), ctx->flags, flags.size() * 4, hipMemcpyDeviceToHost));
+  TTN_CHECK_HIP(hipMemcpy(degen.data(), ctx->degen_acc, degen.size() * 4, hipMemcpyDeviceToHost));
+  TTN_CHECK_HIP(hipMemcpy(disc.data(), ctx->disc_acc, disc.size() * 8, hipMemcpyDeviceToHost));
+  st->max_rank = 1;
+  for (int t = 0; t < ctx->B; ++t)
+    for (int e = 2; e < ctx->L; ++e) st->max_rank = std::max(st->max_rank, ranks[(size_t)t * ctx->L + e]);
+  st->discarded_weight = 0.0;
+  st->degenerate_cuts = 0;
+  st->flagged_rows = 0;
+  for (int t = 0; t < ctx->B; ++t) {
+    st->discarded_weight += disc[t];
+    st->degenerate_cuts += degen[t];
+    st->flagged_rows += flags[t] != 0;
+  }
+  st->hops = ctx->hops;
+  st->launches = ctx->launches;
+  st->gemm_flops = ctx->gemm_flops;
+  st->gram_flops = ctx->gram_flops;
+  return TTN_OK;
+}
+
+static ttn_status run_oplist(ttn_ctx* ctx, const ttn_oplist* ol, const double* theta, const double* gamma,
+                             int64_t pstride, uint64_t traj_offset, uint8_t* records, int8_t* branches,
+                             double* logp, const uint8_t* forced_rec, const int8_t* forced_br, ttn_stats* st) {
+  if (!ol || ol->ctx != ctx) return fail(ctx, TTN_EINVAL, "op list belongs to another context");
+  if (!records || !logp) return fail(ctx, TTN_EINVAL, "records and logp are required");
+  if (ol->n_ad > 0 && !branches && !forced_br) return fail(ctx, TTN_EINVAL, "branches required (AD ops)");
+  ctx->hops = 0; ctx->launches = 0; ctx->gemm_flops = 0.0; ctx->gram_flops = 0.0;
+  TTN_TRY(reset_state(ctx, nullptr));
+  TTN_CHECK_HIP(launch_fill_f64(logp, 0.0, ctx->B, ctx->st));
+  LeafBatch& r = ctx->run;
+  r = LeafBatch{};
+  r.theta = theta; r.theta_row_stride = pstride;
+  r.gamma = gamma; r.gamma_row_stride = pstride;
+  r.records = records; r.rec_stride = ol->n_rec;
+  r.forced_rec = forced_rec; r.forced_rec_stride = ol->n_rec;
+  r.branches = branches; r.br_stride = ol->n_ad;
+  r.forced_br = forced_br; r.forced_br_stride = ol->n_ad;
+  r.logp = logp;
+  r.traj_offset = traj_offset;
+  int ad_col = 0;
+  for (int k = 0; k < ol->n_ops; ++k) {
+    const int32_t* o = &ol->ops[(size_t)k * 9];
+    const int op = o[0], q0 = o[1], q1 = o[2], arg = o[3], loc = o[4], draw = o[5], rec = o[6], prev = o[7];
+    int leg;
+    const int node = bottom_of(ctx, q0, &leg);
+    switch (op) {
+      case TTN_OP_INIT: {
+        LeafOp l = leaf_op(LOP_INIT, leg);
+        l.arg = arg; l.prev = prev; l.rec = rec;
+        push_leaf(ctx, node, l);
+        break;
+      }
+      case TTN_OP_CNOT:
+        TTN_TRY(cnot(ctx, q0, q1));
+        break;
+      case TTN_OP_SRX: {
+        LeafOp l = leaf_op(LOP_SRX, leg);
+        l.loc = loc;
+        push_leaf(ctx, node, l);
+        break;
+      }
+      case TTN_OP_PAULI: {
+        LeafOp l = leaf_op(arg == 0 ? LOP_PAULI_SRX : LOP_PAULI_AD, leg);
+        l.loc = loc; l.draw = draw;
+        push_leaf(ctx, node, l);
+        break;
+      }
+      case TTN_OP_AD: {
+        TTN_TRY(move_centre(ctx, node));
+        LeafOp l = leaf_op(LOP_KRAUS_AD, leg);
+        l.loc = loc; l.draw = draw; l.branch = ad_col++;
+        push_leaf(ctx, node, l);
+        break;
+      }
+      case TTN_OP_MEAS: {
+        TTN_TRY(move_centre(ctx, node));
+        LeafOp l = leaf_op(LOP_MEAS, leg);
+        l.arg = arg; l.rec = rec; l.draw = draw;
+        push_leaf(ctx, node, l);
+        break;
+      }
+      default:
+        return fail(ctx, TTN_EINVAL, "unknown op code");
+    }
+  }
+  TTN_TRY(flush_leaf(ctx));
+  ctx->run = LeafBatch{};
+  if (st) TTN_TRY(fill_stats(ctx, st));
+  return TTN_OK;
+}
+
+// ================================================================ C ABI ====
+extern "C" {
+
+const char* ttn_version(void) { return "ttn-mi355x 0.1 (gfx950)"; }
+
+double ttn_philox_uniform_host(uint64_t seed, uint64_t traj, uint64_t draw) {
+  return philox_uniform(seed, traj, draw);
+}
+
+const char* ttn_last_error(const ttn_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {
+  if (!cfg || !out) return TTN_EINVAL;
+  *out = nullptr;
+  if (cfg->n_qubits < 1 || !cfg->leaf_of_qubit || cfg->chi_max < 1 || cfg->batch < 1 ||
+      !(cfg->cutoff >= 0.0) || (cfg->dtype != TTN_C64 && cfg->dtype != TTN_C128))
+    return TTN_EINVAL;
+  ttn_ctx* ctx = new ttn_ctx();
+  ctx->N = cfg->n_qubits;
+  int L = 2;
+  while (L < ctx->N) L *= 2;
+  ctx->L = L;
+  ctx->B = cfg->batch;
+  ctx->c128 = cfg->dtype == TTN_C128;
+  ctx->es = ctx->c128 ? 16 : 8;
+  ctx->chi = cfg->chi_max;
+  ctx->cutoff = cfg->cutoff;
+  ctx->seed = cfg->seed;
+  ctx->st = (hipStream_t)cfg->stream;
+  ctx->leaf_of_qubit.assign(cfg->leaf_of_qubit, cfg->leaf_of_qubit + ctx->N);
+  ctx->qubit_at_leaf.assign(L, -1);
+  for (int q = 0; q < ctx->N; ++q) {
+    const int l = ctx->leaf_of_qubit[q];
+    if (l < 0 || l >= L || ctx->qubit_at_leaf[l] >= 0) {
+      delete ctx;
+      return TTN_EINVAL;
+    }
+    ctx->qubit_at_leaf[l] = q;
+  }
+  ctx->nq_below.assign(L, 0);
+  for (int node = L - 1; node >= 1; --node) {
+    if (node >= L / 2) {
+      const int l0 = 2 * (node - L / 2);
+      ctx->nq_below[node] = (ctx->qubit_at_leaf[l0] >= 0) + (ctx->qubit_at_leaf[l0 + 1] >= 0);
+    } else {
+      ctx->nq_below[node] = ctx->nq_below[2 * node] + ctx->nq_below[2 * node + 1];
+    }
+  }
+  // largest Gram: a doubled bond during a controlled gate
+  int nmax = 2;
+  for (int e = 2; e < L; ++e) nmax = std::max(nmax, 2 * bond_cap(ctx, e));
+  ctx->nmax = nmax;
+  if (nmax > 128) {
+    delete ctx;
+    return TTN_EINVAL;   // the FP64 Jacobi workspace holds bonds up to 128 (chi_max <= 64)
+  }
+  // node capacities and size classes
+  std::vector<size_t> cap_el(L, 0);
+  for (int node = 1; node < L; ++node) {
+    const long long cu = node == 1 ? 1 : bond_cap(ctx, node);
+    if (node >= L / 2) cap_el[node] = (size_t)(2 * 2 * 2 * cu);
+    else cap_el[node] = (size_t)(4ll * bond_cap(ctx, 2 * node) * bond_cap(ctx, 2 * node + 1) * cu);
+  }
+  ctx->node_cls.assign(L, -1);
+  ctx->node_buf.assign(L, -1);
+  ctx->dims.assign(L, {1, 1, 1});
+  for (int node = 1; node < L; ++node) {
+    int cls = -1;
+    for (size_t c = 0; c < ctx->cls_elems.size(); ++c)
+      if (ctx->cls_elems[c] == cap_el[node]) cls = (int)c;
+    if (cls < 0) {
+      cls = (int)ctx->cls_elems.size();
+      ctx->cls_elems.push_back(cap_el[node]);
+    }
+    ctx->node_cls[node] = cls;
+  }
+  auto bail = [&](ttn_status s) {
+    ttn_destroy(ctx);
+    return s;
+  };
+  for (size_t c = 0; c < ctx->cls_elems.size(); ++c) {
+    int count = 2;
+    for (int node = 1; node < L; ++node) count += ctx->node_cls[node] == (int)c;
+    for (int i = 0; i < count; ++i) {
+      Buf b;
+      b.cls = (int)c;
+      b.bytes = ctx->cls_elems[c] * ctx->es * (size_t)ctx->B;
+      b.bytes = (b.bytes + 255) & ~(size_t)255;
+      if (hipMalloc(&b.p, b.bytes) != hipSuccess) return bail(TTN_ENOMEM);
+      ctx->bufs.push_back(b);
+    }
+  }
+  for (int node = 1; node < L; ++node) {
+    const int b = acquire(ctx, ctx->node_cls[node]);
+    ctx->node_buf[node] = b;
+  }
+  const size_t Bz = (size_t)ctx->B;
+  const int n2 = nmax;
+  ctx->max_steps = eigh_max_sweeps() * (n2 - 1);
+  bool ok = true;
+  ok &= hipMalloc((void**)&ctx->G, Bz * n2 * n2 * sizeof(double2)) == hipSuccess;
+  ok &= hipMalloc(&ctx->Wi, Bz * n2 * n2 * ctx->es) == hipSuccess;
+  ok &= hipMalloc(&ctx->Wa, Bz * n2 * n2 * ctx->es) == hipSuccess;
+  if (n2 > 64) ok &= hipMalloc((void**)&ctx->rot_log, Bz * ctx->max_steps * (n2 / 2) * 3 * sizeof(double)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->lam_sorted, Bz * n2 * sizeof(double)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->order, Bz * n2 * sizeof(int)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->kept, Bz * sizeof(int)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->scale_abs, Bz * sizeof(double)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->nsteps, Bz * sizeof(int)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->rank_table, Bz * L * sizeof(int)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->disc_acc, Bz * sizeof(double)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->flags, Bz * sizeof(int)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->degen_acc, Bz * sizeof(int)) == hipSuccess;
+  if (!ok) return bail(TTN_ENOMEM);
+  if (reset_state(ctx, nullptr) != TTN_OK) return bail(TTN_EDEVICE);
+  if (hipStreamSynchronize(ctx->st) != hipSuccess) return bail(TTN_EDEVICE);
+  *out = ctx;
+  return TTN_OK;
+}
+
+ttn_status ttn_destroy(ttn_ctx* ctx) {
+  if (!ctx) return TTN_EINVAL;
+  hipStreamSynchronize(ctx->st);
+  for (auto& b : ctx->bufs) hipFree(b.p);
+  void* ws[] = {ctx->G, ctx->Wi, ctx->Wa, ctx->rot_log, ctx->lam_sorted, ctx->order, ctx->kept,
+                ctx->scale_abs, ctx->nsteps, ctx->rank_table, ctx->disc_acc, ctx->flags,
+                ctx->degen_acc, ctx->leader, ctx->dec_datarec, ctx->dec_masks};
+  for (void* p : ws)
+    if (p) hipFree(p);
+  delete ctx;
+  return TTN_OK;
+}
+
+ttn_status ttn_init_product(ttn_ctx* ctx, const uint8_t* basis) {
+  if (!ctx) return TTN_EINVAL;
+  if (basis)
+    for (int q = 0; q < ctx->N; ++q)
+      if (basis[q] > 1) return fail(ctx, TTN_EINVAL, "basis must be 0 or 1");
+  return reset_state(ctx, basis);
+}
+
+ttn_status ttn_apply_1q(ttn_ctx* ctx, int32_t q, const double* u, int64_t row_stride) {
+  if (!ctx) return TTN_EINVAL;
+  if (q < 0 || q >= ctx->N || !u || row_stride < 0) return fail(ctx, TTN_EINVAL, "bad qubit or matrix");
+  int leg;
+  const int node = bottom_of(ctx, q, &leg);
+  TTN_TRY(flush_leaf(ctx));
+  ctx->run = LeafBatch{};
+  ctx->run.mat = u;
+  ctx->run.mat_row_stride = row_stride;
+  LeafOp l = leaf_op(LOP_MATRIX, leg);
+  push_leaf(ctx, node, l);
+  ttn_status s = flush_leaf(ctx);
+  ctx->run = LeafBatch{};
+  return s;
+}
+
+ttn_status ttn_apply_2q(ttn_ctx* ctx, int32_t q0, int32_t q1, const double* g) {
+  if (!ctx) return TTN_EINVAL;
+  if (q0 < 0 || q1 < 0 || q0 >= ctx->N || q1 >= ctx->N || q0 == q1 || !g)
+    return fail(ctx, TTN_EINVAL, "bad qubits or gate");
+  for (int i = 0; i < 32; ++i)
+    if (!std::isfinite(g[i])) return fail(ctx, TTN_EINVAL, "non-finite gate");
+  int l0, l1;
+  const int n0 = bottom_of(ctx, q0, &l0), n1 = bottom_of(ctx, q1, &l1);
+  auto G = [&](int r, int c, int ri) { return g[(r * 4 + c) * 2 + ri]; };
+  if (n0 == n1) {
+    // reorder to (leg a, leg b) bit order
+    static thread_local double m[32];
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 4; ++c) {
+        int rr = r, cc = c;
+        if (l0 == 1) {   // q0 on leg b: swap bits
+          rr = ((r & 1) << 1) | (r >> 1);
+          cc = ((c & 1) << 1) | (c >> 1);
+        }
+        m[(rr * 4 + cc) * 2] = G(r, c, 0);
+        m[(rr * 4 + cc) * 2 + 1] = G(r, c, 1);
+      }
+    double* dm = nullptr;
+    TTN_CHECK_HIP(hipMalloc((void**)&dm, sizeof(m)));
+    TTN_CHECK_HIP(hipMemcpy(dm, m, sizeof(m), hipMemcpyHostToDevice));
+    TTN_TRY(flush_leaf(ctx));
+    ctx->run = LeafBatch{};
+    ctx->run.mat = dm;
+    ctx->run.mat_row_stride = 0;
+    push_leaf(ctx, n0, leaf_op(LOP_GATE4, 0));
+    ttn_status s = flush_leaf(ctx);
+    ctx->run = LeafBatch{};
+    hipStreamSynchronize(ctx->st);
+    hipFree(dm);
+    return s;
+  }
+  // controlled on q0 (block diagonal in q0's index) or on q1
+  auto off0 = [&]() {
+    double s = 0;
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 4; ++c)
+        if ((r >> 1) != (c >> 1)) s += std::fabs(G(r, c, 0)) + std::fabs(G(r, c, 1));
+    return s;
+  };
+  auto off1 = [&]() {
+    double s = 0;
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 4; ++c)
+        if ((r & 1) != (c & 1)) s += std::fabs(G(r, c, 0)) + std::fabs(G(r, c, 1));
+    return s;
+  };
+  double P[2][2][2][2], Bm[2][2][2][2];
+  proj(P, 0);
+  if (off0() == 0.0) {
+    for (int k = 0; k < 2; ++k)
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+          for (int z = 0; z < 2; ++z) Bm[k][i][j][z] = G(k * 2 + i, k * 2 + j, z);
+    return controlled_gate(ctx, q0, P, q1, Bm);
+  }
+  if (off1() == 0.0) {
+    for (int k = 0; k < 2; ++k)
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+          for (int z = 0; z < 2; ++z) Bm[k][i][j][z] = G(i * 2 + k, j * 2 + k, z);
+    return controlled_gate(ctx, q1, P, q0, Bm);
+  }
+  return fail(ctx, TTN_EINVAL, "non-sibling gate must be controlled on one of its qubits");
+}
+
+ttn_status ttn_measure_project(ttn_ctx* ctx, int32_t q, int32_t basis, const uint8_t* forced, uint8_t* bits,
+                               double* logp, uint64_t traj_offset, int32_t draw) {
+  if (!ctx) return TTN_EINVAL;
+  if (q < 0 || q >= ctx->N || (basis != 0 && basis != 1) || !bits || !logp || draw < 0)
+    return fail(ctx, TTN_EINVAL, "bad measurement arguments");
+  int leg;
+  const int node = bottom_of(ctx, q, &leg);
+  TTN_TRY(move_centre(ctx, node));
+  TTN_TRY(flush_leaf(ctx));
+  ctx->run = LeafBatch{};
+  ctx->run.records = bits; ctx->run.rec_stride = 1;
+  ctx->run.forced_rec = forced; ctx->run.forced_rec_stride = 1;
+  ctx->run.logp = logp;
+  ctx->run.traj_offset = traj_offset;
+  LeafOp l = leaf_op(LOP_MEAS, leg);
+  l.arg = basis; l.rec = 0; l.draw = draw;
+  push_leaf(ctx, node, l);
+  ttn_status s = flush_leaf(ctx);
+  ctx->run = LeafBatch{};
+  return s;
+}
+
+ttn_status ttn_kraus_jump(ttn_ctx* ctx, int32_t q, const double* k, int64_t row_stride, const int8_t* forced,
+                          int8_t* branch, double* logp, uint64_t traj_offset, int32_t draw) {
+  if (!ctx) return TTN_EINVAL;
+  if (q < 0 || q >= ctx->N || !k || !branch || !logp || row_stride < 0 || draw < 0)
+    return fail(ctx, TTN_EINVAL, "bad Kraus arguments");
+  int leg;
+  const int node = bottom_of(ctx, q, &leg);
+  TTN_TRY(move_centre(ctx, node));
+  TTN_TRY(flush_leaf(ctx));
+  ctx->run = LeafBatch{};
+  ctx->run.mat = k; ctx->run.mat_row_stride = row_stride;
+  ctx->run.branches = branch; ctx->run.br_stride = 1;
+  ctx->run.forced_br = forced; ctx->run.forced_br_stride = 1;
+  ctx->run.logp = logp;
+  ctx->run.traj_offset = traj_offset;
+  LeafOp l = leaf_op(LOP_KRAUS_MAT, leg);
+  l.loc = 0; l.draw = draw; l.branch = 0;
+  push_leaf(ctx, node, l);
+  ttn_status s = flush_leaf(ctx);
+  ctx->run = LeafBatch{};
+  return s;
+}
+
+ttn_status ttn_oplist_upload(ttn_ctx* ctx, const int32_t* ops, int32_t n_ops, int32_t n_loc, int32_t n_rec,
+                             int32_t n_draws, ttn_oplist** out) {
+  if (!ctx) return TTN_EINVAL;
+  if (!ops || n_ops < 0 || n_loc < 0 || n_rec < 0 || n_draws < 0 || !out)
+    return fail(ctx, TTN_EINVAL, "bad op list");
+  ttn_oplist* ol = new ttn_oplist();
+  ol->ctx = ctx;
+  ol->ops.assign(ops, ops + (size_t)n_ops * 9);
+  ol->n_ops = n_ops; ol->n_loc = n_loc; ol->n_rec = n_rec; ol->n_draws = n_draws;
+  for (int k = 0; k < n_ops; ++k) {
+    const int32_t* o = &ops[(size_t)k * 9];
+    const int op = o[0], q0 = o[1], q1 = o[2];
+    bool bad = q0 < 0 || q0 >= ctx->N || op < 0 || op > 5;
+    if (op == TTN_OP_CNOT) bad |= q1 < 0 || q1 >= ctx->N || q1 == q0;
+    if (op == TTN_OP_SRX || op == TTN_OP_AD || op == TTN_OP_PAULI) bad |= o[4] < 0 || o[4] >= n_loc;
+    if (op == TTN_OP_AD || op == TTN_OP_PAULI || op == TTN_OP_MEAS) bad |= o[5] < 0 || o[5] >= n_draws;
+    if (op == TTN_OP_MEAS) bad |= o[6] < 0 || o[6] >= n_rec || (o[3] != 0 && o[3] != 1);
+    if (op == TTN_OP_INIT) bad |= (o[3] != 0 && o[3] != 1) || o[7] < -1 || o[7] > 1 || (o[7] >= 0 && (o[6] < 0 || o[6] >= n_rec));
+    if (op == TTN_OP_PAULI) bad |= (o[3] != 0 && o[3] != 1);
+    if (bad) {
+      delete ol;
+      return fail(ctx, TTN_EINVAL, "op " + std::to_string(k) + " is malformed");
+    }
+    ol->n_ad += op == TTN_OP_AD;
+  }
+  *out = ol;
+  return TTN_OK;
+}
+
+ttn_status ttn_oplist_free(ttn_oplist* ol) {
+  delete ol;
+  return TTN_OK;
+}
+
+ttn_status ttn_batch_run_circuit(ttn_ctx* ctx, const ttn_oplist* ol, const double* theta, const double* gamma,
+                                 int64_t params_stride, uint64_t traj_offset, uint8_t* records, int8_t* branches,
+                                 double* logp, ttn_stats* st) {
+  if (!ctx) return TTN_EINVAL;
+  if (params_stride < 0) return fail(ctx, TTN_EINVAL, "negative parameter stride");
+  ttn_status s = run_oplist(ctx, ol, theta, gamma, params_stride, traj_offset, records, branches, logp,
+                            nullptr, nullptr, st);
+  if (s == TTN_OK && st && st->flagged_rows > 0) return TTN_ENONFINITE;
+  return s;
+}
+
+ttn_status ttn_log_prob(ttn_ctx* ctx, const ttn_oplist* ol, const uint8_t* records, const int8_t* branches,
+                        const double* theta, const double* gamma, int64_t params_stride, double* logp,
+                        ttn_stats* st) {
+  if (!ctx) return TTN_EINVAL;
+  if (!records || params_stride < 0) return fail(ctx, TTN_EINVAL, "records required");
+  if (ol && ol->n_ad > 0 && !branches) return fail(ctx, TTN_EINVAL, "branches required (AD ops)");
+  // forced run: the record buffer is read (and rewritten with identical bits)
+  ttn_status s = run_oplist(ctx, ol, theta, gamma, params_stride, 0, const_cast<uint8_t*>(records),
+                            nullptr, logp, records, branches, st);
+  if (s == TTN_OK && st && st->flagged_rows > 0) return TTN_EPROB;
+  return s;
+}
+
+ttn_status ttn_decode(ttn_ctx* ctx, const uint8_t* records, int32_t n_rec, const int32_t* data_rec, int32_t n_data,
+                      const uint8_t* checks, int32_t n_checks, uint8_t* fail_out) {
+  if (!ctx) return TTN_EINVAL;
+  if (!records || !data_rec || !checks || !fail_out || n_data < 1 || n_data > 64 || n_checks < 0 ||
+      n_checks > 24 || n_rec < 1)
+    return fail(ctx, TTN_EINVAL, "bad decoder arguments");
+  for (int k = 0; k < n_data; ++k)
+    if (data_rec[k] < 0 || data_rec[k] >= n_rec) return fail(ctx, TTN_EINVAL, "bad data record index");
+  // syndrome of each single flip
+  std::vector<uint32_t> col(n_data, 0);
+  std::vector<uint32_t> masks(2 * (size_t)std::max(n_checks, 1), 0);
+  for (int p = 0; p < n_checks; ++p)
+    for (int k = 0; k < n_data; ++k)
+      if (checks[(size_t)p * n_data + k]) {
+        col[k] |= 1u << p;
+        if (k < 32) masks[2 * p] |= 1u << k;
+        else masks[2 * p + 1] |= 1u << (k - 32);
+      }
+  // breadth-first search over single flips: first-reached leader per syndrome
+  const size_t S = (size_t)1 << n_checks;
+  std::vector<uint8_t> par(S, 0), seen(S, 0);
+  std::deque<uint32_t> dq;
+  seen[0] = 1;
+  dq.push_back(0);
+  std::vector<std::vector<uint8_t>> pattern(1, std::vector<uint8_t>(n_data, 0));
+  std::vector<int> pat_of(S, -1);
+  pat_of[0] = 0;
+  while (!dq.empty()) {
+    const uint32_t s = dq.front();
+    dq.pop_front();
+    const std::vector<uint8_t> cur = pattern[pat_of[s]];
+    for (int k = 0; k < n_data; ++k) {
+      if (cur[k]) continue;
+      const uint32_t s2 = s ^ col[k];
+      if (seen[s2]) continue;
+      seen[s2] = 1;
+      std::vector<uint8_t> nxt = cur;
+      nxt[k] = 1;
+      par[s2] = par[s] ^ 1;
+      pat_of[s2] = (int)pattern.size();
+      pattern.push_back(nxt);
+      dq.push_back(s2);
+    }
+  }
+  if (ctx->leader_bytes < S) {
+    if (ctx->leader) hipFree(ctx->leader);
+    ctx->leader = nullptr;
+    TTN_CHECK_HIP(hipMalloc((void**)&ctx->leader, S));
+    ctx->leader_bytes = S;
+  }
+  if (!ctx->dec_datarec) TTN_CHECK_HIP(hipMalloc((void**)&ctx->dec_datarec, 64 * sizeof(int)));
+  if (!ctx->dec_masks) TTN_CHECK_HIP(hipMalloc((void**)&ctx->dec_masks, 2 * 24 * sizeof(uint32_t)));
+  TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
+  TTN_CHECK_HIP(hipMemcpy(ctx->leader, par.data(), S, hipMemcpyHostToDevice));
+  TTN_CHECK_HIP(hipMemcpy(ctx->dec_datarec, data_rec, n_data * sizeof(int), hipMemcpyHostToDevice));
+  TTN_CHECK_HIP(hipMemcpy(ctx->dec_masks, masks.data(), masks.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+  TTN_CHECK_HIP(launch_decode(records, n_rec, ctx->dec_datarec, n_data, ctx->dec_masks, n_checks, ctx->leader,
+                              fail_out, ctx->B, ctx->st));
+  return TTN_OK;
+}
+
+ttn_status ttn_compress(ttn_ctx* ctx) {
+  if (!ctx) return TTN_EINVAL;
+  TTN_TRY(flush_leaf(ctx));
+  // depth-first tour: every bond is crossed in both directions
+  std::vector<int> tour;
+  std::vector<std::pair<int, int>> stack{{1, 0}};
+  tour.push_back(1);
+  while (!stack.empty()) {
+    auto& top = stack.back();
+    const int node = top.first;
+    if (!is_bottom(ctx, node) && top.second < 2) {
+      const int child = 2 * node + top.second;
+      ++top.second;
+      stack.push_back({child, 0});
+      tour.push_back(child);
+    } else {
+      stack.pop_back();
+      if (!stack.empty()) tour.push_back(stack.back().first);
+    }
+  }
+  TTN_TRY(move_centre(ctx, 1));
+  for (size_t i = 0; i + 1 < tour.size(); ++i) TTN_TRY(hop_truncating(ctx, tour[i], tour[i + 1]));
+  return TTN_OK;
+}
+
+ttn_status ttn_to_statevector(ttn_ctx* ctx, int32_t row, double* amp) {
+  if (!ctx) return TTN_EINVAL;
+  if (row < 0 || row >= ctx->B || !amp || ctx->N > 26) return fail(ctx, TTN_EINVAL, "bad row or N > 26");
+  TTN_TRY(flush_leaf(ctx));
+  TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
+  typedef std::complex<double> cd;
+  const int L = ctx->L;
+  std::vector<std::vector<cd>> T(L);
+  for (int node = 1; node < L; ++node) {
+    const long long ne = elems(ctx->dims[node]);
+    std::vector<cd> h(ne);
+    if (ctx->c128) {
+      TTN_CHECK_HIP(hipMemcpy(h.data(), (char*)node_ptr(ctx, node) + (size_t)row * ne * 16, ne * 16,
+                              hipMemcpyDeviceToHost));
+    } else {
+      std::vector<std::complex<float>> f(ne);
+      TTN_CHECK_HIP(hipMemcpy(f.data(), (char*)node_ptr(ctx, node) + (size_t)row * ne * 8, ne * 8,
+                              hipMemcpyDeviceToHost));
+      for (long long i = 0; i < ne; ++i) h[i] = cd(f[i].real(), f[i].imag());
+    }
+    T[node] = std::move(h);
+  }
+  // bottom-up: v[node] = [2^(qubits below)][u], qubits in leaf order
+  std::vector<std::vector<cd>> v(L);
+  std::vector<std::vector<int>> qs(L);
+  for (int node = L - 1; node >= 1; --node) {
+    const auto d = ctx->dims[node];
+    if (node >= L / 2) {
+      const int l0 = 2 * (node - L / 2);
+      const int q0 = ctx->qubit_at_leaf[l0], q1 = ctx->qubit_at_leaf[l0 + 1];
+      const int na = q0 >= 0 ? 2 : 1, nb = q1 >= 0 ? 2 : 1;
+      std::vector<cd> out((size_t)na * nb * d[2]);
+      for (int a = 0; a < na; ++a)
+        for (int b = 0; b < nb; ++b)
+          for (int u = 0; u < d[2]; ++u) out[((size_t)a * nb + b) * d[2] + u] = T[node][((size_t)a * 2 + b) * d[2] + u];
+      v[node] = std::move(out);
+      if (q0 >= 0) qs[node].push_back(q0);
+      if (q1 >= 0) qs[node].push_back(q1);
+    } else {
+      const auto& va = v[2 * node];
+      const auto& vb = v[2 * node + 1];
+      const size_t ra = va.size() / d[0], rb = vb.size() / d[1];
+      std::vector<cd> tmp(ra * d[1] * d[2], cd(0, 0));   // sum_i va[x][i] T[i][j][u]
+      for (size_t x = 0; x < ra; ++x)
+        for (int i = 0; i < d[0]; ++i) {
+          const cd a = va[x * d[0] + i];
+          if (a == cd(0, 0)) continue;
+          for (int j = 0; j < d[1]; ++j)
+            for (int u = 0; u < d[2]; ++u) tmp[(x * d[1] + j) * d[2] + u] += a * T[node][((size_t)i * d[1] + j) * d[2] + u];
+        }
+      std::vector<cd> out(ra * rb * d[2], cd(0, 0));
+      for (size_t x = 0; x < ra; ++x)
+        for (size_t y = 0; y < rb; ++y)
+          for (int j = 0; j < d[1]; ++j) {
+            const cd b = vb[y * d[1] + j];
+            if (b == cd(0, 0)) continue;
+            for (int u = 0; u < d[2]; ++u) out[(x * rb + y) * d[2] + u] += b * tmp[(x * d[1] + j) * d[2] + u];
+          }
+      v[node] = std::move(out);
+      qs[node] = qs[2 * node];
+      qs[node].insert(qs[node].end(), qs[2 * node + 1].begin(), qs[2 * node + 1].end());
+      v[2 * node].clear();
+      v[2 * node + 1].clear();
+    }
+  }
+  const auto& root = v[1];
+  const std::vector<int>& order = qs[1];   // qubits in leaf order, first = most significant
+  const int N = ctx->N;
+  std::vector<double> outh((size_t)2 << N, 0.0);
+  for (size_t idx = 0; idx < ((size_t)1 << N); ++idx) {
+    // idx in leaf order -> qubit-order index
+    size_t qi = 0;
+    for (int p = 0; p < N; ++p) {
+      const int bit = (idx >> (N - 1 - p)) & 1;
+      qi |= (size_t)bit << (N - 1 - order[p]);
+    }
+    outh[2 * qi] = root[idx].real();
+    outh[2 * qi + 1] = root[idx].imag();
+  }
+  TTN_CHECK_HIP(hipMemcpy(amp, outh.data(), outh.size() * sizeof(double), hipMemcpyHostToDevice));
+  return TTN_OK;
+}
+
+ttn_status ttn_bond_dims(ttn_ctx* ctx, int32_t row, int32_t* dims) {
+  if (!ctx) return TTN_EINVAL;
+  if (row < 0 || row >= ctx->B || !dims) return fail(ctx, TTN_EINVAL, "bad row");
+  TTN_TRY(flush_leaf(ctx));
+  TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
+  std::vector<int> r(ctx->L);
+  TTN_CHECK_HIP(hipMemcpy(r.data(), ctx->rank_table + (size_t)row * ctx->L, ctx->L * sizeof(int),
+                          hipMemcpyDeviceToHost));
+  dims[0] = 0;
+  dims[1] = 1;
+  for (int e = 2; e < ctx->L; ++e) dims[e] = r[e];
+  return TTN_OK;
+}
+
+ttn_status ttn_uniforms(ttn_ctx* ctx, uint64_t traj_offset, int32_t rows, int32_t n_draws, double* out) {
+  if (!ctx) return TTN_EINVAL;
+  if (rows < 0 || n_draws < 0 || !out) return fail(ctx, TTN_EINVAL, "bad arguments");
+  TTN_CHECK_HIP(launch_philox_uniforms(ctx->seed, traj_offset, n_draws, out, rows, ctx->st));
+  TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
+  return TTN_OK;
+}
+
+ttn_status ttn_test_leg_apply(ttn_ctx* ctx, int32_t rows, const int32_t* dims3, int32_t leg, const void* T,
+                              int64_t t_elems, const void* W, int64_t w_elems, int32_t newd, void* out,
+                              int64_t out_elems) {
+  if (!ctx) return TTN_EINVAL;
+  if (rows < 1 || !dims3 || leg < 0 || leg > 2 || !T || !W || !out || newd < 1)
+    return fail(ctx, TTN_EINVAL, "bad arguments");
+  std::array<int, 3> d{dims3[0], dims3[1], dims3[2]};
+  if (d[0] < 1 || d[1] < 1 || d[2] < 1) return fail(ctx, TTN_EINVAL, "bad dims");
+  GemmDesc g = leg_desc(T, d, leg, W, newd, out);
+  const bool wA = (leg != 2);
+  if (!gemm_fits(g, rows, wA ? w_elems : t_elems, wA ? t_elems : w_elems, out_elems))
+    return fail(ctx, TTN_EINVAL, "buffers too small for the contraction");
+  TTN_CHECK_HIP(launch_zgemm(g, rows, ctx->c128 ? GEMM_C128 : GEMM_C64, ctx->st));
+  TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
+  return TTN_OK;
+}
+
+ttn_status ttn_test_gram(ttn_ctx* ctx, int32_t rows, const int32_t* dims3, int32_t leg, const void* T,
+                         int64_t t_elems, double* G, int64_t g_elems) {
+  if (!ctx) return TTN_EINVAL;
+  if (rows < 1 || !dims3 || leg < 0 || leg > 2 || !T || !G) return fail(ctx, TTN_EINVAL, "bad arguments");
+  std::array<int, 3> d{dims3[0], dims3[1], dims3[2]};
+  if (d[0] < 1 || d[1] < 1 || d[2] < 1) return fail(ctx, TTN_EINVAL, "bad dims");
+  GemmDesc g = gram_desc(T, d, leg, (double2*)G);
+  if (!gemm_fits(g, rows, t_elems, t_elems, g_elems)) return fail(ctx, TTN_EINVAL, "buffers too small for the Gram");
+  TTN_CHECK_HIP(launch_zgemm(g, rows, ctx->c128 ? GEMM_GRAM_C128 : GEMM_GRAM_C64, ctx->st));
+  TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
+  return TTN_OK;
+}
+
+ttn_status ttn_test_eigh(ttn_ctx* ctx, int32_t rows, int32_t n, int32_t new_pad, int32_t cap, double cutoff,
+                         const double* G, int64_t g_elems, void* W_iso, void* W_abs, int64_t w_elems,
+                         int32_t* rank) {
+  if (!ctx) return TTN_EINVAL;
+  if (rows < 1 || rows > ctx->B || n < 1 || n > ctx->nmax || new_pad < 1 || new_pad > ctx->nmax || cap < 1 || !G ||
+      !W_iso || !W_abs || !rank)
+    return fail(ctx, TTN_EINVAL, "bad arguments (rows <= batch, n and new_pad <= workspace)");
+  if (g_elems < (int64_t)rows * n * n || w_elems < (int64_t)rows * new_pad * n)
+    return fail(ctx, TTN_EINVAL, "buffers too small for the eigen-decomposition");
+  EighDesc ed{};
+  ed.G = (const double2*)G; ed.n = n; ed.new_pad = new_pad; ed.cap = cap; ed.cutoff = cutoff;
+  ed.W_iso = W_iso; ed.W_abs = W_abs; ed.out_c128 = ctx->c128;
+  ed.rank_out = rank; ed.rank_stride = 1;
+  ed.rot_log = ctx->rot_log; ed.max_steps = ctx->max_steps; ed.lam_sorted = ctx->lam_sorted;
+  ed.order = ctx->order; ed.kept = ctx->kept; ed.scale_abs = ctx->scale_abs; ed.nsteps = ctx->nsteps;
+  TTN_CHECK_HIP(launch_eigh(ed, rows, ctx->st));
+  TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
+  return TTN_OK;
+}
+
+}  // extern "C"

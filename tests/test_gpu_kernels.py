@@ -1,0 +1,159 @@
+"""Kernel-level parity on the GPU: the counter-based generator, the MFMA
+contraction and Gram kernels and the FP64 Jacobi centre-move factors, each
+against a direct numpy evaluation of its definition."""
+import ctypes as C
+import zlib
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _engine(dtype="c128", n_qubits=16, chi=64, batch=8):
+    from paper_2511_05719_amd import TTNEngine
+    return TTNEngine(n_qubits, batch, np.arange(n_qubits), chi_max=chi, cutoff=1e-13, dtype=dtype, seed=5)
+
+
+def _dev_complex(a, dtype):
+    t = torch.view_as_real(torch.as_tensor(a.astype(np.complex128 if dtype == "c128" else np.complex64)))
+    return t.contiguous().cuda()
+
+
+def _host_complex(t):
+    a = t.cpu().numpy()
+    return a[..., 0].astype(np.float64) + 1j * a[..., 1].astype(np.float64)
+
+
+def test_device_uniforms_match_oracle_stream():
+    from oracle.rng import uniforms
+    eng = _engine()
+    got = eng.uniforms(traj_offset=11, rows=9, n_draws=37)
+    ref = uniforms(5, np.arange(11, 20), 37)
+    assert np.array_equal(got, ref)
+    eng.close()
+
+
+SHAPES = [(2, 2, 4), (3, 5, 7), (16, 16, 64), (64, 64, 16), (1, 70, 33)]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("leg", [0, 1, 2])
+def test_leg_contraction(dtype, shape, leg):
+    from paper_2511_05719_amd._abi import lib, check
+    g = np.random.default_rng(zlib.crc32(repr((dtype, shape, leg)).encode()))
+    rows = 3
+    n = shape[leg]
+    newd = [1, 5, 64][hash(shape) % 3]
+    T = g.normal(size=(rows,) + shape) + 1j * g.normal(size=(rows,) + shape)
+    W = g.normal(size=(rows, newd, n)) + 1j * g.normal(size=(rows, newd, n))
+    eng = _engine(dtype)
+    Td, Wd = _dev_complex(T, dtype), _dev_complex(W, dtype)
+    oshape = list(shape)
+    oshape[leg] = newd
+    out = torch.zeros((rows,) + tuple(oshape) + (2,), dtype=Td.dtype, device="cuda")
+    dims = (C.c_int32 * 3)(*shape)
+    check(lib().ttn_test_leg_apply(eng._ctx, rows, dims, leg, Td.data_ptr(), T.size, Wd.data_ptr(), W.size,
+                                   newd, out.data_ptr(), out.numel() // 2), eng._ctx)
+    sub = {0: "tijk,tai->tajk", 1: "tijk,taj->tiak", 2: "tijk,tak->tija"}[leg]
+    Tr, Wr = T, W
+    if dtype == "c64":
+        Tr, Wr = T.astype(np.complex64).astype(np.complex128), W.astype(np.complex64).astype(np.complex128)
+    ref = np.einsum(sub, Tr, Wr)
+    got = _host_complex(out)
+    tol = 1e-12 if dtype == "c128" else 2e-6
+    assert np.abs(got - ref).max() <= tol * np.sqrt(n) * np.abs(ref).max()
+    eng.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("leg", [0, 1, 2])
+def test_gram_fp64(dtype, shape, leg):
+    from paper_2511_05719_amd._abi import lib, check
+    g = np.random.default_rng(7 + zlib.crc32(repr((dtype, shape, leg)).encode()))
+    rows = 2
+    n = shape[leg]
+    T = g.normal(size=(rows,) + shape) + 1j * g.normal(size=(rows,) + shape)
+    if dtype == "c64":
+        T = T.astype(np.complex64).astype(np.complex128)     # the kernel sees these exact values
+    eng = _engine(dtype)
+    Td = _dev_complex(T, dtype)
+    G = torch.zeros(rows, n, n, 2, dtype=torch.float64, device="cuda")
+    dims = (C.c_int32 * 3)(*shape)
+    check(lib().ttn_test_gram(eng._ctx, rows, dims, leg, Td.data_ptr(), T.size, G.data_ptr(), rows * n * n),
+          eng._ctx)
+    Tm = np.moveaxis(T, 1 + leg, -1).reshape(rows, -1, n)
+    ref = np.einsum("tmi,tmj->tij", Tm.conj(), Tm)
+    got = _host_complex(G)
+    # FP64 accumulation of exact products: rounding only
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    eng.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,rank", [(1, 1), (2, 2), (4, 3), (16, 16), (64, 40), (64, 64), (128, 128), (128, 77)])
+def test_eigh_centre_move_factors(dtype, n, rank):
+    from paper_2511_05719_amd._abi import lib, check
+    g = np.random.default_rng(n * 1000 + rank)
+    rows, m = 4, max(n, 8) * 3
+    M = (g.normal(size=(rows, m, rank)) + 1j * g.normal(size=(rows, m, rank))) @ \
+        (g.normal(size=(rows, rank, n)) + 1j * g.normal(size=(rows, rank, n)))
+    M *= (10.0 ** (-np.arange(n) / 12.0))[None, None, :]          # graded spectrum
+    M /= np.linalg.norm(M.reshape(rows, -1), axis=1)[:, None, None]
+    G = np.einsum("tmi,tmj->tij", M.conj(), M)
+    eng = _engine(dtype)
+    Gd = torch.view_as_real(torch.as_tensor(G)).contiguous().cuda()
+    wdt = torch.float64 if dtype == "c128" else torch.float32
+    Wi = torch.zeros(rows, n, n, 2, dtype=wdt, device="cuda")
+    Wa = torch.zeros(rows, n, n, 2, dtype=wdt, device="cuda")
+    rk = torch.zeros(rows, dtype=torch.int32, device="cuda")
+    cutoff = 1e-13
+    check(lib().ttn_test_eigh(eng._ctx, rows, n, n, n, cutoff, Gd.data_ptr(), rows * n * n, Wi.data_ptr(),
+                              Wa.data_ptr(), rows * n * n, rk.data_ptr()), eng._ctx)
+    Wi, Wa, rk = _host_complex(Wi), _host_complex(Wa), rk.cpu().numpy()
+    for t in range(rows):
+        s = np.linalg.svd(M[t], compute_uv=False)
+        k_ref = int((s ** 2 > cutoff * (s ** 2).sum()).sum())
+        assert rk[t] == k_ref
+        k = rk[t]
+        tol = 1e-11 if dtype == "c128" else 2e-5
+        # (M V S^-1)(S V^H) reconstructs M (nothing above the cutoff dropped)
+        U = M[t] @ Wi[t, :k].T
+        assert np.abs(U @ Wa[t, :k] - M[t]).max() < tol
+        # M V = U S has Gram diag(s^2): orthogonal columns weighted by s
+        sa = np.linalg.norm(Wa[t, :k], axis=1)
+        US = U * sa[None, :]
+        assert np.abs(US.conj().T @ US - np.diag(sa ** 2)).max() < tol * s[0] ** 2
+        # the kept values are the largest singular values, descending
+        assert np.abs(sa - s[:k]).max() < tol * s[0]
+        assert np.all(np.diff(sa) <= 1e-12)
+        assert np.all(Wi[t, k:] == 0) and np.all(Wa[t, k:] == 0)
+    eng.close()
+
+
+def test_eigh_truncation_cap():
+    from paper_2511_05719_amd._abi import lib, check
+    g = np.random.default_rng(3)
+    rows, n, m, cap = 2, 64, 200, 10
+    M = g.normal(size=(rows, m, n)) + 1j * g.normal(size=(rows, m, n))
+    M /= np.linalg.norm(M.reshape(rows, -1), axis=1)[:, None, None]
+    G = np.einsum("tmi,tmj->tij", M.conj(), M)
+    eng = _engine("c128")
+    Gd = torch.view_as_real(torch.as_tensor(G)).contiguous().cuda()
+    Wi = torch.zeros(rows, cap, n, 2, dtype=torch.float64, device="cuda")
+    Wa = torch.zeros(rows, cap, n, 2, dtype=torch.float64, device="cuda")
+    rk = torch.zeros(rows, dtype=torch.int32, device="cuda")
+    check(lib().ttn_test_eigh(eng._ctx, rows, n, cap, cap, 1e-10, Gd.data_ptr(), rows * n * n, Wi.data_ptr(),
+                              Wa.data_ptr(), rows * cap * n, rk.data_ptr()), eng._ctx)
+    Wi, Wa = _host_complex(Wi), _host_complex(Wa)
+    assert (rk.cpu().numpy() == cap).all()
+    for t in range(rows):
+        u, s, vh = np.linalg.svd(M[t])
+        best = (u[:, :cap] * s[:cap]) @ vh[:cap]
+        best /= np.linalg.norm(best)
+        got = (M[t] @ Wi[t].T) @ Wa[t]                        # renormalised rank-cap truncation
+        assert np.abs(got - best).max() < 1e-10
+    eng.close()
