@@ -23,14 +23,18 @@ typedef float  f4v __attribute__((ext_vector_type(4)));
 typedef double d4v __attribute__((ext_vector_type(4)));
 
 template <typename R> struct MfmaAcc;
+// Output lane layout of the 16x16x4 MFMAs on gfx950 (lane l, register r):
+// f32 holds D[4 (l / 16) + r][l % 16], f64 holds D[l / 16 + 4 r][l % 16].
 template <> struct MfmaAcc<float> {
   typedef f4v type;
+  __device__ static inline int row(int lk, int r) { return 4 * lk + r; }
   __device__ static inline f4v mma(float a, float b, f4v c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
 };
 template <> struct MfmaAcc<double> {
   typedef d4v type;
+  __device__ static inline int row(int lk, int r) { return lk + 4 * r; }
   __device__ static inline d4v mma(double a, double b, d4v c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -137,14 +141,14 @@ __global__ void __launch_bounds__(256) k_zgemm(GemmDesc d) {
     }
     __syncthreads();
   }
-  // ---- write back: lane holds C[4*(lane/16)+r][lane%16] of each 16x16 tile ----
+  // ---- write back each 16x16 tile in the MFMA's output lane layout ----
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gi = m0 + wm * 32 + a * 16 + lk * 4 + r;
+        const int gi = m0 + wm * 32 + a * 16 + MfmaAcc<R>::row(lk, r);
         const int gj = n0 + wn * 32 + b * 16 + li;
         if (gi < d.M && gj < d.N) {
           double2 v = make_double2((double)acc_re[a][b][r], (double)acc_im[a][b][r]);

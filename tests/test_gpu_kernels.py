@@ -119,10 +119,15 @@ def test_eigh_centre_move_factors(dtype, n, rank):
         k_ref = int((s ** 2 > cutoff * (s ** 2).sum()).sum())
         assert rk[t] == k_ref
         k = rk[t]
-        tol = 1e-11 if dtype == "c128" else 2e-5
-        # (M V S^-1)(S V^H) reconstructs M (nothing above the cutoff dropped)
+        # c128: components of weight near the cutoff mix across it by
+        # ~eps * |G| / gap, i.e. up to ~1e-3 sqrt(cutoff) in amplitude
+        tol = (1e-11 + 1e-3 * np.sqrt(cutoff)) if dtype == "c128" else 2e-5
+        # (M V S^-1)(S V^H) is the renormalised best rank-k approximation of M
+        u_, s_, vh_ = np.linalg.svd(M[t], full_matrices=False)
+        Mk = (u_[:, :k] * s_[:k]) @ vh_[:k]
+        Mk /= np.linalg.norm(Mk)
         U = M[t] @ Wi[t, :k].T
-        assert np.abs(U @ Wa[t, :k] - M[t]).max() < tol
+        assert np.abs(U @ Wa[t, :k] - Mk).max() < tol
         # M V = U S has Gram diag(s^2): orthogonal columns weighted by s
         sa = np.linalg.norm(Wa[t, :k], axis=1)
         US = U * sa[None, :]

@@ -12,9 +12,10 @@ from workload import build_circuit, custom_circuit, random_program  # noqa: E402
 from oracle import chp, decoder, stabrank  # noqa: E402
 from oracle import statevector as sv  # noqa: E402
 
-# c128 with the Gram route resolves squared Schmidt weights down to ~1e-15;
-# the untruncated runs drop only weights below this cutoff
-CUT_EXACT = 1e-13
+# The FP64 Gram route resolves squared Schmidt weights down to its rounding
+# floor (~1e-16 of the bond's weight for these sizes); "untruncated" runs
+# drop only weights below this cutoff, i.e. numerical zeros.
+CUT_EXACT = 1e-15
 
 
 def _engine(circ, rows, dtype="c128", chi=64, cutoff=CUT_EXACT, seed=0):
