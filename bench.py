@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Throughput of the TTN trajectory engine on one MI355X.
+
+Workload: the d=5 triangular colour code (37 qubits: 19 data + 18 ancillas),
+5 rounds of X-then-Z syndrome extraction, a systematic X over-rotation
+exp(-i theta X / 2) after every gate, initialisation and idle location with
+theta cycling over an 8-point grid in [0.02, 0.2] rad across trajectories,
+binary tree over 64 leaves (default qubit-to-leaf order), chi_max = 64,
+squared-weight cutoff 1e-10; contractions in complex64 on FP32 MFMA,
+Gram matrices / eigen-decompositions / probabilities in FP64.
+
+A step is one batched run of the whole circuit (2427 ops per trajectory:
+CNOTs, noise ops, initialisations, measurements) for `--batch` trajectories.
+The metric is trajectory-gates/s = trajectories/s x ops per trajectory; the
+same run in complex128, one trajectory at a time (the plain path), and the
+FP64 CPU oracle on a bounded sample are reported beside it.
+
+Prints one JSON line.  --gpus N > 1 is not supported (one GPU per box).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "trajectory-gates/s and shots/s at d=5 chi=64, batched cplx64 vs plain cplx128"
+PEAK = {"fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "fp64_valu": 78.6e12, "hbm": 8.0e12}
+THETAS = [0.02 + i * (0.2 - 0.02) / 7 for i in range(8)]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def theta_rows(circ, rows, offset):
+    import numpy as np
+    th = np.asarray(THETAS)[(offset + np.arange(rows)) % len(THETAS)]
+    return np.repeat(th[:, None], circ.n_loc, axis=1)
+
+
+def run_batched(args, circ):
+    import numpy as np
+    import torch
+    from paper_2511_05719_amd import TTNEngine
+    B = args.batch
+    eng = TTNEngine(circ.n_qubits, B, circ.leaf_of_qubit, chi_max=64, cutoff=1e-10, dtype="c64",
+                    seed=args.seed)
+    ol = eng.upload(circ)
+    for w in range(args.warmup):
+        eng.run_circuit(ol, theta=theta_rows(circ, B, w * B), traj_offset=w * B, stats=False)
+        torch.cuda.synchronize()
+        log(f"warmup step {w} done")
+    params = [theta_rows(circ, B, (args.warmup + k) * B) for k in range(args.steps)]
+    params_dev = [torch.as_tensor(p, device="cuda") for p in params]
+    eng.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = None
+    for k in range(args.steps):
+        res = eng.run_circuit(ol, theta=params_dev[k], traj_offset=(args.warmup + k) * B, stats=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = eng.profile_read()
+    eng.profile(False)
+    log(f"timed {args.steps} steps in {t1 - t0:.3f} s")
+    # one more step with statistics (untimed) for the report
+    st = eng.run_circuit(ol, theta=params_dev[0], traj_offset=args.warmup * B, stats=True).stats
+    fail = eng.decode(res.records, circ.data_rec, circ.code.checks)
+    p_fail = float(fail.float().mean().item())
+    eng.close()
+    return t1 - t0, prof, st, p_fail
+
+
+def run_plain(args, circ):
+    import torch
+    from paper_2511_05719_amd import TTNEngine
+    eng = TTNEngine(circ.n_qubits, 1, circ.leaf_of_qubit, chi_max=64, cutoff=1e-10, dtype="c128",
+                    seed=args.seed)
+    ol = eng.upload(circ)
+    eng.run_circuit(ol, theta=theta_rows(circ, 1, 0), traj_offset=0, stats=False)   # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.plain_shots):
+        eng.run_circuit(ol, theta=theta_rows(circ, 1, 3 * i + 1), traj_offset=3 * i + 1, stats=False)
+        torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    eng.close()
+    return (t1 - t0) / args.plain_shots
+
+
+def cpu_oracle(circ, seed):
+    """The FP64 oracle (lazy-ancilla state vector, numpy, one thread) on the
+    same circuit: ops 47-54 of one trajectory, all on the full 28-qubit live
+    register, timed as the difference of two runs."""
+    import numpy as np
+    from oracle import statevector as sv
+    try:
+        from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(1)
+    except Exception:
+        lim = None
+    ka, kb = 46, 54
+    t0 = time.perf_counter()
+    sv.run(circ, 0.1, 0.0, seed, np.arange(1), stop_after_op=ka)
+    t1 = time.perf_counter()
+    sv.run(circ, 0.1, 0.0, seed, np.arange(1), stop_after_op=kb)
+    t2 = time.perf_counter()
+    if lim is not None:
+        lim.unregister() if hasattr(lim, "unregister") else None
+    rate = (kb - ka) / max((t2 - t1) - (t1 - t0), 1e-9)
+    return rate, (t2 - t0)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--rounds", type=int, default=5)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--plain-shots", type=int, default=2)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (trajectories shard "
+              "across GPUs by id ranges, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs as a single process on one GPU", file=sys.stderr)
+        sys.exit(2)
+    from workload import build_circuit, ops_per_shot
+    circ = build_circuit(5, args.rounds, "srx")
+    ops = ops_per_shot(circ)
+
+    dt, prof, st, p_fail = run_batched(args, circ)
+    shots = args.steps * args.batch
+    shots_per_s = shots / dt
+    value = shots_per_s * ops
+
+    # roofline of the kernel class that took the most time
+    classes = {k: v for k, v in prof.items() if k != "other"}
+    dom = max(classes, key=lambda k: classes[k]["ms"])
+    d = prof[dom]
+    avg_ms = d["ms"] / max(d["launches"], 1)
+    roof = {"kernel_class": dom, "launches": d["launches"], "avg_ms": avg_ms,
+            "share_of_gpu_time": d["ms"] / max(sum(v["ms"] for v in prof.values()), 1e-9)}
+    if dom.startswith("eigh"):
+        achieved = d["alg_flops"] / max(d["ms"] / 1e3, 1e-12)
+        roof.update({"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK["fp64_valu"] / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK["fp64_valu"], "traffic": None,
+                     "per_unit": "36 n^3 real flops per n x n complex Hermitian eigen-decomposition, "
+                                 "n = actual bond dimension"})
+    else:
+        roof.update({"bound": "mfma", "achieved": None, "peak": (PEAK["fp32_mfma"] if dom == "contract"
+                                                                 else PEAK["fp64_mfma"]) / 1e12,
+                     "unit": "TFLOP/s", "frac": None, "traffic": None})
+
+    plain = None
+    if not args.no_plain:
+        sec = run_plain(args, circ)
+        plain = {"dtype": "c128", "batch": 1, "s_per_shot": sec, "shots_per_s": 1.0 / sec,
+                 "trajectory_gates_per_s": ops / sec, "shots": args.plain_shots}
+    cpu = None
+    if not args.no_cpu:
+        rate, wall = cpu_oracle(circ, args.seed)
+        cpu = {"value": rate, "unit": "trajectory-gates/s", "cores": 1, "kind": "oracle",
+               "sample": "FP64 lazy-ancilla state-vector oracle (numpy, 1 thread): ops 47-54 of one "
+                         "d=5 C=5 SRX trajectory on the full 28-qubit live register "
+                         f"({wall:.1f} s of CPU work)"}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "trajectory-gates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 (FP32 MFMA) + f64 (Gram, eigen, probabilities)",
+        "data": "synthetic",
+        "config": {"workload": f"d=5 colour code, 37 qubits, {args.rounds} rounds, SRX theta grid "
+                               "linspace(0.02,0.2,8), chi_max=64, cutoff 1e-10, batched complex64",
+                   "batch": args.batch, "ops_per_shot": ops, "leaves": circ.n_leaves,
+                   "layout": "default (qubit i on leaf i)", "parallelism": "single GPU"},
+        "shots_per_s": shots_per_s,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "plain_c128": plain,
+        "speedup_vs_plain_c128": (shots_per_s * plain["s_per_shot"]) if plain else None,
+        "kernel_time_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
+        "run_stats": {"p_fail": p_fail, "max_rank": st.get("max_rank"),
+                      "mean_discarded_weight": st.get("discarded_weight", 0.0) / args.batch,
+                      "hops_per_batch": st.get("hops"), "launches_per_batch": st.get("launches")},
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -219,7 +219,8 @@ double ttn_philox_uniform_host(uint64_t seed, uint64_t traj, uint64_t draw);
  *  ttn_test_eigh: the factors of a centre move computed from G (as in
  *    ttn_ctx's hops): W_iso[t][a][i] = V[i][a] / s_a, W_abs[t][a][i] =
  *    conj(V[i][a]) s_a / |s_kept|, a < rank[t] in descending s, zero beyond;
- *    rows <= batch, n <= 2 * min(chi_max, ...) of the context. */
+ *    rows <= batch, n <= 2 * min(chi_max, ...) of the context; sweeps
+ *    (device int32 [rows] or NULL) receives the Jacobi sweep count. */
 ttn_status ttn_test_leg_apply(ttn_ctx* ctx, int32_t rows, const int32_t* dims3, int32_t leg, const void* T,
                               int64_t t_elems, const void* W, int64_t w_elems, int32_t newd, void* out,
                               int64_t out_elems);
@@ -227,7 +228,28 @@ ttn_status ttn_test_gram(ttn_ctx* ctx, int32_t rows, const int32_t* dims3, int32
                          int64_t t_elems, double* G, int64_t g_elems);
 ttn_status ttn_test_eigh(ttn_ctx* ctx, int32_t rows, int32_t n, int32_t new_pad, int32_t cap, double cutoff,
                          const double* G, int64_t g_elems, void* W_iso, void* W_abs, int64_t w_elems,
-                         int32_t* rank);
+                         int32_t* rank, int32_t* sweeps);
+
+/* Profiling.  While enabled, every kernel launch of the context is
+ * bracketed by HIP events on its stream, grouped by kernel class, and the
+ * eigen-decomposition kernels add their algorithmic work to a per-row ledger
+ * (36 n^3 real flops for an n x n complex Hermitian eigen-decomposition with
+ * vectors, n = the actual number of non-zero eigenvalues).  Enabling resets
+ * the counters.  ttn_profile_read [sync] returns, for one class, the summed
+ * elapsed milliseconds, the number of launches and the ledgered flops (0 for
+ * classes without a ledger). */
+enum {
+  TTN_CLASS_CONTRACT = 0,     /* c64/c128 leg contractions (MFMA)           */
+  TTN_CLASS_GRAM = 1,         /* FP64 Gram matrices (MFMA)                  */
+  TTN_CLASS_EIGH_SMALL = 2,   /* Jacobi eigensolver, n <= 64, vectors in LDS */
+  TTN_CLASS_EIGH_LARGE = 3,   /* Jacobi eigensolver, n > 64 (both kernels)  */
+  TTN_CLASS_LEAF = 4,         /* bottom-node gates, measurements, jumps     */
+  TTN_CLASS_EXTEND = 5,       /* controlled-gate index extensions           */
+  TTN_CLASS_OTHER = 6,
+  TTN_NCLASS = 7
+};
+ttn_status ttn_profile_enable(ttn_ctx* ctx, int32_t on);
+ttn_status ttn_profile_read(ttn_ctx* ctx, int32_t cls, double* ms, int64_t* launches, double* alg_flops);
 
 /* Library build identification (no GPU needed). */
 const char* ttn_version(void);

@@ -11,13 +11,20 @@
 // renormalises the kept part (the paper truncates the smallest Schmidt
 // coefficients, Sec. IV.A).
 //
-// One 256-thread workgroup per trajectory.  G lives in LDS as its packed
-// upper triangle (<= 132 KB at n = 128).  Each Jacobi step rotates n/2
-// disjoint index pairs chosen by the round-robin (circle) schedule, so every
-// pair is visited once per sweep; a step updates every 2 x 2 block
-// (P, Q) of G by J_P^H G_PQ J_Q.  For n <= 64 the eigenvectors are
-// accumulated in LDS next to G; for larger n each step's rotations are
-// written to a log that a second kernel replays onto row blocks of V.
+// One workgroup per problem.  G lives in LDS as its packed upper triangle
+// (<= 132 KB at n = 128).  Each Jacobi step rotates n/2 disjoint index pairs
+// chosen by the round-robin (circle) schedule, so every pair is visited once
+// per sweep; a step updates every 2 x 2 block (P, Q) of G by J_P^H G_PQ J_Q.
+// For n <= 64 the eigenvectors are accumulated in LDS next to G; for larger n
+// each step's rotations go to a log that a second kernel replays onto row
+// blocks of V.
+//
+// Block-diagonal mode (blocks = 2): while a controlled gate's index rides on
+// a bond, the Gram matrix is block diagonal (the two halves carry orthogonal
+// projections of the start qubit), so each diagonal half is solved by its
+// own workgroup; cutoff and normalisation refer to the trace of the whole
+// matrix, and each workgroup writes its own diagonal block of the factors
+// (and zeros in its rows of the other block).
 #include "ttn_device.h"
 #include "ttn_kernels.h"
 
@@ -25,6 +32,7 @@ namespace ttn {
 
 constexpr int kMaxSweeps = 24;
 constexpr int kVLdsMax = 64;
+constexpr int kThreads = 512;
 int eigh_max_sweeps() { return kMaxSweeps; }
 
 __device__ inline int pidx(int i, int j, int n) {   // packed upper triangle, i <= j
@@ -37,24 +45,50 @@ __device__ inline void gset(double2* Gp, int i, int j, int n, double2 v) {
   if (i <= j) Gp[pidx(i, j, n)] = v;
   else Gp[pidx(j, i, n)] = cconj(v);
 }
+// circle-method pairing for step s of an even size n (no integer division)
 __device__ inline void pair_of(int n, int s, int j, int* p, int* q) {
   int a, b;
   if (j == 0) { a = n - 1; b = s; }
-  else { a = (s + j) % (n - 1); b = (s - j + n - 1) % (n - 1); }
+  else {
+    a = s + j; if (a >= n - 1) a -= n - 1;
+    b = s - j; if (b < 0) b += n - 1;
+  }
   *p = a < b ? a : b;
   *q = a < b ? b : a;
 }
 
 struct Rot { double c; double2 s; double delta; };
 
+struct Problem {       // one diagonal block of one trajectory's matrix
+  long long t;
+  int k;               // block index
+  int n;               // block size
+  int off;             // row/column offset of the block in G and in W
+  int pad;             // rows of W owned by this block
+  int pad_off;         // first such row
+};
+
+__device__ inline Problem problem_of(const EighDesc& d, long long bid) {
+  Problem p;
+  const int nb = d.blocks > 1 ? 2 : 1;
+  p.t = bid / nb;
+  p.k = (int)(bid % nb);
+  p.n = d.n / nb;
+  p.off = p.k * p.n;
+  p.pad = d.new_pad / nb;
+  p.pad_off = p.k * p.pad;
+  return p;
+}
+
 template <typename S>
-__device__ void write_factors(const EighDesc& d, long long t, int row_lo, int row_hi,
-                              const double2* Vrows /* rows [row_lo,row_hi) x n2 */, int n2,
-                              const int* order, const double* lam_sorted, int k, double scale_abs) {
-  S* Wi = (S*)d.W_iso + t * (long long)d.new_pad * d.n;
-  S* Wa = (S*)d.W_abs + t * (long long)d.new_pad * d.n;
+__device__ void write_factors(const EighDesc& d, const Problem& pb, int row_lo, int row_hi,
+                              const double2* Vrows /* rows [row_lo,row_hi) x n2 */, int n2, const int* order,
+                              const double* lam_sorted, int k, double scale_abs) {
+  S* Wi = (S*)d.W_iso + pb.t * (long long)d.new_pad * d.n;
+  S* Wa = (S*)d.W_abs + pb.t * (long long)d.new_pad * d.n;
   const int nrows = row_hi - row_lo;
-  for (int idx = threadIdx.x; idx < d.new_pad * nrows; idx += blockDim.x) {
+  // own block: rows pad_off .. pad_off + pad, columns off + [row_lo, row_hi)
+  for (int idx = threadIdx.x; idx < pb.pad * nrows; idx += blockDim.x) {
     const int a = idx / nrows;
     const int i = row_lo + idx % nrows;
     double2 wi = make_double2(0.0, 0.0), wa = make_double2(0.0, 0.0);
@@ -64,46 +98,64 @@ __device__ void write_factors(const EighDesc& d, long long t, int row_lo, int ro
       wi = cscale(v, 1.0 / s);
       wa = cscale(cconj(v), s * scale_abs);
     }
-    Wi[(long long)a * d.n + i] = from_d2<S>(wi);
-    Wa[(long long)a * d.n + i] = from_d2<S>(wa);
+    const long long o = (long long)(pb.pad_off + a) * d.n + pb.off + i;
+    Wi[o] = from_d2<S>(wi);
+    Wa[o] = from_d2<S>(wa);
+  }
+  if (d.blocks > 1) {
+    // zeros of my rows in the other block's columns
+    const int other = (1 - pb.k) * pb.n;
+    for (int idx = threadIdx.x; idx < pb.pad * nrows; idx += blockDim.x) {
+      const int a = idx / nrows;
+      const int i = row_lo + idx % nrows;
+      const long long o = (long long)(pb.pad_off + a) * d.n + other + i;
+      Wi[o] = from_d2<S>(make_double2(0.0, 0.0));
+      Wa[o] = from_d2<S>(make_double2(0.0, 0.0));
+    }
   }
 }
 
 template <bool kVinLds>
-__global__ void __launch_bounds__(256) k_jacobi(EighDesc d) {
+__global__ void __launch_bounds__(kThreads) k_jacobi(EighDesc d) {
   extern __shared__ double2 smem[];
-  const long long t = blockIdx.x;
-  const int n = d.n;
+  const Problem pb = problem_of(d, blockIdx.x);
+  const long long t = pb.t;
+  const int n = pb.n;
   const int n2 = n + (n & 1);          // even size, a zero dummy index if odd
   const int h = n2 / 2;
   const int npk = n2 * (n2 + 1) / 2;
+  const int nblk = h * (h + 1) / 2;
   double2* Gp = smem;                                  // packed G
   double2* V = smem + npk;                             // [n2][n2] if kVinLds
   __shared__ Rot rot[64];
+  __shared__ unsigned short blk[2080];                 // (P, Q) of the upper 2x2 blocks
   __shared__ double lam[128];
   __shared__ int order_s[128];
-  __shared__ double red[256];
+  __shared__ double red[kThreads];
   __shared__ int any_rot;
   __shared__ double trace_s;
-  const double2* G = d.G + t * (long long)n * n;
+  const double2* G = d.G + t * (long long)d.n * d.n;
 
   for (int idx = threadIdx.x; idx < npk; idx += blockDim.x) {
-    // decode packed index -> (i, j)
     int i = 0, rem = idx;
     while (rem >= n2 - i) { rem -= n2 - i; ++i; }
     const int j = i + rem;
-    Gp[idx] = (i < n && j < n) ? G[(long long)i * n + j] : make_double2(0.0, 0.0);
+    Gp[idx] = (i < n && j < n) ? G[(long long)(pb.off + i) * d.n + pb.off + j] : make_double2(0.0, 0.0);
+  }
+  for (int idx = threadIdx.x; idx < nblk; idx += blockDim.x) {
+    int P = 0, rem = idx;
+    while (rem >= h - P) { rem -= h - P; ++P; }
+    blk[idx] = (unsigned short)(P | ((P + rem) << 8));
   }
   if (kVinLds)
     for (int idx = threadIdx.x; idx < n2 * n2; idx += blockDim.x)
       V[idx] = make_double2((idx / n2 == idx % n2) ? 1.0 : 0.0, 0.0);
-  __syncthreads();
-  // trace (for the absolute rotation floor)
+  // trace of the whole matrix (both blocks in block-diagonal mode)
   double part = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) part += Gp[pidx(i, i, n2)].x;
+  for (int i = threadIdx.x; i < d.n; i += blockDim.x) part += G[(long long)i * d.n + i].x;
   red[threadIdx.x] = part;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
@@ -112,7 +164,7 @@ __global__ void __launch_bounds__(256) k_jacobi(EighDesc d) {
   const double tr = trace_s;
   const bool finite = isfinite(tr) && tr > 0.0;
 
-  int step_count = 0;
+  int step_count = 0, sweeps_done = 0;
   double* log = d.rot_log ? d.rot_log + t * (long long)d.max_steps * h * 3 : nullptr;
   if (n2 >= 2 && finite) {
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
@@ -146,12 +198,12 @@ __global__ void __launch_bounds__(256) k_jacobi(EighDesc d) {
         }
         __syncthreads();
         // -- G <- J^H G J, block by block --
-        for (int idx = threadIdx.x; idx < h * h; idx += blockDim.x) {
-          const int P = idx / h, Q = idx % h;
-          if (P > Q) continue;
-          int p, q, pp, qq;
-          pair_of(n2, s, P, &p, &q);
+        for (int idx = threadIdx.x; idx < nblk; idx += blockDim.x) {
+          const unsigned short pq = blk[idx];
+          const int P = pq & 0xff, Q = pq >> 8;
           const Rot rP = rot[P];
+          int p, q;
+          pair_of(n2, s, P, &p, &q);
           if (P == Q) {
             if (rP.delta != 0.0) {
               double2 gpp = Gp[pidx(p, p, n2)], gqq = Gp[pidx(q, q, n2)];
@@ -163,9 +215,10 @@ __global__ void __launch_bounds__(256) k_jacobi(EighDesc d) {
             }
             continue;
           }
-          pair_of(n2, s, Q, &pp, &qq);
           const Rot rQ = rot[Q];
           if (rP.delta == 0.0 && rQ.delta == 0.0) continue;
+          int pp, qq;
+          pair_of(n2, s, Q, &pp, &qq);
           const double2 g00 = gget(Gp, p, pp, n2), g01 = gget(Gp, p, qq, n2);
           const double2 g10 = gget(Gp, q, pp, n2), g11 = gget(Gp, q, qq, n2);
           // X = G_PQ J_Q,  J = [[c, s], [-conj(s), c]]
@@ -184,7 +237,7 @@ __global__ void __launch_bounds__(256) k_jacobi(EighDesc d) {
         if (kVinLds) {
           // V <- V J (columns p, q of every row)
           for (int idx = threadIdx.x; idx < n2 * h; idx += blockDim.x) {
-            const int r = idx / h, P = idx % h;
+            const int r = idx / h, P = idx - (idx / h) * h;
             const Rot rP = rot[P];
             if (rP.delta == 0.0) continue;
             int p, q;
@@ -197,6 +250,7 @@ __global__ void __launch_bounds__(256) k_jacobi(EighDesc d) {
         ++step_count;
         __syncthreads();
       }
+      ++sweeps_done;
       if (any_rot == 0) break;
       __syncthreads();
     }
@@ -217,28 +271,50 @@ __global__ void __launch_bounds__(256) k_jacobi(EighDesc d) {
   __shared__ int k_s;
   __shared__ double scale_s;
   if (threadIdx.x == 0) {
-    double tot = 0.0;
-    for (int i = 0; i < n; ++i) tot += lam[i];
+    double mine = 0.0;
+    for (int i = 0; i < n; ++i) mine += lam[i];
+    const double tot = d.blocks > 1 ? tr : mine;
     int k = 0;
     double kept = 0.0;
-    const int lim = min(min(d.cap, d.new_pad), n);
+    const int lim = min(min(d.cap, pb.pad), n);
     if (finite && tot > 0.0) {
       while (k < lim && lam[order_s[k]] > d.cutoff * tot) { kept += lam[order_s[k]]; ++k; }
     }
-    if (!(kept > 0.0) || !isfinite(kept)) {
-      k = 0;
-      if (d.flags) d.flags[t] |= 1;
-      scale_s = 0.0;
+    if (d.blocks > 1) {
+      // the joint state is normalised by the whole trace (the tiny dropped
+      // parts are renormalised by the truncating sweep that follows)
+      scale_s = finite ? 1.0 / sqrt(tr) : 0.0;
+      if (!finite && d.flags) atomicOr(d.flags + t, 1);
+      if (d.disc_acc && tot > 0.0) atomicAdd(d.disc_acc + t, (mine - kept) / tot);
     } else {
-      scale_s = 1.0 / sqrt(kept);
+      if (!(kept > 0.0) || !isfinite(kept)) {
+        k = 0;
+        if (d.flags) d.flags[t] |= 1;
+        scale_s = 0.0;
+      } else {
+        scale_s = 1.0 / sqrt(kept);
+      }
+      if (d.disc_acc && tot > 0.0) d.disc_acc[t] += (tot - kept) / tot;
+      if (d.degen_acc && k > 0 && k < n) {
+        const double lk1 = lam[order_s[k - 1]], lk = lam[order_s[k]];
+        if (lk > d.cutoff * tot && lk1 - lk <= 1e-6 * lk1) d.degen_acc[t] += 1;
+      }
+      if (d.rank_out) d.rank_out[t * d.rank_stride] = k;
+      if (d.rank_max) d.rank_max[t * d.rank_stride] = max(d.rank_max[t * d.rank_stride], k);
     }
-    if (d.disc_acc && tot > 0.0) d.disc_acc[t] += (tot - kept) / tot;
-    if (d.degen_acc && k > 0 && k < n) {
-      const double lk1 = lam[order_s[k - 1]], lk = lam[order_s[k]];
-      if (lk > d.cutoff * tot && lk1 - lk <= 1e-6 * lk1) d.degen_acc[t] += 1;
+    if (d.flops_acc) {
+      // algorithmic work of an n x n complex Hermitian eigen-decomposition
+      // with vectors: 36 n^3 real flops (9 n^3 for the real symmetric case,
+      // Golub & Van Loan, times 4 for complex arithmetic), n = the number of
+      // non-zero eigenvalues (the actual bond dimension)
+      int na = 0;
+      for (int i = 0; i < n; ++i) na += lam[i] > 1e-15 * tot;
+      const double f = 36.0 * (double)na * na * na;
+      if (d.blocks > 1) atomicAdd(d.flops_acc + t, f);
+      else d.flops_acc[t] += f;
     }
-    if (d.rank_out) d.rank_out[t * d.rank_stride] = k;
     k_s = k;
+    if (d.sweeps_out) d.sweeps_out[t] = sweeps_done;
     if (!kVinLds) {
       d.kept[t] = k;
       d.scale_abs[t] = scale_s;
@@ -251,9 +327,9 @@ __global__ void __launch_bounds__(256) k_jacobi(EighDesc d) {
     for (int a = threadIdx.x; a < n; a += blockDim.x) lam_sorted[a] = lam[order_s[a]];
     __syncthreads();
     if (d.out_c128)
-      write_factors<double2>(d, t, 0, n, V, n2, order_s, lam_sorted, k_s, scale_s);
+      write_factors<double2>(d, pb, 0, n, V, n2, order_s, lam_sorted, k_s, scale_s);
     else
-      write_factors<float2>(d, t, 0, n, V, n2, order_s, lam_sorted, k_s, scale_s);
+      write_factors<float2>(d, pb, 0, n, V, n2, order_s, lam_sorted, k_s, scale_s);
   } else {
     for (int a = threadIdx.x; a < n; a += blockDim.x) {
       d.order[t * n + a] = order_s[a];
@@ -262,9 +338,10 @@ __global__ void __launch_bounds__(256) k_jacobi(EighDesc d) {
   }
 }
 
-// Replay the rotation log onto a block of rows of V = I and write the factors.
-constexpr int kRowsPerBlock = 32;
-__global__ void __launch_bounds__(256) k_jacobi_vectors(EighDesc d) {
+// Replay the rotation log onto a block of rows of V = I and write the factors
+// (single-block problems of size > 64).
+constexpr int kRowsPerBlock = 64;
+__global__ void __launch_bounds__(kThreads) k_jacobi_vectors(EighDesc d) {
   extern __shared__ double2 smem[];
   const int n = d.n;
   const int n2 = n + (n & 1);
@@ -285,15 +362,15 @@ __global__ void __launch_bounds__(256) k_jacobi_vectors(EighDesc d) {
   const int steps = d.nsteps[t];
   const double* log = d.rot_log + t * (long long)d.max_steps * h * 3;
   __syncthreads();
+  int s = 0;
   for (int st = 0; st < steps; ++st) {
-    const int s = st % (n2 - 1);
     if (threadIdx.x < h) {
       const double* e = log + ((long long)st * h + threadIdx.x) * 3;
       rc[threadIdx.x] = e[0]; rsx[threadIdx.x] = e[1]; rsy[threadIdx.x] = e[2];
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < nr * h; idx += blockDim.x) {
-      const int r = idx / h, P = idx % h;
+      const int r = idx / h, P = idx - (idx / h) * h;
       const double c = rc[P];
       const double2 sv = make_double2(rsx[P], rsy[P]);
       if (c == 1.0 && sv.x == 0.0 && sv.y == 0.0) continue;
@@ -303,6 +380,7 @@ __global__ void __launch_bounds__(256) k_jacobi_vectors(EighDesc d) {
       V[r * n2 + p] = csub(cscale(vp, c), cmul(cconj(sv), vq));
       V[r * n2 + q] = cadd(cmul(sv, vp), cscale(vq, c));
     }
+    if (++s == n2 - 1) s = 0;
     __syncthreads();
   }
   for (int a = threadIdx.x; a < n; a += blockDim.x) {
@@ -312,31 +390,45 @@ __global__ void __launch_bounds__(256) k_jacobi_vectors(EighDesc d) {
   __syncthreads();
   const int k = d.kept[t];
   const double sc = d.scale_abs[t];
+  Problem pb;
+  pb.t = t; pb.k = 0; pb.n = n; pb.off = 0; pb.pad = d.new_pad; pb.pad_off = 0;
   if (d.out_c128)
-    write_factors<double2>(d, t, row_lo, row_hi, V, n2, order_s, lam_s, k, sc);
+    write_factors<double2>(d, pb, row_lo, row_hi, V, n2, order_s, lam_s, k, sc);
   else
-    write_factors<float2>(d, t, row_lo, row_hi, V, n2, order_s, lam_s, k, sc);
+    write_factors<float2>(d, pb, row_lo, row_hi, V, n2, order_s, lam_s, k, sc);
 }
+
+static bool g_attr_done = false;
 
 hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st) {
   if (batch <= 0) return hipSuccess;
-  if (d.n < 1 || d.n > 128 || d.new_pad < 1) return hipErrorInvalidValue;
-  const int n2 = d.n + (d.n & 1);
+  const int nb = d.blocks > 1 ? 2 : 1;
+  if (d.n < 1 || d.n > 128 || d.new_pad < 1 || (nb == 2 && ((d.n & 1) || (d.new_pad & 1))))
+    return hipErrorInvalidValue;
+  if (!g_attr_done) {
+    hipFuncSetAttribute((const void*)k_jacobi<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
+    hipFuncSetAttribute((const void*)k_jacobi<false>, hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
+    hipFuncSetAttribute((const void*)k_jacobi_vectors, hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
+    g_attr_done = true;
+  }
+  const int nsub = d.n / nb;
+  const int n2 = nsub + (nsub & 1);
   const size_t gbytes = (size_t)n2 * (n2 + 1) / 2 * sizeof(double2);
   if (n2 <= kVLdsMax) {
     const size_t bytes = gbytes + (size_t)n2 * n2 * sizeof(double2);
-    hipLaunchKernelGGL(k_jacobi<true>, dim3(batch), dim3(256), bytes, st, d);
+    hipLaunchKernelGGL(k_jacobi<true>, dim3((unsigned)((long long)batch * nb)), dim3(kThreads), bytes, st, d);
     return hipGetLastError();
   }
+  if (nb != 1) return hipErrorInvalidValue;
   if (!d.rot_log || !d.order || !d.lam_sorted || !d.kept || !d.scale_abs || !d.nsteps)
     return hipErrorInvalidValue;
   if ((long long)d.max_steps < (long long)kMaxSweeps * (n2 - 1)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_jacobi<false>, dim3(batch), dim3(256), gbytes, st, d);
+  hipLaunchKernelGGL(k_jacobi<false>, dim3(batch), dim3(kThreads), gbytes, st, d);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int nblk = (d.n + kRowsPerBlock - 1) / kRowsPerBlock;
   const size_t vbytes = (size_t)kRowsPerBlock * n2 * sizeof(double2);
-  hipLaunchKernelGGL(k_jacobi_vectors, dim3((unsigned)((long long)batch * nblk)), dim3(256), vbytes, st, d);
+  hipLaunchKernelGGL(k_jacobi_vectors, dim3((unsigned)((long long)batch * nblk)), dim3(kThreads), vbytes, st, d);
   return hipGetLastError();
 }
 

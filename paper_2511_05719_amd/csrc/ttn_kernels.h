@@ -38,8 +38,12 @@ struct EighDesc {
   void* W_iso;          // [batch][new_pad][n]  (float2 or double2)
   void* W_abs;          // [batch][new_pad][n]
   int out_c128;         // 1: W in double2, 0: float2
+  int blocks;           // 1, or 2: G is block diagonal, solve the halves apart
   int* rank_out;        // [batch] stride rank_stride (may be null)
+  int* rank_max;        // [batch] stride rank_stride: running maximum (may be null)
   long long rank_stride;
+  double* flops_acc;    // [batch] += algorithmic flops (may be null)
+  int* sweeps_out;      // [batch] Jacobi sweeps used (may be null)
   double* disc_acc;     // [batch] += discarded weight fraction
   int* flags;           // [batch] |= 1 on non-finite / zero norm
   int* degen_acc;       // [batch] += 1 on a cut inside a near-degenerate cluster

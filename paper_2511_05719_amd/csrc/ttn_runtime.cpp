@@ -34,6 +34,12 @@
 
 using namespace ttn;
 
+enum {
+  CLS_GEMM = TTN_CLASS_CONTRACT, CLS_GRAM = TTN_CLASS_GRAM, CLS_EIGH_SMALL = TTN_CLASS_EIGH_SMALL,
+  CLS_EIGH_LARGE = TTN_CLASS_EIGH_LARGE, CLS_LEAF = TTN_CLASS_LEAF, CLS_EXTEND = TTN_CLASS_EXTEND,
+  CLS_OTHER = TTN_CLASS_OTHER
+};
+
 namespace {
 
 struct Buf {
@@ -80,6 +86,8 @@ struct ttn_ctx {
   double* scale_abs = nullptr;
   int* nsteps = nullptr;
   int* rank_table = nullptr;   // [B][L] bond above node e
+  int* rank_max = nullptr;     // [B][L] running maximum of rank_table
+  double* eigh_flops = nullptr;  // [B] algorithmic flops of the eigen-decompositions
   double* disc_acc = nullptr;  // [B]
   int* flags = nullptr;        // [B]
   int* degen_acc = nullptr;    // [B]
@@ -91,6 +99,11 @@ struct ttn_ctx {
   std::vector<LeafOp> pend_ops;
   std::vector<int> pend_node;
   LeafBatch run{};             // run-level pointers of the pending ops
+  // profiling: HIP events around every launch of each kernel class
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[TTN_NCLASS];
+  size_t prof_used[TTN_NCLASS] = {0};
+  double* eigh_flops_cls[TTN_NCLASS] = {nullptr};   // device [B] ledgers of eigh classes
   // stats
   int64_t hops = 0, launches = 0;
   double gemm_flops = 0.0, gram_flops = 0.0;
@@ -165,6 +178,31 @@ static void adopt(ttn_ctx* c, int node, int buf) {
   c->node_buf[node] = buf;
 }
 static inline void* node_ptr(ttn_ctx* c, int node) { return c->bufs[c->node_buf[node]].p; }
+
+// ----------------------------------------------------------- profiling ----
+static void prof_begin(ttn_ctx* ctx, int cls, hipEvent_t* stop) {
+  *stop = nullptr;
+  if (!ctx->prof) return;
+  auto& v = ctx->prof_ev[cls];
+  size_t& u = ctx->prof_used[cls];
+  if (u == v.size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+    v.push_back({a, b});
+  }
+  hipEventRecord(v[u].first, ctx->st);
+  *stop = v[u].second;
+  ++u;
+}
+static void prof_end(ttn_ctx* ctx, hipEvent_t stop) {
+  if (stop) hipEventRecord(stop, ctx->st);
+}
+struct ProfScope {
+  ttn_ctx* c;
+  hipEvent_t e;
+  ProfScope(ttn_ctx* ctx, int cls) : c(ctx) { prof_begin(ctx, cls, &e); }
+  ~ProfScope() { prof_end(c, e); }
+};
 
 // -------------------------------------------------------- contractions ----
 // Largest element offset a GEMM operand can touch (host-side bounds check:
@@ -255,6 +293,7 @@ static ttn_status leg_apply(ttn_ctx* ctx, int src_buf, std::array<int, 3> d, int
     return fail(ctx, TTN_EINVAL, "internal: contraction exceeds its buffers");
   ctx->gemm_flops += 8.0 * (double)g.M * g.N * g.K * g.H * ctx->B;
   ++ctx->launches;
+  ProfScope ps(ctx, CLS_GEMM);
   TTN_CHECK_HIP(launch_zgemm(g, ctx->B, ctx->c128 ? GEMM_C128 : GEMM_C64, ctx->st));
   return TTN_OK;
 }
@@ -265,6 +304,7 @@ static ttn_status gram(ttn_ctx* ctx, int src_buf, std::array<int, 3> d, int leg)
     return fail(ctx, TTN_EINVAL, "internal: Gram exceeds its buffers");
   ctx->gram_flops += 8.0 * (double)g.M * g.N * g.K * ctx->B;
   ++ctx->launches;
+  ProfScope ps(ctx, CLS_GRAM);
   TTN_CHECK_HIP(launch_zgemm(g, ctx->B, ctx->c128 ? GEMM_GRAM_C128 : GEMM_GRAM_C64, ctx->st));
   return TTN_OK;
 }
@@ -273,7 +313,7 @@ static ttn_status gram(ttn_ctx* ctx, int src_buf, std::array<int, 3> d, int leg)
 // canonical form that makes local Schmidt values and Born probabilities
 // local): factor x = (x V S^-1)(S V^H) across the bond, keep the first factor
 // in x, absorb the second into y, truncating to `cap` values above `cutoff`.
-static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int new_pad) {
+static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int new_pad, int blocks = 1) {
   const int lx = leg_toward(x, y), ly = leg_toward(y, x);
   const int e = bond_node(x, y);
   std::array<int, 3> dx = ctx->dims[x], dy = ctx->dims[y];
@@ -285,12 +325,20 @@ static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int ne
   EighDesc ed{};
   ed.G = ctx->G; ed.n = n; ed.new_pad = new_pad; ed.cap = cap; ed.cutoff = cutoff;
   ed.W_iso = ctx->Wi; ed.W_abs = ctx->Wa; ed.out_c128 = ctx->c128;
-  ed.rank_out = ctx->rank_table + e; ed.rank_stride = ctx->L;
+  ed.blocks = blocks;
+  ed.rank_out = blocks > 1 ? nullptr : ctx->rank_table + e;
+  ed.rank_max = blocks > 1 ? nullptr : ctx->rank_max + e;
+  ed.rank_stride = ctx->L;
+  const bool large = (n / blocks + ((n / blocks) & 1)) > 64;
+  ed.flops_acc = ctx->eigh_flops_cls[large ? CLS_EIGH_LARGE : CLS_EIGH_SMALL];
   ed.disc_acc = ctx->disc_acc; ed.flags = ctx->flags; ed.degen_acc = ctx->degen_acc;
   ed.rot_log = ctx->rot_log; ed.max_steps = ctx->max_steps; ed.lam_sorted = ctx->lam_sorted;
   ed.order = ctx->order; ed.kept = ctx->kept; ed.scale_abs = ctx->scale_abs; ed.nsteps = ctx->nsteps;
-  ctx->launches += (n + (n & 1)) > 64 ? 2 : 1;
-  TTN_CHECK_HIP(launch_eigh(ed, ctx->B, ctx->st));
+  ctx->launches += large ? 2 : 1;
+  {
+    ProfScope ps(ctx, large ? CLS_EIGH_LARGE : CLS_EIGH_SMALL);
+    TTN_CHECK_HIP(launch_eigh(ed, ctx->B, ctx->st));
+  }
   const int bx = acquire(ctx, ctx->node_cls[x]);
   if (bx < 0) return fail(ctx, TTN_EINVAL, "internal: pool exhausted");
   TTN_TRY(leg_apply(ctx, ctx->node_buf[x], dx, lx, ctx->Wi, new_pad, bx));
@@ -344,6 +392,7 @@ static ttn_status flush_leaf(ttn_ctx* ctx) {
     b.flags = ctx->flags;
     b.seed = ctx->seed;
     ++ctx->launches;
+    ProfScope ps(ctx, CLS_LEAF);
     TTN_CHECK_HIP(launch_leaf_ops(b, ctx->st));
   }
   ctx->pend_ops.clear();
@@ -396,6 +445,7 @@ static ttn_status controlled_gate(ttn_ctx* ctx, int qs, const double P[2][2][2][
     if (elems(d) * 2 * ctx->B > buf_elems(ctx, b)) return fail(ctx, TTN_EINVAL, "internal: split exceeds buffer");
     x.dst = ctx->bufs[b].p;
     ++ctx->launches;
+    ProfScope ps(ctx, CLS_EXTEND);
     TTN_CHECK_HIP(launch_extend(x, ctx->B, ctx->st));
     adopt(ctx, ns, b);
     ctx->dims[ns][2] *= 2;
@@ -426,15 +476,23 @@ static ttn_status controlled_gate(ttn_ctx* ctx, int qs, const double P[2][2][2][
     if (elems(e) * ctx->B > buf_elems(ctx, b)) return fail(ctx, TTN_EINVAL, "internal: extension exceeds buffer");
     ex.dst = ctx->bufs[b].p;
     ++ctx->launches;
-    TTN_CHECK_HIP(launch_extend(ex, ctx->B, ctx->st));
+    {
+      ProfScope ps(ctx, CLS_EXTEND);
+      TTN_CHECK_HIP(launch_extend(ex, ctx->B, ctx->st));
+    }
     adopt(ctx, y, b);
     ctx->dims[y] = e;
     // exact move across (x, y): the bond can hold the near side's full space
     const int n = ctx->dims[x][leg_toward(x, y)];
     const int qnear = (y == x / 2) ? ctx->nq_below[x] : ctx->N - ctx->nq_below[y];
     const long long near_dim = qnear >= 30 ? (1ll << 30) : (1ll << qnear);
-    const int pad = (int)std::min<long long>(n, near_dim);
-    TTN_TRY(hop(ctx, x, y, ctx->cutoff, pad, pad));
+    if (n >= 64 && near_dim >= n) {
+      // the Gram matrix is block diagonal in k: two independent halves
+      TTN_TRY(hop(ctx, x, y, ctx->cutoff, n / 2, n, 2));
+    } else {
+      const int pad = (int)std::min<long long>(n, near_dim);
+      TTN_TRY(hop(ctx, x, y, ctx->cutoff, pad, pad));
+    }
   }
   for (int i = m; i > 0; --i) TTN_TRY(hop_truncating(ctx, path[i], path[i - 1]));
   return TTN_OK;
@@ -499,6 +557,8 @@ static ttn_status reset_state(ttn_ctx* ctx, const uint8_t* basis) {
   }
   ctx->centre = 1;
   TTN_CHECK_HIP(launch_fill_i32(ctx->rank_table, 1, (long long)ctx->B * ctx->L, ctx->st));
+  TTN_CHECK_HIP(launch_fill_i32(ctx->rank_max, 1, (long long)ctx->B * ctx->L, ctx->st));
+  TTN_CHECK_HIP(launch_fill_f64(ctx->eigh_flops, 0.0, 2ll * ctx->B, ctx->st));
   TTN_CHECK_HIP(launch_fill_i32(ctx->flags, 0, ctx->B, ctx->st));
   TTN_CHECK_HIP(launch_fill_i32(ctx->degen_acc, 0, ctx->B, ctx->st));
   TTN_CHECK_HIP(launch_fill_f64(ctx->disc_acc, 0.0, ctx->B, ctx->st));
@@ -511,7 +571,7 @@ static ttn_status fill_stats(ttn_ctx* ctx, ttn_stats* st) {
   TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
   std::vector<int> ranks((size_t)ctx->B * ctx->L), flags(ctx->B), degen(ctx->B);
   std::vector<double> disc(ctx->B);
-  TTN_CHECK_HIP(hipMemcpy(ranks.data(), ctx->rank_table, ranks.size() * 4, hipMemcpyDeviceToHost));
+  TTN_CHECK_HIP(hipMemcpy(ranks.data(), ctx->rank_max, ranks.size() * 4, hipMemcpyDeviceToHost));
   TTN_CHECK_HIP(hipMemcpy(flags.data(), ctx->flags, flags.size() * 4, hipMemcpyDeviceToHost));
   TTN_CHECK_HIP(hipMemcpy(degen.data(), ctx->degen_acc, degen.size() * 4, hipMemcpyDeviceToHost));
   TTN_CHECK_HIP(hipMemcpy(disc.data(), ctx->disc_acc, disc.size() * 8, hipMemcpyDeviceToHost));
@@ -714,6 +774,10 @@ ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {
   ok &= hipMalloc((void**)&ctx->scale_abs, Bz * sizeof(double)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->nsteps, Bz * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->rank_table, Bz * L * sizeof(int)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->rank_max, Bz * L * sizeof(int)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->eigh_flops, 2 * Bz * sizeof(double)) == hipSuccess;
+  ctx->eigh_flops_cls[CLS_EIGH_SMALL] = ctx->eigh_flops;
+  ctx->eigh_flops_cls[CLS_EIGH_LARGE] = ctx->eigh_flops + Bz;
   ok &= hipMalloc((void**)&ctx->disc_acc, Bz * sizeof(double)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->flags, Bz * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->degen_acc, Bz * sizeof(int)) == hipSuccess;
@@ -728,8 +792,14 @@ ttn_status ttn_destroy(ttn_ctx* ctx) {
   if (!ctx) return TTN_EINVAL;
   hipStreamSynchronize(ctx->st);
   for (auto& b : ctx->bufs) hipFree(b.p);
+  for (int c = 0; c < TTN_NCLASS; ++c)
+    for (auto& e : ctx->prof_ev[c]) {
+      hipEventDestroy(e.first);
+      hipEventDestroy(e.second);
+    }
   void* ws[] = {ctx->G, ctx->Wi, ctx->Wa, ctx->rot_log, ctx->lam_sorted, ctx->order, ctx->kept,
-                ctx->scale_abs, ctx->nsteps, ctx->rank_table, ctx->disc_acc, ctx->flags,
+                ctx->scale_abs, ctx->nsteps, ctx->rank_table, ctx->rank_max, ctx->eigh_flops,
+                ctx->disc_acc, ctx->flags,
                 ctx->degen_acc, ctx->leader, ctx->dec_datarec, ctx->dec_masks};
   for (void* p : ws)
     if (p) hipFree(p);
@@ -1117,6 +1187,36 @@ ttn_status ttn_bond_dims(ttn_ctx* ctx, int32_t row, int32_t* dims) {
   return TTN_OK;
 }
 
+ttn_status ttn_profile_enable(ttn_ctx* ctx, int32_t on) {
+  if (!ctx) return TTN_EINVAL;
+  TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
+  ctx->prof = on != 0;
+  for (int c = 0; c < TTN_NCLASS; ++c) ctx->prof_used[c] = 0;
+  TTN_CHECK_HIP(launch_fill_f64(ctx->eigh_flops, 0.0, 2ll * ctx->B, ctx->st));
+  return TTN_OK;
+}
+
+ttn_status ttn_profile_read(ttn_ctx* ctx, int32_t cls, double* ms, int64_t* launches, double* alg_flops) {
+  if (!ctx) return TTN_EINVAL;
+  if (cls < 0 || cls >= TTN_NCLASS || !ms || !launches || !alg_flops) return fail(ctx, TTN_EINVAL, "bad class");
+  TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
+  double tot = 0.0;
+  for (size_t i = 0; i < ctx->prof_used[cls]; ++i) {
+    float e = 0.0f;
+    TTN_CHECK_HIP(hipEventElapsedTime(&e, ctx->prof_ev[cls][i].first, ctx->prof_ev[cls][i].second));
+    tot += e;
+  }
+  *ms = tot;
+  *launches = (int64_t)ctx->prof_used[cls];
+  *alg_flops = 0.0;
+  if (ctx->eigh_flops_cls[cls]) {
+    std::vector<double> f(ctx->B);
+    TTN_CHECK_HIP(hipMemcpy(f.data(), ctx->eigh_flops_cls[cls], ctx->B * sizeof(double), hipMemcpyDeviceToHost));
+    for (double v : f) *alg_flops += v;
+  }
+  return TTN_OK;
+}
+
 ttn_status ttn_uniforms(ttn_ctx* ctx, uint64_t traj_offset, int32_t rows, int32_t n_draws, double* out) {
   if (!ctx) return TTN_EINVAL;
   if (rows < 0 || n_draws < 0 || !out) return fail(ctx, TTN_EINVAL, "bad arguments");
@@ -1157,7 +1257,7 @@ ttn_status ttn_test_gram(ttn_ctx* ctx, int32_t rows, const int32_t* dims3, int32
 
 ttn_status ttn_test_eigh(ttn_ctx* ctx, int32_t rows, int32_t n, int32_t new_pad, int32_t cap, double cutoff,
                          const double* G, int64_t g_elems, void* W_iso, void* W_abs, int64_t w_elems,
-                         int32_t* rank) {
+                         int32_t* rank, int32_t* sweeps) {
   if (!ctx) return TTN_EINVAL;
   if (rows < 1 || rows > ctx->B || n < 1 || n > ctx->nmax || new_pad < 1 || new_pad > ctx->nmax || cap < 1 || !G ||
       !W_iso || !W_abs || !rank)
@@ -1167,6 +1267,8 @@ ttn_status ttn_test_eigh(ttn_ctx* ctx, int32_t rows, int32_t n, int32_t new_pad,
   EighDesc ed{};
   ed.G = (const double2*)G; ed.n = n; ed.new_pad = new_pad; ed.cap = cap; ed.cutoff = cutoff;
   ed.W_iso = W_iso; ed.W_abs = W_abs; ed.out_c128 = ctx->c128;
+  ed.blocks = 1;
+  ed.sweeps_out = sweeps;
   ed.rank_out = rank; ed.rank_stride = 1;
   ed.rot_log = ctx->rot_log; ed.max_steps = ctx->max_steps; ed.lam_sorted = ctx->lam_sorted;
   ed.order = ctx->order; ed.kept = ctx->kept; ed.scale_abs = ctx->scale_abs; ed.nsteps = ctx->nsteps;

@@ -209,6 +209,18 @@ class TTNEngine:
               self._ctx)
         return fail
 
+    # ---------------------------------------------------------- profiling ----
+    def profile(self, on: bool = True):
+        check(lib().ttn_profile_enable(self._ctx, 1 if on else 0), self._ctx)
+
+    def profile_read(self) -> dict:
+        out = {}
+        for name, cls in _abi.CLASSES.items():
+            ms, n, fl = C.c_double(), C.c_int64(), C.c_double()
+            check(lib().ttn_profile_read(self._ctx, cls, C.byref(ms), C.byref(n), C.byref(fl)), self._ctx)
+            out[name] = {"ms": ms.value, "launches": n.value, "alg_flops": fl.value}
+        return out
+
     # ------------------------------------------------------------ exports ----
     def compress(self):
         check(lib().ttn_compress(self._ctx), self._ctx)

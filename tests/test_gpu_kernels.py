@@ -112,7 +112,7 @@ def test_eigh_centre_move_factors(dtype, n, rank):
     rk = torch.zeros(rows, dtype=torch.int32, device="cuda")
     cutoff = 1e-13
     check(lib().ttn_test_eigh(eng._ctx, rows, n, n, n, cutoff, Gd.data_ptr(), rows * n * n, Wi.data_ptr(),
-                              Wa.data_ptr(), rows * n * n, rk.data_ptr()), eng._ctx)
+                              Wa.data_ptr(), rows * n * n, rk.data_ptr(), None), eng._ctx)
     Wi, Wa, rk = _host_complex(Wi), _host_complex(Wa), rk.cpu().numpy()
     for t in range(rows):
         s = np.linalg.svd(M[t], compute_uv=False)
@@ -152,7 +152,7 @@ def test_eigh_truncation_cap():
     Wa = torch.zeros(rows, cap, n, 2, dtype=torch.float64, device="cuda")
     rk = torch.zeros(rows, dtype=torch.int32, device="cuda")
     check(lib().ttn_test_eigh(eng._ctx, rows, n, cap, cap, 1e-10, Gd.data_ptr(), rows * n * n, Wi.data_ptr(),
-                              Wa.data_ptr(), rows * cap * n, rk.data_ptr()), eng._ctx)
+                              Wa.data_ptr(), rows * cap * n, rk.data_ptr(), None), eng._ctx)
     Wi, Wa = _host_complex(Wi), _host_complex(Wa)
     assert (rk.cpu().numpy() == cap).all()
     for t in range(rows):
