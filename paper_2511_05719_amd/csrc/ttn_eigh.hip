@@ -338,64 +338,279 @@ __global__ void __launch_bounds__(kThreads) k_jacobi(EighDesc d) {
   }
 }
 
-// Replay the rotation log onto a block of rows of V = I and write the factors
-// (single-block problems of size > 64).
-constexpr int kRowsPerBlock = 64;
-__global__ void __launch_bounds__(kThreads) k_jacobi_vectors(EighDesc d) {
-  extern __shared__ double2 smem[];
+// Kept eigenvectors of a single-block problem of size > 64 from the rotation
+// log.  V = J_1 J_2 ... J_S, so column c of V is J_1 (J_2 (... (J_S e_c))):
+// the log is replayed in reverse on the unit vectors of the kept columns
+// only.  Columns are independent, so each wavefront owns a few of them in
+// LDS and runs through the log with no workgroup barrier; lane j applies the
+// rotation of pair j of every step.
+constexpr int kVecWaves = 16;
+constexpr int kVecCols = 4;     // columns per wave: 16 x 4 = 64 >= kept count
+__global__ void __launch_bounds__(kVecWaves * 64) k_jacobi_vectors(EighDesc d) {
+  __shared__ double2 X[kVecWaves][kVecCols][128];
+  __shared__ int order_s[128];
+  __shared__ double lam_s[128];
   const int n = d.n;
   const int n2 = n + (n & 1);
   const int h = n2 / 2;
-  const int nblk = (n + kRowsPerBlock - 1) / kRowsPerBlock;
-  const long long t = blockIdx.x / nblk;
-  const int row_lo = (blockIdx.x % nblk) * kRowsPerBlock;
-  const int row_hi = min(n, row_lo + kRowsPerBlock);
-  const int nr = row_hi - row_lo;
-  double2* V = smem;                              // [nr][n2]
-  __shared__ double rc[64], rsx[64], rsy[64];
-  __shared__ int order_s[128];
-  __shared__ double lam_s[128];
-  for (int idx = threadIdx.x; idx < nr * n2; idx += blockDim.x) {
-    const int r = idx / n2, c = idx % n2;
-    V[idx] = make_double2((row_lo + r == c) ? 1.0 : 0.0, 0.0);
-  }
-  const int steps = d.nsteps[t];
-  const double* log = d.rot_log + t * (long long)d.max_steps * h * 3;
-  __syncthreads();
-  int s = 0;
-  for (int st = 0; st < steps; ++st) {
-    if (threadIdx.x < h) {
-      const double* e = log + ((long long)st * h + threadIdx.x) * 3;
-      rc[threadIdx.x] = e[0]; rsx[threadIdx.x] = e[1]; rsy[threadIdx.x] = e[2];
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < nr * h; idx += blockDim.x) {
-      const int r = idx / h, P = idx - (idx / h) * h;
-      const double c = rc[P];
-      const double2 sv = make_double2(rsx[P], rsy[P]);
-      if (c == 1.0 && sv.x == 0.0 && sv.y == 0.0) continue;
-      int p, q;
-      pair_of(n2, s, P, &p, &q);
-      const double2 vp = V[r * n2 + p], vq = V[r * n2 + q];
-      V[r * n2 + p] = csub(cscale(vp, c), cmul(cconj(sv), vq));
-      V[r * n2 + q] = cadd(cmul(sv, vp), cscale(vq, c));
-    }
-    if (++s == n2 - 1) s = 0;
-    __syncthreads();
-  }
+  const long long t = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int k = d.kept[t];
   for (int a = threadIdx.x; a < n; a += blockDim.x) {
     order_s[a] = d.order[t * n + a];
     lam_s[a] = d.lam_sorted[t * n + a];
   }
   __syncthreads();
-  const int k = d.kept[t];
+  const int steps = d.nsteps[t];
+  const double* log = d.rot_log + t * (long long)d.max_steps * h * 3;
   const double sc = d.scale_abs[t];
-  Problem pb;
-  pb.t = t; pb.k = 0; pb.n = n; pb.off = 0; pb.pad = d.new_pad; pb.pad_off = 0;
-  if (d.out_c128)
-    write_factors<double2>(d, pb, row_lo, row_hi, V, n2, order_s, lam_s, k, sc);
-  else
-    write_factors<float2>(d, pb, row_lo, row_hi, V, n2, order_s, lam_s, k, sc);
+  const bool c128 = d.out_c128 != 0;
+  const int per_pass = kVecWaves * kVecCols;
+  for (int base = 0; base < d.new_pad; base += per_pass) {
+    int ncol = 0;
+    for (int cc = 0; cc < kVecCols; ++cc) {
+      const int a = base + wave + cc * kVecWaves;
+      if (a < k) ncol = cc + 1;
+      for (int i = lane; i < n2; i += 64)
+        X[wave][cc][i] = make_double2((a < k && i == order_s[a]) ? 1.0 : 0.0, 0.0);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    if (ncol > 0 && lane < h) {
+      int s = (steps - 1) % (n2 - 1);
+      for (int st = steps - 1; st >= 0; --st) {
+        const double* e = log + ((long long)st * h + lane) * 3;
+        const double c = e[0];
+        const double2 sv = make_double2(e[1], e[2]);
+        if (!(c == 1.0 && sv.x == 0.0 && sv.y == 0.0)) {
+          int p, q;
+          pair_of(n2, s, lane, &p, &q);
+          for (int cc = 0; cc < ncol; ++cc) {
+            const double2 xp = X[wave][cc][p], xq = X[wave][cc][q];
+            X[wave][cc][p] = cadd(cscale(xp, c), cmul(sv, xq));
+            X[wave][cc][q] = csub(cscale(xq, c), cmul(cconj(sv), xp));
+          }
+        }
+        // the next (earlier) step touches entries other lanes just wrote
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        s = (s == 0) ? n2 - 2 : s - 1;
+      }
+    }
+    __syncthreads();
+    // W_iso[a][i] = V[i][order a] / s_a,  W_abs[a][i] = conj(V[i][order a]) s_a scale
+    const int rows = min(per_pass, d.new_pad - base);
+    for (int idx = threadIdx.x; idx < rows * n; idx += blockDim.x) {
+      const int al = idx / n, i = idx - (idx / n) * n;
+      const int a = base + al;
+      double2 wi = make_double2(0.0, 0.0), wa = make_double2(0.0, 0.0);
+      if (a < k) {
+        const double2 v = X[al % kVecWaves][al / kVecWaves][i];
+        const double sv = sqrt(lam_s[a]);
+        wi = cscale(v, 1.0 / sv);
+        wa = cscale(cconj(v), sv * sc);
+      }
+      const long long o = t * (long long)d.new_pad * n + (long long)a * n + i;
+      if (c128) {
+        ((double2*)d.W_iso)[o] = wi;
+        ((double2*)d.W_abs)[o] = wa;
+      } else {
+        ((float2*)d.W_iso)[o] = from_d2<float2>(wi);
+        ((float2*)d.W_abs)[o] = from_d2<float2>(wa);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Small problems (n <= 32): one wavefront per matrix, the full matrix and V
+// in LDS, several matrices per workgroup.  Every step's 2 x 2 blocks (P, Q)
+// over all P, Q partition the matrix, so the lanes update disjoint entries;
+// a wavefront's LDS operations complete in order, so consecutive steps need
+// no workgroup barrier.
+template <int NMAX>
+__global__ void __launch_bounds__(256) k_jacobi_wave(EighDesc d, long long nprob) {
+  constexpr int PER = 4;                       // wavefronts (matrices) per workgroup
+  __shared__ double2 Gs[PER][NMAX * NMAX];
+  __shared__ double2 Vs[PER][NMAX * NMAX];
+  __shared__ Rot rots[PER][NMAX / 2 > 0 ? NMAX / 2 : 1];
+  __shared__ double lam_s[PER][NMAX];
+  __shared__ int order_s[PER][NMAX];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long long bid = (long long)blockIdx.x * PER + wave;
+  if (bid >= nprob) return;                    // whole wavefront leaves; no workgroup barriers below
+  const Problem pb = problem_of(d, bid);
+  const long long t = pb.t;
+  const int n = pb.n;
+  const int n2 = n + (n & 1);
+  const int h = n2 / 2;
+  double2* G = Gs[wave];
+  double2* V = Vs[wave];
+  const double2* Gg = d.G + t * (long long)d.n * d.n;
+  for (int idx = lane; idx < n2 * n2; idx += 64) {
+    const int i = idx / n2, j = idx - (idx / n2) * n2;
+    G[idx] = (i < n && j < n) ? Gg[(long long)(pb.off + i) * d.n + pb.off + j] : make_double2(0.0, 0.0);
+    V[idx] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  double part = 0.0;
+  for (int i = lane; i < d.n; i += 64) part += Gg[(long long)i * d.n + i].x;
+  for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+  const double tr = part;
+  const bool finite = isfinite(tr) && tr > 0.0;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  int sweeps_done = 0;
+  if (n2 >= 2 && finite) {
+    for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+      bool rotated = false;
+      for (int s = 0; s < n2 - 1; ++s) {
+        bool mine = false;
+        if (lane < h) {
+          int p, q;
+          pair_of(n2, s, lane, &p, &q);
+          const double a = G[p * n2 + p].x, dd = G[q * n2 + q].x;
+          const double2 b = G[p * n2 + q];
+          const double ab = sqrt(cabs2(b));
+          Rot r;
+          r.c = 1.0; r.s = make_double2(0.0, 0.0); r.delta = 0.0;
+          if (ab > 1e-15 * sqrt(fabs(a * dd)) && ab > 1e-16 * tr && ab > 0.0) {
+            const double th = (dd - a) / (2.0 * ab);
+            const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+            const double c = 1.0 / sqrt(1.0 + tt * tt);
+            const double sn = tt * c;
+            r.c = c;
+            r.s = make_double2(sn * b.x / ab, sn * b.y / ab);
+            r.delta = tt * ab;
+            mine = true;
+          }
+          rots[wave][lane] = r;
+        }
+        rotated |= __any(mine);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        // G <- J^H G J over every 2x2 block (P, Q)
+        for (int idx = lane; idx < h * h; idx += 64) {
+          const int P = idx / h, Q = idx - (idx / h) * h;
+          const Rot rP = rots[wave][P], rQ = rots[wave][Q];
+          if (rP.delta == 0.0 && rQ.delta == 0.0) continue;
+          int p, q, pp, qq;
+          pair_of(n2, s, P, &p, &q);
+          pair_of(n2, s, Q, &pp, &qq);
+          if (P == Q) {
+            G[p * n2 + p] = make_double2(G[p * n2 + p].x - rP.delta, 0.0);
+            G[q * n2 + q] = make_double2(G[q * n2 + q].x + rP.delta, 0.0);
+            G[p * n2 + q] = make_double2(0.0, 0.0);
+            G[q * n2 + p] = make_double2(0.0, 0.0);
+            continue;
+          }
+          const double2 g00 = G[p * n2 + pp], g01 = G[p * n2 + qq];
+          const double2 g10 = G[q * n2 + pp], g11 = G[q * n2 + qq];
+          const double2 sQc = cconj(rQ.s);
+          const double2 x00 = csub(cscale(g00, rQ.c), cmul(g01, sQc));
+          const double2 x01 = cadd(cmul(g00, rQ.s), cscale(g01, rQ.c));
+          const double2 x10 = csub(cscale(g10, rQ.c), cmul(g11, sQc));
+          const double2 x11 = cadd(cmul(g10, rQ.s), cscale(g11, rQ.c));
+          const double2 sPc = cconj(rP.s);
+          G[p * n2 + pp] = csub(cscale(x00, rP.c), cmul(rP.s, x10));
+          G[p * n2 + qq] = csub(cscale(x01, rP.c), cmul(rP.s, x11));
+          G[q * n2 + pp] = cadd(cmul(sPc, x00), cscale(x10, rP.c));
+          G[q * n2 + qq] = cadd(cmul(sPc, x01), cscale(x11, rP.c));
+        }
+        // V <- V J
+        for (int idx = lane; idx < n2 * h; idx += 64) {
+          const int r = idx / h, P = idx - (idx / h) * h;
+          const Rot rP = rots[wave][P];
+          if (rP.delta == 0.0) continue;
+          int p, q;
+          pair_of(n2, s, P, &p, &q);
+          const double2 vp = V[r * n2 + p], vq = V[r * n2 + q];
+          V[r * n2 + p] = csub(cscale(vp, rP.c), cmul(cconj(rP.s), vq));
+          V[r * n2 + q] = cadd(cmul(rP.s, vp), cscale(vq, rP.c));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+      ++sweeps_done;
+      if (!rotated) break;
+    }
+  }
+  // eigenvalues, descending order, truncation
+  for (int i = lane; i < n; i += 64) {
+    const double l = G[i * n2 + i].x;
+    lam_s[wave][i] = (isfinite(l) && l > 0.0) ? l : 0.0;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (int i = lane; i < n; i += 64) {
+    int rk = 0;
+    const double li = lam_s[wave][i];
+    for (int j = 0; j < n; ++j) rk += (lam_s[wave][j] > li) || (lam_s[wave][j] == li && j < i);
+    order_s[wave][rk] = i;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  double mine = 0.0;
+  for (int i = 0; i < n; ++i) mine += lam_s[wave][i];
+  const double tot = d.blocks > 1 ? tr : mine;
+  int k = 0;
+  double kept = 0.0;
+  const int lim = min(min(d.cap, pb.pad), n);
+  if (finite && tot > 0.0)
+    while (k < lim && lam_s[wave][order_s[wave][k]] > d.cutoff * tot) { kept += lam_s[wave][order_s[wave][k]]; ++k; }
+  double scale;
+  if (d.blocks > 1) {
+    scale = finite ? 1.0 / sqrt(tr) : 0.0;
+  } else if (!(kept > 0.0) || !isfinite(kept)) {
+    k = 0;
+    scale = 0.0;
+  } else {
+    scale = 1.0 / sqrt(kept);
+  }
+  if (lane == 0) {
+    if (d.blocks > 1) {
+      if (!finite && d.flags) atomicOr(d.flags + t, 1);
+      if (d.disc_acc && tot > 0.0) atomicAdd(d.disc_acc + t, (mine - kept) / tot);
+    } else {
+      if (k == 0 && d.flags) d.flags[t] |= 1;
+      if (d.disc_acc && tot > 0.0) d.disc_acc[t] += (tot - kept) / tot;
+      if (d.degen_acc && k > 0 && k < n) {
+        const double lk1 = lam_s[wave][order_s[wave][k - 1]], lk = lam_s[wave][order_s[wave][k]];
+        if (lk > d.cutoff * tot && lk1 - lk <= 1e-6 * lk1) d.degen_acc[t] += 1;
+      }
+      if (d.rank_out) d.rank_out[t * d.rank_stride] = k;
+      if (d.rank_max) d.rank_max[t * d.rank_stride] = max(d.rank_max[t * d.rank_stride], k);
+    }
+    if (d.flops_acc) {
+      int na = 0;
+      for (int i = 0; i < n; ++i) na += lam_s[wave][i] > 1e-15 * tot;
+      const double f = 36.0 * (double)na * na * na;
+      if (d.blocks > 1) atomicAdd(d.flops_acc + t, f);
+      else d.flops_acc[t] += f;
+    }
+    if (d.sweeps_out) d.sweeps_out[t] = sweeps_done;
+  }
+  // factors: own block rows, and zeros in the other block's columns
+  const int ncols = d.n;
+  for (int idx = lane; idx < pb.pad * n; idx += 64) {
+    const int a = idx / n, i = idx - (idx / n) * n;
+    double2 wi = make_double2(0.0, 0.0), wa = make_double2(0.0, 0.0);
+    if (a < k) {
+      const double2 v = V[i * n2 + order_s[wave][a]];
+      const double sv = sqrt(lam_s[wave][order_s[wave][a]]);
+      wi = cscale(v, 1.0 / sv);
+      wa = cscale(cconj(v), sv * scale);
+    }
+    const long long o = t * (long long)d.new_pad * ncols + (long long)(pb.pad_off + a) * ncols + pb.off + i;
+    if (d.out_c128) { ((double2*)d.W_iso)[o] = wi; ((double2*)d.W_abs)[o] = wa; }
+    else { ((float2*)d.W_iso)[o] = from_d2<float2>(wi); ((float2*)d.W_abs)[o] = from_d2<float2>(wa); }
+    if (d.blocks > 1) {
+      const long long o2 = t * (long long)d.new_pad * ncols + (long long)(pb.pad_off + a) * ncols +
+                           (1 - pb.k) * pb.n + i;
+      if (d.out_c128) { ((double2*)d.W_iso)[o2] = make_double2(0, 0); ((double2*)d.W_abs)[o2] = make_double2(0, 0); }
+      else { ((float2*)d.W_iso)[o2] = make_float2(0, 0); ((float2*)d.W_abs)[o2] = make_float2(0, 0); }
+    }
+  }
 }
 
 static bool g_attr_done = false;
@@ -408,12 +623,22 @@ hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st) {
   if (!g_attr_done) {
     hipFuncSetAttribute((const void*)k_jacobi<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
     hipFuncSetAttribute((const void*)k_jacobi<false>, hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
-    hipFuncSetAttribute((const void*)k_jacobi_vectors, hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
     g_attr_done = true;
   }
   const int nsub = d.n / nb;
   const int n2 = nsub + (nsub & 1);
   const size_t gbytes = (size_t)n2 * (n2 + 1) / 2 * sizeof(double2);
+  const long long nprob = (long long)batch * nb;
+  // one wavefront per matrix pays off once there are enough matrices to give
+  // every SIMD of the chip a few of them; otherwise the workgroup kernel
+  // below spreads each matrix over 8 wavefronts
+  if (n2 <= 32 && nprob >= 4096) {
+    const unsigned grid = (unsigned)((nprob + 3) / 4);
+    if (n2 <= 8) hipLaunchKernelGGL(k_jacobi_wave<8>, dim3(grid), dim3(256), 0, st, d, nprob);
+    else if (n2 <= 16) hipLaunchKernelGGL(k_jacobi_wave<16>, dim3(grid), dim3(256), 0, st, d, nprob);
+    else hipLaunchKernelGGL(k_jacobi_wave<32>, dim3(grid), dim3(256), 0, st, d, nprob);
+    return hipGetLastError();
+  }
   if (n2 <= kVLdsMax) {
     const size_t bytes = gbytes + (size_t)n2 * n2 * sizeof(double2);
     hipLaunchKernelGGL(k_jacobi<true>, dim3((unsigned)((long long)batch * nb)), dim3(kThreads), bytes, st, d);
@@ -426,9 +651,7 @@ hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st) {
   hipLaunchKernelGGL(k_jacobi<false>, dim3(batch), dim3(kThreads), gbytes, st, d);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int nblk = (d.n + kRowsPerBlock - 1) / kRowsPerBlock;
-  const size_t vbytes = (size_t)kRowsPerBlock * n2 * sizeof(double2);
-  hipLaunchKernelGGL(k_jacobi_vectors, dim3((unsigned)((long long)batch * nblk)), dim3(kThreads), vbytes, st, d);
+  hipLaunchKernelGGL(k_jacobi_vectors, dim3((unsigned)batch), dim3(kVecWaves * 64), 0, st, d);
   return hipGetLastError();
 }
 
