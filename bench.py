@@ -145,23 +145,35 @@ def main():
     shots_per_s = shots / dt
     value = shots_per_s * ops
 
-    # roofline of the kernel class that took the most time
-    classes = {k: v for k, v in prof.items() if k != "other"}
-    dom = max(classes, key=lambda k: classes[k]["ms"])
+    # roofline of the kernel class that took the most time; achieved =
+    # algorithmic flops ledgered from the actual (unpadded) dimensions of
+    # every row / the class's summed launch durations (HIP events)
+    per_unit = {
+        "eigh": "36 n^3 real flops per n x n complex Hermitian eigen-decomposition with vectors, "
+                "n = actual bond dimension (non-zero Gram eigenvalues)",
+        "gram": "8 n^2 r real flops per Gram matrix (n = actual bond dimension, r = product of the other "
+                "two actual leg dimensions; per diagonal block in block-diagonal moves)",
+        "contract": "8 k n r real flops per factor product (k kept, n actual bond dimension, r = product "
+                    "of the other two actual leg dimensions)",
+    }
+    bound_of = {"contract": ("mfma", PEAK["fp32_mfma"]), "gram": ("mfma", PEAK["fp64_mfma"]),
+                "eigh_small": ("alu", PEAK["fp64_valu"]), "eigh_large": ("alu", PEAK["fp64_valu"])}
+    total_ms = max(sum(v["ms"] for v in prof.values()), 1e-9)
+    classes = {}
+    for k, (bound, peak) in bound_of.items():
+        v = prof[k]
+        ach = v["alg_flops"] / max(v["ms"] / 1e3, 1e-12)
+        classes[k] = {"share": v["ms"] / total_ms, "launches": v["launches"],
+                      "avg_ms": v["ms"] / max(v["launches"], 1), "achieved_tflops": ach / 1e12,
+                      "frac": ach / peak, "bound": bound}
+    dom = max(bound_of, key=lambda k: prof[k]["ms"])
     d = prof[dom]
-    avg_ms = d["ms"] / max(d["launches"], 1)
-    roof = {"kernel_class": dom, "launches": d["launches"], "avg_ms": avg_ms,
-            "share_of_gpu_time": d["ms"] / max(sum(v["ms"] for v in prof.values()), 1e-9)}
-    if dom.startswith("eigh"):
-        achieved = d["alg_flops"] / max(d["ms"] / 1e3, 1e-12)
-        roof.update({"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK["fp64_valu"] / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK["fp64_valu"], "traffic": None,
-                     "per_unit": "36 n^3 real flops per n x n complex Hermitian eigen-decomposition, "
-                                 "n = actual bond dimension"})
-    else:
-        roof.update({"bound": "mfma", "achieved": None, "peak": (PEAK["fp32_mfma"] if dom == "contract"
-                                                                 else PEAK["fp64_mfma"]) / 1e12,
-                     "unit": "TFLOP/s", "frac": None, "traffic": None})
+    bound, peak = bound_of[dom]
+    achieved = d["alg_flops"] / max(d["ms"] / 1e3, 1e-12)
+    roof = {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": None, "kernel_class": dom, "launches": d["launches"],
+            "avg_ms": d["ms"] / max(d["launches"], 1), "share_of_gpu_time": d["ms"] / total_ms,
+            "per_unit": per_unit["eigh" if dom.startswith("eigh") else dom]}
 
     plain = None
     if not args.no_plain:
@@ -199,9 +211,11 @@ def main():
         "plain_c128": plain,
         "speedup_vs_plain_c128": (shots_per_s * plain["s_per_shot"]) if plain else None,
         "kernel_time_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
+        "kernel_classes": classes,
         "run_stats": {"p_fail": p_fail, "max_rank": st.get("max_rank"),
                       "mean_discarded_weight": st.get("discarded_weight", 0.0) / args.batch,
-                      "hops_per_batch": st.get("hops"), "launches_per_batch": st.get("launches")},
+                      "hops_per_batch": st.get("hops"), "block_hops_per_batch": st.get("block_hops"),
+                      "launches_per_batch": st.get("launches")},
     }
     print(json.dumps(out))
 

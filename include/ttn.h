@@ -90,6 +90,7 @@ typedef struct {
   int64_t launches;          /* kernel launches enqueued */
   double gemm_flops;         /* real flops of the contraction GEMMs, padded shapes, whole batch */
   double gram_flops;         /* real flops of the FP64 Gram GEMMs, padded shapes, whole batch */
+  int64_t block_hops;        /* centre moves solved as two diagonal blocks (controlled-gate zip) */
 } ttn_stats;
 
 /* [sync] Validates the configuration and allocates the tensor pool and
@@ -232,12 +233,21 @@ ttn_status ttn_test_eigh(ttn_ctx* ctx, int32_t rows, int32_t n, int32_t new_pad,
 
 /* Profiling.  While enabled, every kernel launch of the context is
  * bracketed by HIP events on its stream, grouped by kernel class, and the
- * eigen-decomposition kernels add their algorithmic work to a per-row ledger
- * (36 n^3 real flops for an n x n complex Hermitian eigen-decomposition with
- * vectors, n = the actual number of non-zero eigenvalues).  Enabling resets
- * the counters.  ttn_profile_read [sync] returns, for one class, the summed
- * elapsed milliseconds, the number of launches and the ledgered flops (0 for
- * classes without a ledger). */
+ * algorithmic work of the launches is added to per-row ledgers from the
+ * actual (unpadded) dimensions of each row:
+ *   eigensolver   36 n^3 real flops for an n x n complex Hermitian
+ *                 eigen-decomposition with vectors, n = the number of
+ *                 non-zero eigenvalues;
+ *   Gram          8 n^2 r real flops (n as above, r = product of the other
+ *                 two actual leg dimensions), per diagonal block when the
+ *                 move is block diagonal;
+ *   contraction   8 k n r real flops for each of the two factor products
+ *                 (k = kept values).
+ * The Gram and contraction ledgers track the actual leg dimensions from the
+ * last state reset (ttn_init_product, or the start of a run) on: enable
+ * profiling before it.  Enabling resets the counters.  ttn_profile_read
+ * [sync] returns, for one class, the summed elapsed milliseconds, the number
+ * of launches and the ledgered flops (0 for classes without a ledger). */
 enum {
   TTN_CLASS_CONTRACT = 0,     /* c64/c128 leg contractions (MFMA)           */
   TTN_CLASS_GRAM = 1,         /* FP64 Gram matrices (MFMA)                  */

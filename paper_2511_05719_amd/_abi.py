@@ -32,7 +32,7 @@ class Stats(C.Structure):
     _fields_ = [("max_rank", C.c_int32), ("discarded_weight", C.c_double),
                 ("degenerate_cuts", C.c_int64), ("flagged_rows", C.c_int32),
                 ("hops", C.c_int64), ("launches", C.c_int64),
-                ("gemm_flops", C.c_double), ("gram_flops", C.c_double)]
+                ("gemm_flops", C.c_double), ("gram_flops", C.c_double), ("block_hops", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(kThreads) k_jacobi(EighDesc d) {
       if (d.rank_out) d.rank_out[t * d.rank_stride] = k;
       if (d.rank_max) d.rank_max[t * d.rank_stride] = max(d.rank_max[t * d.rank_stride], k);
     }
-    if (d.flops_acc) {
+    if (d.flops_acc || d.nk_out) {
       // algorithmic work of an n x n complex Hermitian eigen-decomposition
       // with vectors: 36 n^3 real flops (9 n^3 for the real symmetric case,
       // Golub & Van Loan, times 4 for complex arithmetic), n = the number of
@@ -310,8 +310,15 @@ __global__ void __launch_bounds__(kThreads) k_jacobi(EighDesc d) {
       int na = 0;
       for (int i = 0; i < n; ++i) na += lam[i] > 1e-15 * tot;
       const double f = 36.0 * (double)na * na * na;
-      if (d.blocks > 1) atomicAdd(d.flops_acc + t, f);
-      else d.flops_acc[t] += f;
+      if (d.flops_acc) {
+        if (d.blocks > 1) atomicAdd(d.flops_acc + t, f);
+        else d.flops_acc[t] += f;
+      }
+      if (d.nk_out) {
+        d.nk_out[t * 4 + 2 * pb.k] = na;
+        d.nk_out[t * 4 + 2 * pb.k + 1] = k;
+        if (d.blocks <= 1) { d.nk_out[t * 4 + 2] = 0; d.nk_out[t * 4 + 3] = 0; }
+      }
     }
     k_s = k;
     if (d.sweeps_out) d.sweeps_out[t] = sweeps_done;
@@ -581,12 +588,19 @@ __global__ void __launch_bounds__(256) k_jacobi_wave(EighDesc d, long long nprob
       if (d.rank_out) d.rank_out[t * d.rank_stride] = k;
       if (d.rank_max) d.rank_max[t * d.rank_stride] = max(d.rank_max[t * d.rank_stride], k);
     }
-    if (d.flops_acc) {
+    if (d.flops_acc || d.nk_out) {
       int na = 0;
       for (int i = 0; i < n; ++i) na += lam_s[wave][i] > 1e-15 * tot;
       const double f = 36.0 * (double)na * na * na;
-      if (d.blocks > 1) atomicAdd(d.flops_acc + t, f);
-      else d.flops_acc[t] += f;
+      if (d.flops_acc) {
+        if (d.blocks > 1) atomicAdd(d.flops_acc + t, f);
+        else d.flops_acc[t] += f;
+      }
+      if (d.nk_out) {
+        d.nk_out[t * 4 + 2 * pb.k] = na;
+        d.nk_out[t * 4 + 2 * pb.k + 1] = k;
+        if (d.blocks <= 1) { d.nk_out[t * 4 + 2] = 0; d.nk_out[t * 4 + 3] = 0; }
+      }
     }
     if (d.sweeps_out) d.sweeps_out[t] = sweeps_done;
   }

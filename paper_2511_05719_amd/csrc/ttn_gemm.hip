@@ -4,10 +4,11 @@
 //   * applying a small matrix W to one leg of a 3-leg node tensor
 //     T'[.., a, ..] = sum_i W[a][i] T[.., i, ..]            (absorb / isometrise)
 //   * the Gram matrix of one leg,  G[i][j] = sum_rest conj(T[..i..]) T[..j..]
-// Both are C[t,h][i][j] = sum_l op(A)[t,h][i][l] op(B)[t,h][l][j] with
-// per-operand element strides, a trajectory batch index t and an inner batch
-// index h, and a K index that may be split in two strided parts (l / Kin,
-// l % Kin) so the middle-leg Gram needs no transpose.
+// Both are C[t,g,h][i][j] = sum_l op(A)[t,g,h][i][l] op(B)[t,g,h][l][j]
+// with per-operand element strides, a trajectory batch index t, a block
+// index g (the two diagonal blocks of a block-diagonal problem), an inner
+// batch index h, and a K index that may be split in two strided parts
+// (l / Kin, l % Kin) so the middle-leg Gram needs no transpose.
 //
 // Tiling: a 256-thread workgroup (4 wave64) owns a 64 x 64 output tile; each
 // wave owns a 32 x 32 quadrant built from 2 x 2 MFMA 16x16x4 tiles.  A complex
@@ -59,15 +60,16 @@ __global__ void __launch_bounds__(256) k_zgemm(GemmDesc d) {
   const int wave = tid >> 6;
   const long long bx = blockIdx.x;
   const int tile_n = (int)(bx % d.tilesN);
-  const long long bh = bx / d.tilesN;            // flattened (t, h)
+  const long long bh = bx / d.tilesN;            // flattened (t, g, h)
   const int h = (int)(bh % d.H);
-  const long long t = bh / d.H;
+  const int g = (int)((bh / d.H) % d.G2);
+  const long long t = bh / ((long long)d.H * d.G2);
   const int tile_m = blockIdx.y;
   const int m0 = tile_m * TM, n0 = tile_n * TN;
 
-  const SA* A = (const SA*)d.A + t * d.sAt + h * d.sAh;
-  const SB* B = (const SB*)d.B + t * d.sBt + h * d.sBh;
-  SC* C = (SC*)d.C + t * d.sCt + h * d.sCh;
+  const SA* A = (const SA*)d.A + t * d.sAt + h * d.sAh + g * d.sAg;
+  const SB* B = (const SB*)d.B + t * d.sBt + h * d.sBh + g * d.sBg;
+  SC* C = (SC*)d.C + t * d.sCt + h * d.sCh + g * d.sCg;
   const R sgnA = d.conjA ? (R)-1 : (R)1;
   const R sgnB = d.conjB ? (R)-1 : (R)1;
 
@@ -164,7 +166,9 @@ hipError_t launch_zgemm_t(GemmDesc d, int batch, hipStream_t st) {
   if (d.M <= 0 || d.N <= 0 || batch <= 0) return hipSuccess;
   if (d.K <= 0) return hipErrorInvalidValue;
   if (d.Kin <= 0) d.Kin = d.K;
-  dim3 grid((unsigned)((long long)batch * d.H * d.tilesN), (unsigned)tilesM, 1);
+  if (d.G2 < 1) d.G2 = 1;
+  if (d.H < 1) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((long long)batch * d.G2 * d.H * d.tilesN), (unsigned)tilesM, 1);
   hipLaunchKernelGGL((k_zgemm<SA, SB, SC, R>), grid, dim3(256), 0, st, d);
   return hipGetLastError();
 }

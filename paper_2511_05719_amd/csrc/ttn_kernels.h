@@ -14,9 +14,11 @@ struct GemmDesc {
   void* C;
   int M, N, K, Kin;   // K index l = (l / Kin, l % Kin) with strides (l1, l2)
   int H;              // inner batch size (>= 1)
-  long long sAt, sAh, sAi, sAl1, sAl2;
-  long long sBt, sBh, sBl1, sBl2, sBj;
-  long long sCt, sCh, sCi, sCj;
+  int G2;             // block batch size (0 or 1: none; 2: the two diagonal
+                      // blocks of a block-diagonal operand, strides s?g)
+  long long sAt, sAh, sAi, sAl1, sAl2, sAg;
+  long long sBt, sBh, sBl1, sBl2, sBj, sBg;
+  long long sCt, sCh, sCi, sCj, sCg;
   int conjA, conjB;
   int a_m_fast, b_n_fast;   // operand dimension that is unit-stride on load
   int tilesN;               // filled by the launcher
@@ -55,6 +57,7 @@ struct EighDesc {
   int* kept;            // [batch]
   double* scale_abs;    // [batch]
   int* nsteps;          // [batch]
+  int* nk_out;          // [batch][4]: (non-zero eigenvalues, kept) of block 0, block 1 (may be null)
 };
 hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st);
 int eigh_max_sweeps();
@@ -143,6 +146,25 @@ hipError_t launch_fill_f64(double* p, double value, long long n, hipStream_t st)
 hipError_t launch_decode(const uint8_t* records, long long rec_stride, const int* data_rec, int n_data,
                          const uint32_t* check_masks /*[P] bitmask over data index*/, int n_checks,
                          const uint8_t* leader_parity /*[2^P]*/, uint8_t* fail, int batch, hipStream_t st);
+
+// Work ledger of the profiler: per-row actual leg dimensions adim[B][L][3]
+// (the padded shapes of the launches are upper bounds of these), updated
+// after every centre move and leg doubling, and the algorithmic flops of the
+// Gram and contraction launches computed from them.
+struct LedgerHop {
+  int* adim;
+  const int* nk;        // [B][4] written by the eigensolver (EighDesc::nk_out)
+  int L;
+  int x, lx, y, ly;     // centre moved from x (leg lx) to y (leg ly)
+  double* gram_acc;     // [B]
+  double* contract_acc; // [B]
+};
+hipError_t launch_ledger_hop(const LedgerHop& d, int batch, hipStream_t st);
+hipError_t launch_ledger_double(int* adim, int L, int node, int l0, int l1, int batch, hipStream_t st);
+hipError_t launch_ledger_reset(int* adim, int L, int batch, hipStream_t st);
+
+// out[c] = max over rows t of nk[t][c], c = 0..3 (one workgroup)
+hipError_t launch_nk_max(const int* nk, int batch, int* out, hipStream_t st);
 
 // uniform draws for tests
 hipError_t launch_philox_uniforms(uint64_t seed, uint64_t traj_offset, int n_draws, double* out, int batch,

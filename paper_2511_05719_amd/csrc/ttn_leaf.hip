@@ -331,6 +331,85 @@ hipError_t launch_init_product(const InitDesc& d, int batch, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------------ work ledger ----
+// adim[t][node][leg]: actual (unpadded) leg dimensions of row t.  The flops of
+// a centre move from x to y, with na_b non-zero Gram eigenvalues and k_b kept
+// values in block b (one block unless the move is block diagonal):
+//   Gram          8 sum_b na_b^2 rest_x
+//   contractions  8 sum_b k_b na_b (rest_x + rest_y)
+// where rest_x, rest_y are the products of the other two leg dimensions of x
+// and y (dense complex products, 8 real flops per complex multiply-add).
+__global__ void k_ledger_hop(LedgerHop d, int batch) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= batch) return;
+  int* ax = d.adim + ((long long)t * d.L + d.x) * 3;
+  int* ay = d.adim + ((long long)t * d.L + d.y) * 3;
+  const int* nk = d.nk + (long long)t * 4;
+  double rx = 1.0, ry = 1.0;
+  for (int l = 0; l < 3; ++l) {
+    if (l != d.lx) rx *= ax[l];
+    if (l != d.ly) ry *= ay[l];
+  }
+  const double na0 = nk[0], k0 = nk[1], na1 = nk[2], k1 = nk[3];
+  d.gram_acc[t] += 8.0 * (na0 * na0 + na1 * na1) * rx;
+  d.contract_acc[t] += 8.0 * (k0 * na0 + k1 * na1) * (rx + ry);
+  ax[d.lx] = nk[1] + nk[3];
+  ay[d.ly] = nk[1] + nk[3];
+}
+__global__ void k_ledger_double(int* adim, int L, int node, int l0, int l1, int batch) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= batch) return;
+  int* a = adim + ((long long)t * L + node) * 3;
+  a[l0] *= 2;
+  if (l1 >= 0) a[l1] *= 2;
+}
+__global__ void k_ledger_reset(int* adim, int L, int batch) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)batch * L * 3) return;
+  const int leg = (int)(i % 3);
+  const int node = (int)((i / 3) % L);
+  adim[i] = (node >= L / 2 && leg < 2) ? 2 : 1;
+}
+hipError_t launch_ledger_hop(const LedgerHop& d, int batch, hipStream_t st) {
+  if (batch <= 0) return hipSuccess;
+  if (d.x < 1 || d.x >= d.L || d.y < 1 || d.y >= d.L || d.lx < 0 || d.lx > 2 || d.ly < 0 || d.ly > 2)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ledger_hop, dim3((batch + 255) / 256), dim3(256), 0, st, d, batch);
+  return hipGetLastError();
+}
+hipError_t launch_ledger_double(int* adim, int L, int node, int l0, int l1, int batch, hipStream_t st) {
+  if (batch <= 0) return hipSuccess;
+  if (node < 1 || node >= L || l0 < 0 || l0 > 2 || l1 > 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ledger_double, dim3((batch + 255) / 256), dim3(256), 0, st, adim, L, node, l0, l1, batch);
+  return hipGetLastError();
+}
+hipError_t launch_ledger_reset(int* adim, int L, int batch, hipStream_t st) {
+  const long long n = (long long)batch * L * 3;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ledger_reset, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, adim, L, batch);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_nk_max(const int* nk, int batch, int* out) {
+  __shared__ int red[4][256];
+  int m[4] = {0, 0, 0, 0};
+  for (int t = threadIdx.x; t < batch; t += 256)
+    for (int c = 0; c < 4; ++c) m[c] = max(m[c], nk[(long long)t * 4 + c]);
+  for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = m[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = max(red[c][threadIdx.x], red[c][threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) out[threadIdx.x] = red[threadIdx.x][0];
+}
+hipError_t launch_nk_max(const int* nk, int batch, int* out, hipStream_t st) {
+  if (batch <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_nk_max, dim3(1), dim3(256), 0, st, nk, batch, out);
+  return hipGetLastError();
+}
+
 __global__ void k_fill_i32(int* p, int v, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;

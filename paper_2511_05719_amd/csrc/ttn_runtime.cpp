@@ -8,9 +8,12 @@
 // 2(i - L/2) and 2(i - L/2) + 1.  The root keeps an up leg of dimension 1
 // (instead of being absorbed into a child, Fig. 7), so every node is 3-leg.
 // All B rows of a node live in one buffer, row-major [B][a][b][u]; the leg
-// dimensions are padded to values known on the host (the per-row Schmidt
-// ranks are <= the padding and the padding is zero), so every launch has a
-// static shape and no device-to-host read-back is needed.
+// dimensions are padded to values the host knows (the per-row Schmidt ranks
+// are <= the padding and the padding is zero).  After each centre move's
+// eigen-decomposition the host reads one small record, the largest kept
+// count over the rows, and pads the new bond to exactly that: the shapes of
+// all launches follow the batch's actual ranks, which fall again after
+// measurements, instead of staying at their static bounds.
 //
 // Pool.  A node's buffer must hold its largest shape: two legs doubled while
 // a controlled gate's index rides on them.  Nodes with equal capacity share
@@ -87,7 +90,6 @@ struct ttn_ctx {
   int* nsteps = nullptr;
   int* rank_table = nullptr;   // [B][L] bond above node e
   int* rank_max = nullptr;     // [B][L] running maximum of rank_table
-  double* eigh_flops = nullptr;  // [B] algorithmic flops of the eigen-decompositions
   double* disc_acc = nullptr;  // [B]
   int* flags = nullptr;        // [B]
   int* degen_acc = nullptr;    // [B]
@@ -103,9 +105,14 @@ struct ttn_ctx {
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[TTN_NCLASS];
   size_t prof_used[TTN_NCLASS] = {0};
-  double* eigh_flops_cls[TTN_NCLASS] = {nullptr};   // device [B] ledgers of eigh classes
+  double* ledger[TTN_NCLASS] = {nullptr};   // device [B] algorithmic flops per class (or null)
+  double* ledger_mem = nullptr;             // [4][B]: eigh small, eigh large, Gram, contraction
+  int* adim = nullptr;                      // [B][L][3] actual leg dimensions (profiling)
+  int* nk = nullptr;                        // [B][4] eigensolver counts of the last move
+  int* nk_max = nullptr;                    // [4] their maxima over rows (device)
+  int* nk_host = nullptr;                   // [4] pinned host copy
   // stats
-  int64_t hops = 0, launches = 0;
+  int64_t hops = 0, launches = 0, block_hops = 0;
   double gemm_flops = 0.0, gram_flops = 0.0;
   std::string err;
 };
@@ -207,22 +214,26 @@ struct ProfScope {
 // -------------------------------------------------------- contractions ----
 // Largest element offset a GEMM operand can touch (host-side bounds check:
 // no launch is made whose indexing could leave its buffer).
-static long long extent(long long batch, long long sT, int H, long long sH, int M, long long sM, int K, int Kin,
-                        long long s1, long long s2) {
+static long long extent(long long batch, long long sT, int G2, long long sG, int H, long long sH, int M,
+                        long long sM, int K, int Kin, long long s1, long long s2) {
   const long long kq = (K - 1) / Kin, kr = (K >= Kin) ? Kin - 1 : K - 1;
-  return (batch - 1) * sT + (long long)(H - 1) * sH + (long long)(M - 1) * sM + kq * s1 + kr * s2 + 1;
+  return (batch - 1) * sT + (long long)(G2 - 1) * sG + (long long)(H - 1) * sH + (long long)(M - 1) * sM +
+         kq * s1 + kr * s2 + 1;
 }
 static bool gemm_fits(const GemmDesc& g, int batch, long long capA, long long capB, long long capC) {
   if (g.M < 1 || g.N < 1 || g.K < 1 || g.H < 1 || g.Kin < 1) return false;
-  const long long eA = extent(batch, g.sAt, g.H, g.sAh, g.M, g.sAi, g.K, g.Kin, g.sAl1, g.sAl2);
-  const long long eB = extent(batch, g.sBt, g.H, g.sBh, g.N, g.sBj, g.K, g.Kin, g.sBl1, g.sBl2);
-  const long long eC = (long long)(batch - 1) * g.sCt + (long long)(g.H - 1) * g.sCh +
+  const int G2 = std::max(g.G2, 1);
+  const long long eA = extent(batch, g.sAt, G2, g.sAg, g.H, g.sAh, g.M, g.sAi, g.K, g.Kin, g.sAl1, g.sAl2);
+  const long long eB = extent(batch, g.sBt, G2, g.sBg, g.H, g.sBh, g.N, g.sBj, g.K, g.Kin, g.sBl1, g.sBl2);
+  const long long eC = (long long)(batch - 1) * g.sCt + (long long)(G2 - 1) * g.sCg + (long long)(g.H - 1) * g.sCh +
                        (long long)(g.M - 1) * g.sCi + (long long)(g.N - 1) * g.sCj + 1;
   return eA <= capA && eB <= capB && eC <= capC;
 }
 
-// T'[.., a, ..] = sum_i W[a][i] T[.., i, ..] on leg `leg`, W: [rows][newd][n]
-static GemmDesc leg_desc(const void* T, std::array<int, 3> d, int leg, const void* W, int newd, void* out) {
+// T'[.., a, ..] = sum_i W[a][i] T[.., i, ..] on leg `leg`, W: [rows][wrows][n]
+// (rows a < newd <= wrows are used)
+static GemmDesc leg_desc(const void* T, std::array<int, 3> d, int leg, const void* W, int wrows, int newd,
+                         void* out) {
   const int n = d[leg];
   GemmDesc g{};
   g.H = 1;
@@ -232,19 +243,19 @@ static GemmDesc leg_desc(const void* T, std::array<int, 3> d, int leg, const voi
   const long long sO = elems(e);
   if (leg == 0) {
     const long long R = (long long)d[1] * d[2];
-    g.A = W; g.sAt = (long long)newd * n; g.sAi = n; g.sAl2 = 1; g.a_m_fast = 0;
+    g.A = W; g.sAt = (long long)wrows * n; g.sAi = n; g.sAl2 = 1; g.a_m_fast = 0;
     g.B = T; g.sBt = sT; g.sBl2 = R; g.sBj = 1; g.b_n_fast = 1;
     g.C = out; g.sCt = sO; g.sCi = R; g.sCj = 1;
     g.M = newd; g.N = (int)R; g.K = n;
   } else if (leg == 2) {
     const long long R = (long long)d[0] * d[1];
     g.A = T; g.sAt = sT; g.sAi = n; g.sAl2 = 1; g.a_m_fast = 0;
-    g.B = W; g.sBt = (long long)newd * n; g.sBl2 = 1; g.sBj = n; g.b_n_fast = 0;
+    g.B = W; g.sBt = (long long)wrows * n; g.sBl2 = 1; g.sBj = n; g.b_n_fast = 0;
     g.C = out; g.sCt = sO; g.sCi = newd; g.sCj = 1;
     g.M = (int)R; g.N = newd; g.K = n;
   } else {
     g.H = d[0];
-    g.A = W; g.sAt = (long long)newd * n; g.sAh = 0; g.sAi = n; g.sAl2 = 1; g.a_m_fast = 0;
+    g.A = W; g.sAt = (long long)wrows * n; g.sAh = 0; g.sAi = n; g.sAl2 = 1; g.a_m_fast = 0;
     g.B = T; g.sBt = sT; g.sBh = (long long)n * d[2]; g.sBl2 = d[2]; g.sBj = 1; g.b_n_fast = 1;
     g.C = out; g.sCt = sO; g.sCh = (long long)newd * d[2]; g.sCi = d[2]; g.sCj = 1;
     g.M = newd; g.N = d[2]; g.K = n;
@@ -281,28 +292,76 @@ static GemmDesc gram_desc(const void* T, std::array<int, 3> d, int leg, double2*
   return g;
 }
 
+// Block-diagonal moves (two independent halves of the bond, Sec. III.B
+// zip): the Gram matrix is needed only on its two diagonal blocks and both
+// factor matrices are block diagonal, so every product splits into two
+// half-size products (here on the block index g).
+static void gram_split(GemmDesc& g) {
+  const int h = g.M / 2;
+  g.G2 = 2;
+  g.sAg = h * g.sAi;
+  g.sBg = h * g.sBj;
+  g.sCg = h * (g.sCi + g.sCj);
+  g.M = h;
+  g.N = h;
+}
 static long long buf_elems(const ttn_ctx* ctx, int b) { return (long long)(ctx->bufs[b].bytes / ctx->es); }
 static long long ws_elems(const ttn_ctx* ctx) { return (long long)ctx->B * ctx->nmax * ctx->nmax; }
 
-static ttn_status leg_apply(ttn_ctx* ctx, int src_buf, std::array<int, 3> d, int leg, const void* W, int newd,
-                            int dst_buf) {
-  GemmDesc g = leg_desc(ctx->bufs[src_buf].p, d, leg, W, newd, ctx->bufs[dst_buf].p);
+static inline void* offset_ptr(const void* p, long long elems, size_t es) {
+  return (void*)((const char*)p + elems * (long long)es);
+}
+
+// T' = W applied on leg `leg` of the node in src_buf, written to dst_buf with
+// that leg of dimension newd.  W is [rows][wrows][n].  blocks = 2: W is block
+// diagonal with diagonal blocks [wrows/2][n/2]; block b contributes kb[b]
+// rows, placed at new indices [kb[0] * b, kb[0] * b + kb[b]) (newd = kb[0] + kb[1]).
+static ttn_status leg_apply(ttn_ctx* ctx, int src_buf, std::array<int, 3> d, int leg, const void* W, int wrows,
+                            int newd, int dst_buf, int blocks = 1, const int* kb = nullptr) {
+  const int n = d[leg];
   const bool wA = (leg != 2);
-  if (!gemm_fits(g, ctx->B, wA ? ws_elems(ctx) : buf_elems(ctx, src_buf), wA ? buf_elems(ctx, src_buf) : ws_elems(ctx),
-                 buf_elems(ctx, dst_buf)))
-    return fail(ctx, TTN_EINVAL, "internal: contraction exceeds its buffers");
-  ctx->gemm_flops += 8.0 * (double)g.M * g.N * g.K * g.H * ctx->B;
-  ++ctx->launches;
-  ProfScope ps(ctx, CLS_GEMM);
-  TTN_CHECK_HIP(launch_zgemm(g, ctx->B, ctx->c128 ? GEMM_C128 : GEMM_C64, ctx->st));
+  const long long capT = buf_elems(ctx, src_buf), capW = ws_elems(ctx), capC = buf_elems(ctx, dst_buf);
+  const int nb = blocks > 1 ? 2 : 1;
+  int off = 0;
+  for (int b = 0; b < nb; ++b) {
+    GemmDesc g = leg_desc(ctx->bufs[src_buf].p, d, leg, W, wrows, newd, ctx->bufs[dst_buf].p);
+    long long oT = 0, oW = 0, oC = 0;
+    if (nb == 2) {
+      const int rows_b = kb[b];
+      if (rows_b == 0) continue;
+      oW = (long long)b * (wrows / 2) * n + (long long)b * (n / 2);
+      if (leg == 2) {
+        oT = (long long)b * (n / 2) * g.sAl2;
+        oC = (long long)off * g.sCj;
+        g.N = rows_b;
+      } else {
+        oT = (long long)b * (n / 2) * g.sBl2;
+        oC = (long long)off * g.sCi;
+        g.M = rows_b;
+      }
+      g.K = n / 2;
+      g.Kin = g.K;
+      off += rows_b;
+      if (wA) { g.A = offset_ptr(g.A, oW, ctx->es); g.B = offset_ptr(g.B, oT, ctx->es); }
+      else { g.A = offset_ptr(g.A, oT, ctx->es); g.B = offset_ptr(g.B, oW, ctx->es); }
+      g.C = offset_ptr(g.C, oC, ctx->es);
+    }
+    if (!gemm_fits(g, ctx->B, wA ? capW - oW : capT - oT, wA ? capT - oT : capW - oW, capC - oC))
+      return fail(ctx, TTN_EINVAL, "internal: contraction exceeds its buffers");
+    ctx->gemm_flops += 8.0 * (double)g.M * g.N * g.K * g.H * ctx->B;
+    ++ctx->launches;
+    ProfScope ps(ctx, CLS_GEMM);
+    TTN_CHECK_HIP(launch_zgemm(g, ctx->B, ctx->c128 ? GEMM_C128 : GEMM_C64, ctx->st));
+  }
   return TTN_OK;
 }
 
-static ttn_status gram(ttn_ctx* ctx, int src_buf, std::array<int, 3> d, int leg) {
+static ttn_status gram(ttn_ctx* ctx, int src_buf, std::array<int, 3> d, int leg, int blocks = 1) {
   GemmDesc g = gram_desc(ctx->bufs[src_buf].p, d, leg, ctx->G);
+  if (blocks > 1) gram_split(g);
   if (!gemm_fits(g, ctx->B, buf_elems(ctx, src_buf), buf_elems(ctx, src_buf), ws_elems(ctx)))
     return fail(ctx, TTN_EINVAL, "internal: Gram exceeds its buffers");
-  ctx->gram_flops += 8.0 * (double)g.M * g.N * g.K * ctx->B;
+  ctx->gram_flops += 8.0 * (double)g.M * g.N * g.K * std::max(g.G2, 1) * ctx->B;
   ++ctx->launches;
   ProfScope ps(ctx, CLS_GRAM);
   TTN_CHECK_HIP(launch_zgemm(g, ctx->B, ctx->c128 ? GEMM_GRAM_C128 : GEMM_GRAM_C64, ctx->st));
@@ -313,6 +372,19 @@ static ttn_status gram(ttn_ctx* ctx, int src_buf, std::array<int, 3> d, int leg)
 // canonical form that makes local Schmidt values and Born probabilities
 // local): factor x = (x V S^-1)(S V^H) across the bond, keep the first factor
 // in x, absorb the second into y, truncating to `cap` values above `cutoff`.
+// The batch's kept counts of the last eigen-decomposition: kb[b] = the
+// largest number of values any row kept in block b.  The only device-to-host
+// read of a centre move: the new bond is padded to what some row uses, not to
+// its static bound, so padding never accumulates on bonds whose rank fell.
+static ttn_status read_kept(ttn_ctx* ctx, int kb[2]) {
+  TTN_CHECK_HIP(launch_nk_max(ctx->nk, ctx->B, ctx->nk_max, ctx->st));
+  TTN_CHECK_HIP(hipMemcpyAsync(ctx->nk_host, ctx->nk_max, 4 * sizeof(int), hipMemcpyDeviceToHost, ctx->st));
+  TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
+  kb[0] = ctx->nk_host[1];
+  kb[1] = ctx->nk_host[3];
+  return TTN_OK;
+}
+
 static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int new_pad, int blocks = 1) {
   const int lx = leg_toward(x, y), ly = leg_toward(y, x);
   const int e = bond_node(x, y);
@@ -321,7 +393,8 @@ static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int ne
   if (n != dy[ly]) return fail(ctx, TTN_EINVAL, "internal: bond dimension mismatch");
   if (n > ctx->nmax || new_pad > ctx->nmax)
     return fail(ctx, TTN_EINVAL, "internal: bond dimension exceeds workspace");
-  TTN_TRY(gram(ctx, ctx->node_buf[x], dx, lx));
+  if (blocks > 1 && ((n & 1) || (new_pad & 1))) return fail(ctx, TTN_EINVAL, "internal: odd block size");
+  TTN_TRY(gram(ctx, ctx->node_buf[x], dx, lx, blocks));
   EighDesc ed{};
   ed.G = ctx->G; ed.n = n; ed.new_pad = new_pad; ed.cap = cap; ed.cutoff = cutoff;
   ed.W_iso = ctx->Wi; ed.W_abs = ctx->Wa; ed.out_c128 = ctx->c128;
@@ -330,27 +403,46 @@ static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int ne
   ed.rank_max = blocks > 1 ? nullptr : ctx->rank_max + e;
   ed.rank_stride = ctx->L;
   const bool large = (n / blocks + ((n / blocks) & 1)) > 64;
-  ed.flops_acc = ctx->eigh_flops_cls[large ? CLS_EIGH_LARGE : CLS_EIGH_SMALL];
+  ed.flops_acc = ctx->ledger[large ? CLS_EIGH_LARGE : CLS_EIGH_SMALL];
   ed.disc_acc = ctx->disc_acc; ed.flags = ctx->flags; ed.degen_acc = ctx->degen_acc;
   ed.rot_log = ctx->rot_log; ed.max_steps = ctx->max_steps; ed.lam_sorted = ctx->lam_sorted;
   ed.order = ctx->order; ed.kept = ctx->kept; ed.scale_abs = ctx->scale_abs; ed.nsteps = ctx->nsteps;
+  ed.nk_out = ctx->nk;
   ctx->launches += large ? 2 : 1;
   {
     ProfScope ps(ctx, large ? CLS_EIGH_LARGE : CLS_EIGH_SMALL);
     TTN_CHECK_HIP(launch_eigh(ed, ctx->B, ctx->st));
   }
+  int kb[2];
+  TTN_TRY(read_kept(ctx, kb));
+  if (kb[0] < 0 || kb[1] < 0 || kb[0] + kb[1] > new_pad || (blocks > 1 && std::max(kb[0], kb[1]) > new_pad / 2))
+    return fail(ctx, TTN_EDEVICE, "internal: kept count out of range");
+  int newd = blocks > 1 ? kb[0] + kb[1] : kb[0];
+  if (newd == 0) {             // every row lost its norm (flagged): keep one zero column
+    newd = 1;
+    kb[0] = 1;
+  }
   const int bx = acquire(ctx, ctx->node_cls[x]);
   if (bx < 0) return fail(ctx, TTN_EINVAL, "internal: pool exhausted");
-  TTN_TRY(leg_apply(ctx, ctx->node_buf[x], dx, lx, ctx->Wi, new_pad, bx));
+  TTN_TRY(leg_apply(ctx, ctx->node_buf[x], dx, lx, ctx->Wi, new_pad, newd, bx, blocks, kb));
   adopt(ctx, x, bx);
   const int by = acquire(ctx, ctx->node_cls[y]);
   if (by < 0) return fail(ctx, TTN_EINVAL, "internal: pool exhausted");
-  TTN_TRY(leg_apply(ctx, ctx->node_buf[y], dy, ly, ctx->Wa, new_pad, by));
+  TTN_TRY(leg_apply(ctx, ctx->node_buf[y], dy, ly, ctx->Wa, new_pad, newd, by, blocks, kb));
   adopt(ctx, y, by);
-  ctx->dims[x][lx] = new_pad;
-  ctx->dims[y][ly] = new_pad;
+  ctx->dims[x][lx] = newd;
+  ctx->dims[y][ly] = newd;
   ctx->centre = y;
   ++ctx->hops;
+  if (blocks > 1) ++ctx->block_hops;
+  if (ctx->prof) {
+    LedgerHop lh{};
+    lh.adim = ctx->adim; lh.nk = ctx->nk; lh.L = ctx->L;
+    lh.x = x; lh.lx = lx; lh.y = y; lh.ly = ly;
+    lh.gram_acc = ctx->ledger[CLS_GRAM];
+    lh.contract_acc = ctx->ledger[CLS_GEMM];
+    TTN_CHECK_HIP(launch_ledger_hop(lh, ctx->B, ctx->st));
+  }
   return TTN_OK;
 }
 
@@ -412,6 +504,11 @@ static LeafOp leaf_op(int kind, int leg) {
 }
 
 // ----------------------------------------------------- controlled gate ----
+// Zip moves across bonds of at least this (doubled) dimension are solved as
+// two diagonal blocks; below it one dense solve costs less than the extra
+// launches.
+constexpr int kBlockMin = 16;
+
 // g = sum_k P_k (x) B_k with P_k = |v_k><v_k| orthogonal projectors on the
 // `start` qubit.  The start node gets its up bond doubled into (k, u) with
 // block k = P_k applied; the index k then rides along the tree path
@@ -449,6 +546,7 @@ static ttn_status controlled_gate(ttn_ctx* ctx, int qs, const double P[2][2][2][
     TTN_CHECK_HIP(launch_extend(x, ctx->B, ctx->st));
     adopt(ctx, ns, b);
     ctx->dims[ns][2] *= 2;
+    if (ctx->prof) TTN_CHECK_HIP(launch_ledger_double(ctx->adim, ctx->L, ns, 2, -1, ctx->B, ctx->st));
   }
   for (int i = 0; i < m; ++i) {
     const int x = path[i], y = path[i + 1];
@@ -482,11 +580,13 @@ static ttn_status controlled_gate(ttn_ctx* ctx, int qs, const double P[2][2][2][
     }
     adopt(ctx, y, b);
     ctx->dims[y] = e;
+    if (ctx->prof)
+      TTN_CHECK_HIP(launch_ledger_double(ctx->adim, ctx->L, y, ex.leg_in, ex.leg_out, ctx->B, ctx->st));
     // exact move across (x, y): the bond can hold the near side's full space
     const int n = ctx->dims[x][leg_toward(x, y)];
     const int qnear = (y == x / 2) ? ctx->nq_below[x] : ctx->N - ctx->nq_below[y];
     const long long near_dim = qnear >= 30 ? (1ll << 30) : (1ll << qnear);
-    if (n >= 64 && near_dim >= n) {
+    if (n >= kBlockMin) {
       // the Gram matrix is block diagonal in k: two independent halves
       TTN_TRY(hop(ctx, x, y, ctx->cutoff, n / 2, n, 2));
     } else {
@@ -558,7 +658,7 @@ static ttn_status reset_state(ttn_ctx* ctx, const uint8_t* basis) {
   ctx->centre = 1;
   TTN_CHECK_HIP(launch_fill_i32(ctx->rank_table, 1, (long long)ctx->B * ctx->L, ctx->st));
   TTN_CHECK_HIP(launch_fill_i32(ctx->rank_max, 1, (long long)ctx->B * ctx->L, ctx->st));
-  TTN_CHECK_HIP(launch_fill_f64(ctx->eigh_flops, 0.0, 2ll * ctx->B, ctx->st));
+  TTN_CHECK_HIP(launch_ledger_reset(ctx->adim, ctx->L, ctx->B, ctx->st));
   TTN_CHECK_HIP(launch_fill_i32(ctx->flags, 0, ctx->B, ctx->st));
   TTN_CHECK_HIP(launch_fill_i32(ctx->degen_acc, 0, ctx->B, ctx->st));
   TTN_CHECK_HIP(launch_fill_f64(ctx->disc_acc, 0.0, ctx->B, ctx->st));
@@ -590,6 +690,7 @@ static ttn_status fill_stats(ttn_ctx* ctx, ttn_stats* st) {
   st->launches = ctx->launches;
   st->gemm_flops = ctx->gemm_flops;
   st->gram_flops = ctx->gram_flops;
+  st->block_hops = ctx->block_hops;
   return TTN_OK;
 }
 
@@ -599,7 +700,7 @@ static ttn_status run_oplist(ttn_ctx* ctx, const ttn_oplist* ol, const double* t
   if (!ol || ol->ctx != ctx) return fail(ctx, TTN_EINVAL, "op list belongs to another context");
   if (!records || !logp) return fail(ctx, TTN_EINVAL, "records and logp are required");
   if (ol->n_ad > 0 && !branches && !forced_br) return fail(ctx, TTN_EINVAL, "branches required (AD ops)");
-  ctx->hops = 0; ctx->launches = 0; ctx->gemm_flops = 0.0; ctx->gram_flops = 0.0;
+  ctx->hops = 0; ctx->launches = 0; ctx->block_hops = 0; ctx->gemm_flops = 0.0; ctx->gram_flops = 0.0;
   TTN_TRY(reset_state(ctx, nullptr));
   TTN_CHECK_HIP(launch_fill_f64(logp, 0.0, ctx->B, ctx->st));
   LeafBatch& r = ctx->run;
@@ -775,9 +876,18 @@ ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {
   ok &= hipMalloc((void**)&ctx->nsteps, Bz * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->rank_table, Bz * L * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->rank_max, Bz * L * sizeof(int)) == hipSuccess;
-  ok &= hipMalloc((void**)&ctx->eigh_flops, 2 * Bz * sizeof(double)) == hipSuccess;
-  ctx->eigh_flops_cls[CLS_EIGH_SMALL] = ctx->eigh_flops;
-  ctx->eigh_flops_cls[CLS_EIGH_LARGE] = ctx->eigh_flops + Bz;
+  ok &= hipMalloc((void**)&ctx->ledger_mem, 4 * Bz * sizeof(double)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->adim, Bz * L * 3 * sizeof(int)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->nk, Bz * 4 * sizeof(int)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->nk_max, 4 * sizeof(int)) == hipSuccess;
+  ok &= hipHostMalloc((void**)&ctx->nk_host, 4 * sizeof(int), hipHostMallocDefault) == hipSuccess;
+  if (ok) {
+    ctx->ledger[CLS_EIGH_SMALL] = ctx->ledger_mem;
+    ctx->ledger[CLS_EIGH_LARGE] = ctx->ledger_mem + Bz;
+    ctx->ledger[CLS_GRAM] = ctx->ledger_mem + 2 * Bz;
+    ctx->ledger[CLS_GEMM] = ctx->ledger_mem + 3 * Bz;
+    ok &= launch_fill_f64(ctx->ledger_mem, 0.0, 4ll * ctx->B, ctx->st) == hipSuccess;
+  }
   ok &= hipMalloc((void**)&ctx->disc_acc, Bz * sizeof(double)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->flags, Bz * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->degen_acc, Bz * sizeof(int)) == hipSuccess;
@@ -798,11 +908,13 @@ ttn_status ttn_destroy(ttn_ctx* ctx) {
       hipEventDestroy(e.second);
     }
   void* ws[] = {ctx->G, ctx->Wi, ctx->Wa, ctx->rot_log, ctx->lam_sorted, ctx->order, ctx->kept,
-                ctx->scale_abs, ctx->nsteps, ctx->rank_table, ctx->rank_max, ctx->eigh_flops,
+                ctx->scale_abs, ctx->nsteps, ctx->rank_table, ctx->rank_max, ctx->ledger_mem,
+                ctx->adim, ctx->nk, ctx->nk_max,
                 ctx->disc_acc, ctx->flags,
                 ctx->degen_acc, ctx->leader, ctx->dec_datarec, ctx->dec_masks};
   for (void* p : ws)
     if (p) hipFree(p);
+  if (ctx->nk_host) hipHostFree(ctx->nk_host);
   delete ctx;
   return TTN_OK;
 }
@@ -1192,7 +1304,7 @@ ttn_status ttn_profile_enable(ttn_ctx* ctx, int32_t on) {
   TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
   ctx->prof = on != 0;
   for (int c = 0; c < TTN_NCLASS; ++c) ctx->prof_used[c] = 0;
-  TTN_CHECK_HIP(launch_fill_f64(ctx->eigh_flops, 0.0, 2ll * ctx->B, ctx->st));
+  TTN_CHECK_HIP(launch_fill_f64(ctx->ledger_mem, 0.0, 4ll * ctx->B, ctx->st));
   return TTN_OK;
 }
 
@@ -1209,9 +1321,9 @@ ttn_status ttn_profile_read(ttn_ctx* ctx, int32_t cls, double* ms, int64_t* laun
   *ms = tot;
   *launches = (int64_t)ctx->prof_used[cls];
   *alg_flops = 0.0;
-  if (ctx->eigh_flops_cls[cls]) {
+  if (ctx->ledger[cls]) {
     std::vector<double> f(ctx->B);
-    TTN_CHECK_HIP(hipMemcpy(f.data(), ctx->eigh_flops_cls[cls], ctx->B * sizeof(double), hipMemcpyDeviceToHost));
+    TTN_CHECK_HIP(hipMemcpy(f.data(), ctx->ledger[cls], ctx->B * sizeof(double), hipMemcpyDeviceToHost));
     for (double v : f) *alg_flops += v;
   }
   return TTN_OK;
@@ -1233,7 +1345,7 @@ ttn_status ttn_test_leg_apply(ttn_ctx* ctx, int32_t rows, const int32_t* dims3, 
     return fail(ctx, TTN_EINVAL, "bad arguments");
   std::array<int, 3> d{dims3[0], dims3[1], dims3[2]};
   if (d[0] < 1 || d[1] < 1 || d[2] < 1) return fail(ctx, TTN_EINVAL, "bad dims");
-  GemmDesc g = leg_desc(T, d, leg, W, newd, out);
+  GemmDesc g = leg_desc(T, d, leg, W, newd, newd, out);
   const bool wA = (leg != 2);
   if (!gemm_fits(g, rows, wA ? w_elems : t_elems, wA ? t_elems : w_elems, out_elems))
     return fail(ctx, TTN_EINVAL, "buffers too small for the contraction");
@@ -1272,6 +1384,7 @@ ttn_status ttn_test_eigh(ttn_ctx* ctx, int32_t rows, int32_t n, int32_t new_pad,
   ed.rank_out = rank; ed.rank_stride = 1;
   ed.rot_log = ctx->rot_log; ed.max_steps = ctx->max_steps; ed.lam_sorted = ctx->lam_sorted;
   ed.order = ctx->order; ed.kept = ctx->kept; ed.scale_abs = ctx->scale_abs; ed.nsteps = ctx->nsteps;
+  ed.nk_out = ctx->prof ? ctx->nk : nullptr;
   TTN_CHECK_HIP(launch_eigh(ed, rows, ctx->st));
   TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
   return TTN_OK;

@@ -182,3 +182,49 @@ def test_single_op_entry_points():
     assert np.array_equal(b2.cpu().numpy(), ref.records[:, 1])
     assert np.abs(logp.cpu().numpy() - ref.logp).max() < 1e-10
     eng.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_block_diagonal_zip_moves(dtype):
+    # 14 qubits on 16 leaves: the root bond (8 | 6 qubits) reaches 64, so a
+    # controlled gate across it rides a 128-wide bond that is solved as two
+    # diagonal blocks (block-split Gram, eigensolver and both contractions);
+    # chi = 64 bounds every bond of this tree, so the run is untruncated.
+    g = np.random.default_rng(21)
+    nq = 14
+    prog = random_program(nq, 14, g, noise=("srx",), measure_every=5)[:-nq]
+    circ = custom_circuit(nq, prog)
+    rows = 3
+    th = g.uniform(0.1, 1.2, (rows, circ.n_loc))
+    eng = _engine(circ, rows, dtype, seed=5)
+    res = eng.run_circuit(eng.upload(circ), theta=th, gamma=0.0)
+    assert res.stats["block_hops"] > 0
+    ref_res, st = sv.run(circ, th, 0.0, 5, np.arange(rows), stop_after_op=circ.n_ops - 1)
+    full = st.full_state(nq)
+    if circ.n_rec:
+        assert np.array_equal(res.records.cpu().numpy(), ref_res.records)
+    tol = _amp_tol(dtype, res.stats["discarded_weight"])
+    for r in range(rows):
+        amp = eng.statevector(r)
+        assert np.abs(amp - full[r]).max() < tol, (r, np.abs(amp - full[r]).max())
+    eng.close()
+
+
+def test_profile_ledger_bounded_by_executed_work():
+    # the algorithmic flops ledgered from actual dimensions never exceed the
+    # flops of the padded launches, and every hot class has a ledger
+    circ = build_circuit(3, 1, "srx")
+    rows = 64
+    eng = _engine(circ, rows, "c64", cutoff=1e-10, seed=0)
+    ol = eng.upload(circ)
+    eng.profile(True)
+    res = eng.run_circuit(ol, theta=0.05, gamma=0.0)
+    prof = eng.profile_read()
+    eng.profile(False)
+    st = res.stats
+    assert prof["gram"]["launches"] > 0 and prof["contract"]["launches"] > 0
+    assert 0 < prof["gram"]["alg_flops"] <= st["gram_flops"] * (1 + 1e-12)
+    assert 0 < prof["contract"]["alg_flops"] <= st["gemm_flops"] * (1 + 1e-12)
+    assert prof["eigh_small"]["alg_flops"] + prof["eigh_large"]["alg_flops"] > 0
+    assert all(v["ms"] >= 0 for v in prof.values())
+    eng.close()
