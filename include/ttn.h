@@ -216,7 +216,9 @@ double ttn_philox_uniform_host(uint64_t seed, uint64_t traj, uint64_t draw);
  *  ttn_test_leg_apply: out[t][..a..] = sum_i W[t][a][i] T[t][..i..] on leg
  *    `leg` (0, 1, 2) of T [rows][d0][d1][d2]; W [rows][newd][n], n = d[leg].
  *  ttn_test_gram: G[t][i][j] = sum over the other legs of
- *    conj(T[..i..]) T[..j..], G float64 [rows][n][n][2] (FP64 accumulation).
+ *    conj(T[..i..]) T[..j..], G float64 [ksplit][rows][n][n][2] (FP64
+ *    accumulation): with ksplit > 1 the sum runs in ksplit parts, one per
+ *    slice, and G is the sum of the slices.
  *  ttn_test_eigh: the factors of a centre move computed from G (as in
  *    ttn_ctx's hops): W_iso[t][a][i] = V[i][a] / s_a, W_abs[t][a][i] =
  *    conj(V[i][a]) s_a / |s_kept|, a < rank[t] in descending s, zero beyond;
@@ -226,7 +228,7 @@ ttn_status ttn_test_leg_apply(ttn_ctx* ctx, int32_t rows, const int32_t* dims3, 
                               int64_t t_elems, const void* W, int64_t w_elems, int32_t newd, void* out,
                               int64_t out_elems);
 ttn_status ttn_test_gram(ttn_ctx* ctx, int32_t rows, const int32_t* dims3, int32_t leg, const void* T,
-                         int64_t t_elems, double* G, int64_t g_elems);
+                         int64_t t_elems, double* G, int64_t g_elems, int32_t ksplit);
 ttn_status ttn_test_eigh(ttn_ctx* ctx, int32_t rows, int32_t n, int32_t new_pad, int32_t cap, double cutoff,
                          const double* G, int64_t g_elems, void* W_iso, void* W_abs, int64_t w_elems,
                          int32_t* rank, int32_t* sweeps);

@@ -32,7 +32,8 @@ namespace ttn {
 
 constexpr int kMaxSweeps = 24;
 constexpr int kVLdsMax = 64;
-constexpr int kThreads = 512;
+constexpr int kThreadsSmall = 512;    // n <= 64: G and V in LDS
+constexpr int kThreadsLarge = 1024;   // n > 64: G alone fills the LDS, one workgroup per CU
 int eigh_max_sweeps() { return kMaxSweeps; }
 
 __device__ inline int pidx(int i, int j, int n) {   // packed upper triangle, i <= j
@@ -58,6 +59,14 @@ __device__ inline void pair_of(int n, int s, int j, int* p, int* q) {
 }
 
 struct Rot { double c; double2 s; double delta; };
+
+// entry o of one row's Gram matrix: the sum of its partial products when the
+// Gram launch split its K range
+__device__ inline double2 gram_at(const EighDesc& d, const double2* G, long long o) {
+  double2 v = G[o];
+  for (int z = 1; z < d.gsplit; ++z) v = cadd(v, G[o + z * d.gslice]);
+  return v;
+}
 
 struct Problem {       // one diagonal block of one trajectory's matrix
   long long t;
@@ -115,8 +124,13 @@ __device__ void write_factors(const EighDesc& d, const Problem& pb, int row_lo, 
   }
 }
 
-template <bool kVinLds>
-__global__ void __launch_bounds__(kThreads) k_jacobi(EighDesc d) {
+// Convergence.  A pair is rotated while |g_pq| > tol sqrt(g_pp g_qq) (and
+// above 0.1 tol of the trace).  Cyclic Jacobi converges quadratically, so a
+// sweep whose largest rotated ratio |g_pq| / sqrt(g_pp g_qq) stayed below
+// sqrt(tol) / 4 leaves off-diagonal entries far below tol: the solver stops
+// after it instead of spending one more sweep to find nothing to rotate.
+template <bool kVinLds, int NT>
+__global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
   extern __shared__ double2 smem[];
   const Problem pb = problem_of(d, blockIdx.x);
   const long long t = pb.t;
@@ -131,8 +145,9 @@ __global__ void __launch_bounds__(kThreads) k_jacobi(EighDesc d) {
   __shared__ unsigned short blk[2080];                 // (P, Q) of the upper 2x2 blocks
   __shared__ double lam[128];
   __shared__ int order_s[128];
-  __shared__ double red[kThreads];
+  __shared__ double red[NT];
   __shared__ int any_rot;
+  __shared__ double sweep_ratio;
   __shared__ double trace_s;
   const double2* G = d.G + t * (long long)d.n * d.n;
 
@@ -140,7 +155,7 @@ __global__ void __launch_bounds__(kThreads) k_jacobi(EighDesc d) {
     int i = 0, rem = idx;
     while (rem >= n2 - i) { rem -= n2 - i; ++i; }
     const int j = i + rem;
-    Gp[idx] = (i < n && j < n) ? G[(long long)(pb.off + i) * d.n + pb.off + j] : make_double2(0.0, 0.0);
+    Gp[idx] = (i < n && j < n) ? gram_at(d, G, (long long)(pb.off + i) * d.n + pb.off + j) : make_double2(0.0, 0.0);
   }
   for (int idx = threadIdx.x; idx < nblk; idx += blockDim.x) {
     int P = 0, rem = idx;
@@ -152,10 +167,10 @@ __global__ void __launch_bounds__(kThreads) k_jacobi(EighDesc d) {
       V[idx] = make_double2((idx / n2 == idx % n2) ? 1.0 : 0.0, 0.0);
   // trace of the whole matrix (both blocks in block-diagonal mode)
   double part = 0.0;
-  for (int i = threadIdx.x; i < d.n; i += blockDim.x) part += G[(long long)i * d.n + i].x;
+  for (int i = threadIdx.x; i < d.n; i += blockDim.x) part += gram_at(d, G, (long long)i * d.n + i).x;
   red[threadIdx.x] = part;
   __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
+  for (int w = NT / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
@@ -166,10 +181,13 @@ __global__ void __launch_bounds__(kThreads) k_jacobi(EighDesc d) {
 
   int step_count = 0, sweeps_done = 0;
   double* log = d.rot_log ? d.rot_log + t * (long long)d.max_steps * h * 3 : nullptr;
+  const double tol = d.tol > 0.0 ? d.tol : 1e-15;
+  const double stop_ratio = 0.25 * sqrt(tol);
   if (n2 >= 2 && finite) {
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
       if (threadIdx.x == 0) any_rot = 0;
       __syncthreads();
+      double my_ratio = 0.0;     // rotation threads: largest rotated ratio this sweep
       for (int s = 0; s < n2 - 1; ++s) {
         // -- rotation parameters of the n2/2 pairs --
         if (threadIdx.x < h) {
@@ -180,7 +198,9 @@ __global__ void __launch_bounds__(kThreads) k_jacobi(EighDesc d) {
           const double ab = sqrt(cabs2(b));
           Rot r;
           r.c = 1.0; r.s = make_double2(0.0, 0.0); r.delta = 0.0;
-          if (ab > 1e-15 * sqrt(fabs(a * dd)) && ab > 1e-16 * tr && ab > 0.0) {
+          const double sad = sqrt(fabs(a * dd));
+          if (ab > tol * sad && ab > 0.1 * tol * tr && ab > 0.0) {
+            my_ratio = fmax(my_ratio, sad > 0.0 ? ab / sad : 1.0);
             const double th = (dd - a) / (2.0 * ab);
             const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
             const double c = 1.0 / sqrt(1.0 + tt * tt);
@@ -251,7 +271,14 @@ __global__ void __launch_bounds__(kThreads) k_jacobi(EighDesc d) {
         __syncthreads();
       }
       ++sweeps_done;
-      if (any_rot == 0) break;
+      // the rotation threads are wavefront 0 (h <= 64)
+      if (threadIdx.x < 64) {
+        double m = my_ratio;
+        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+        if (threadIdx.x == 0) sweep_ratio = m;
+      }
+      __syncthreads();
+      if (any_rot == 0 || sweep_ratio < stop_ratio) break;
       __syncthreads();
     }
   }
@@ -457,20 +484,23 @@ __global__ void __launch_bounds__(256) k_jacobi_wave(EighDesc d, long long nprob
   const double2* Gg = d.G + t * (long long)d.n * d.n;
   for (int idx = lane; idx < n2 * n2; idx += 64) {
     const int i = idx / n2, j = idx - (idx / n2) * n2;
-    G[idx] = (i < n && j < n) ? Gg[(long long)(pb.off + i) * d.n + pb.off + j] : make_double2(0.0, 0.0);
+    G[idx] = (i < n && j < n) ? gram_at(d, Gg, (long long)(pb.off + i) * d.n + pb.off + j) : make_double2(0.0, 0.0);
     V[idx] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   double part = 0.0;
-  for (int i = lane; i < d.n; i += 64) part += Gg[(long long)i * d.n + i].x;
+  for (int i = lane; i < d.n; i += 64) part += gram_at(d, Gg, (long long)i * d.n + i).x;
   for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
   const double tr = part;
   const bool finite = isfinite(tr) && tr > 0.0;
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
   int sweeps_done = 0;
+  const double tol = d.tol > 0.0 ? d.tol : 1e-15;
+  const double stop_ratio = 0.25 * sqrt(tol);
   if (n2 >= 2 && finite) {
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
       bool rotated = false;
+      double my_ratio = 0.0;
       for (int s = 0; s < n2 - 1; ++s) {
         bool mine = false;
         if (lane < h) {
@@ -481,7 +511,8 @@ __global__ void __launch_bounds__(256) k_jacobi_wave(EighDesc d, long long nprob
           const double ab = sqrt(cabs2(b));
           Rot r;
           r.c = 1.0; r.s = make_double2(0.0, 0.0); r.delta = 0.0;
-          if (ab > 1e-15 * sqrt(fabs(a * dd)) && ab > 1e-16 * tr && ab > 0.0) {
+          if (ab > tol * sqrt(fabs(a * dd)) && ab > 0.1 * tol * tr && ab > 0.0) {
+            my_ratio = fmax(my_ratio, ab / fmax(sqrt(fabs(a * dd)), 1e-300));
             const double th = (dd - a) / (2.0 * ab);
             const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
             const double c = 1.0 / sqrt(1.0 + tt * tt);
@@ -539,7 +570,9 @@ __global__ void __launch_bounds__(256) k_jacobi_wave(EighDesc d, long long nprob
         __builtin_amdgcn_wave_barrier();
       }
       ++sweeps_done;
-      if (!rotated) break;
+      double m = my_ratio;
+      for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+      if (!rotated || m < stop_ratio) break;
     }
   }
   // eigenvalues, descending order, truncation
@@ -635,8 +668,10 @@ hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st) {
   if (d.n < 1 || d.n > 128 || d.new_pad < 1 || (nb == 2 && ((d.n & 1) || (d.new_pad & 1))))
     return hipErrorInvalidValue;
   if (!g_attr_done) {
-    hipFuncSetAttribute((const void*)k_jacobi<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
-    hipFuncSetAttribute((const void*)k_jacobi<false>, hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
+    hipFuncSetAttribute((const void*)k_jacobi<true, kThreadsSmall>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        140 * 1024);
+    hipFuncSetAttribute((const void*)k_jacobi<false, kThreadsLarge>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        140 * 1024);
     g_attr_done = true;
   }
   const int nsub = d.n / nb;
@@ -655,14 +690,15 @@ hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st) {
   }
   if (n2 <= kVLdsMax) {
     const size_t bytes = gbytes + (size_t)n2 * n2 * sizeof(double2);
-    hipLaunchKernelGGL(k_jacobi<true>, dim3((unsigned)((long long)batch * nb)), dim3(kThreads), bytes, st, d);
+    hipLaunchKernelGGL((k_jacobi<true, kThreadsSmall>), dim3((unsigned)((long long)batch * nb)), dim3(kThreadsSmall),
+                       bytes, st, d);
     return hipGetLastError();
   }
   if (nb != 1) return hipErrorInvalidValue;
   if (!d.rot_log || !d.order || !d.lam_sorted || !d.kept || !d.scale_abs || !d.nsteps)
     return hipErrorInvalidValue;
   if ((long long)d.max_steps < (long long)kMaxSweeps * (n2 - 1)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_jacobi<false>, dim3(batch), dim3(kThreads), gbytes, st, d);
+  hipLaunchKernelGGL((k_jacobi<false, kThreadsLarge>), dim3(batch), dim3(kThreadsLarge), gbytes, st, d);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_jacobi_vectors, dim3((unsigned)batch), dim3(kVecWaves * 64), 0, st, d);

@@ -8,13 +8,19 @@
 // with per-operand element strides, a trajectory batch index t, a block
 // index g (the two diagonal blocks of a block-diagonal problem), an inner
 // batch index h, and a K index that may be split in two strided parts
-// (l / Kin, l % Kin) so the middle-leg Gram needs no transpose.
+// (l / Kin, l % Kin) so the middle-leg Gram needs no transpose.  With
+// ksplit > 1 the K range is cut into ksplit slices whose partial products
+// go to ksplit copies of C (stride sCz); the consumer sums them.
 //
-// Tiling: a 256-thread workgroup (4 wave64) owns a 64 x 64 output tile; each
-// wave owns a 32 x 32 quadrant built from 2 x 2 MFMA 16x16x4 tiles.  A complex
-// multiply-accumulate is four real MFMAs (re*re, -im*im, re*im, im*re).
-// K is staged through LDS in chunks of 16, with the contiguous operand
-// dimension mapped to consecutive lanes on the global load.
+// Tiling: a 256-thread workgroup (4 wave64).  Each wave owns a 32 x 32
+// output block built from 2 x 2 MFMA 16x16x4 tiles; a complex
+// multiply-accumulate is four real MFMAs (re*re, -im*im, re*im, im*re).  The
+// waves are arranged WM x WN over the output tile (32 WM x 32 WN), or, for
+// outputs of at most 32 x 32 (KW = 4), all four share one 32 x 32 block and
+// each takes a quarter of every K chunk, reduced through LDS at the end.  K
+// is staged through LDS in chunks of 16 KW; the next chunk's global loads are
+// issued before the current chunk's MFMAs, and the contiguous operand
+// dimension is mapped to consecutive lanes on the global load.
 #include "ttn_device.h"
 #include "ttn_kernels.h"
 
@@ -41,7 +47,7 @@ template <> struct MfmaAcc<double> {
   }
 };
 
-constexpr int TM = 64, TN = 64, TK = 16, PADL = 1;
+constexpr int PADL = 1;
 
 template <typename S> __device__ inline void load_c(const S* p, long long off, double& re, double& im) {
   S v = p[off];
@@ -49,15 +55,23 @@ template <typename S> __device__ inline void load_c(const S* p, long long off, d
   im = (double)v.y;
 }
 
-template <typename SA, typename SB, typename SC, typename R>
+template <typename SA, typename SB, typename SC, typename R, int WM, int WN, int KW>
 __global__ void __launch_bounds__(256) k_zgemm(GemmDesc d) {
-  __shared__ R As[2][TK][TM + PADL];   // [re/im][k][m]
-  __shared__ R Bs[2][TK][TN + PADL];   // [re/im][k][n]
+  static_assert(WM * WN * KW == 4, "four waves per workgroup");
+  constexpr int TM = 32 * WM, TN = 32 * WN, TK = 16 * KW;
+  constexpr int AE = TM * TK / 256, BE = TN * TK / 256;   // staged elements per thread
+  constexpr int STAGE = 2 * TK * (TM + PADL) + 2 * TK * (TN + PADL);
+  constexpr int RED = (KW > 1) ? (KW - 1) * 64 * 32 : 0;   // partial accumulators of waves kw > 0
+  __shared__ R smem[STAGE > RED ? STAGE : RED];
+  R (*As)[TK][TM + PADL] = reinterpret_cast<R (*)[TK][TM + PADL]>(smem);                 // [re/im][k][m]
+  R (*Bs)[TK][TN + PADL] = reinterpret_cast<R (*)[TK][TN + PADL]>(smem + 2 * TK * (TM + PADL));
   typedef typename MfmaAcc<R>::type acc_t;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
+  const int kw = wave / (WM * WN);
+  const int wm = (wave % (WM * WN)) / WN, wn = wave % WN;
   const long long bx = blockIdx.x;
   const int tile_n = (int)(bx % d.tilesN);
   const long long bh = bx / d.tilesN;            // flattened (t, g, h)
@@ -65,13 +79,20 @@ __global__ void __launch_bounds__(256) k_zgemm(GemmDesc d) {
   const int g = (int)((bh / d.H) % d.G2);
   const long long t = bh / ((long long)d.H * d.G2);
   const int tile_m = blockIdx.y;
+  const int z = blockIdx.z;
   const int m0 = tile_m * TM, n0 = tile_n * TN;
 
   const SA* A = (const SA*)d.A + t * d.sAt + h * d.sAh + g * d.sAg;
   const SB* B = (const SB*)d.B + t * d.sBt + h * d.sBh + g * d.sBg;
-  SC* C = (SC*)d.C + t * d.sCt + h * d.sCh + g * d.sCg;
+  SC* C = (SC*)d.C + t * d.sCt + h * d.sCh + g * d.sCg + z * d.sCz;
   const R sgnA = d.conjA ? (R)-1 : (R)1;
   const R sgnB = d.conjB ? (R)-1 : (R)1;
+
+  // K slice of this split (an empty slice still writes its zero partials)
+  const int nchunks = (d.K + TK - 1) / TK;
+  const int per = (nchunks + d.ksplit - 1) / d.ksplit;
+  const int kbeg = z * per * TK;
+  const int kend = min(d.K, kbeg + per * TK);
 
   acc_t acc_re[2][2], acc_im[2][2];
 #pragma unroll
@@ -81,55 +102,78 @@ __global__ void __launch_bounds__(256) k_zgemm(GemmDesc d) {
       acc_re[a][b] = (acc_t){0, 0, 0, 0};
       acc_im[a][b] = (acc_t){0, 0, 0, 0};
     }
-
-  const int wm = wave >> 1, wn = wave & 1;
   const int li = lane & 15, lk = lane >> 4;
 
-  for (int k0 = 0; k0 < d.K; k0 += TK) {
-    // ---- stage A tile [TM x TK] and B tile [TK x TN] ----
+  R ra_re[AE], ra_im[AE], rb_re[BE], rb_im[BE];
+  auto fetch = [&](int k0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int mm, kk;
-      if (d.a_m_fast) { mm = tid & 63; kk = (tid >> 6) + 4 * r; }
-      else            { mm = (tid >> 4) + 16 * r; kk = tid & 15; }
+    for (int r = 0; r < AE; ++r) {
+      const int e = tid + 256 * r;
+      const int mm = d.a_m_fast ? e % TM : e / TK;
+      const int kk = d.a_m_fast ? e / TM : e % TK;
       const int gm = m0 + mm, gk = k0 + kk;
       double re = 0.0, im = 0.0;
-      if (gm < d.M && gk < d.K) {
-        long long off = (long long)gm * d.sAi + (long long)(gk / d.Kin) * d.sAl1 +
-                        (long long)(gk % d.Kin) * d.sAl2;
+      if (gm < d.M && gk < kend) {
+        const long long off = (long long)gm * d.sAi + (long long)(gk / d.Kin) * d.sAl1 +
+                              (long long)(gk % d.Kin) * d.sAl2;
         load_c(A, off, re, im);
       }
-      As[0][kk][mm] = (R)re;
-      As[1][kk][mm] = (R)im * sgnA;
+      ra_re[r] = (R)re;
+      ra_im[r] = (R)im * sgnA;
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int nn, kk;
-      if (d.b_n_fast) { nn = tid & 63; kk = (tid >> 6) + 4 * r; }
-      else            { nn = (tid >> 4) + 16 * r; kk = tid & 15; }
+    for (int r = 0; r < BE; ++r) {
+      const int e = tid + 256 * r;
+      const int nn = d.b_n_fast ? e % TN : e / TK;
+      const int kk = d.b_n_fast ? e / TN : e % TK;
       const int gn = n0 + nn, gk = k0 + kk;
       double re = 0.0, im = 0.0;
-      if (gn < d.N && gk < d.K) {
-        long long off = (long long)(gk / d.Kin) * d.sBl1 + (long long)(gk % d.Kin) * d.sBl2 +
-                        (long long)gn * d.sBj;
+      if (gn < d.N && gk < kend) {
+        const long long off = (long long)(gk / d.Kin) * d.sBl1 + (long long)(gk % d.Kin) * d.sBl2 +
+                              (long long)gn * d.sBj;
         load_c(B, off, re, im);
       }
-      Bs[0][kk][nn] = (R)re;
-      Bs[1][kk][nn] = (R)im * sgnB;
+      rb_re[r] = (R)re;
+      rb_im[r] = (R)im * sgnB;
     }
-    __syncthreads();
-    // ---- 4 k-steps of the 16x16x4 MFMA per chunk ----
+  };
+  auto stage = [&]() {
 #pragma unroll
-    for (int ks = 0; ks < TK; ks += 4) {
+    for (int r = 0; r < AE; ++r) {
+      const int e = tid + 256 * r;
+      const int mm = d.a_m_fast ? e % TM : e / TK;
+      const int kk = d.a_m_fast ? e / TM : e % TK;
+      As[0][kk][mm] = ra_re[r];
+      As[1][kk][mm] = ra_im[r];
+    }
+#pragma unroll
+    for (int r = 0; r < BE; ++r) {
+      const int e = tid + 256 * r;
+      const int nn = d.b_n_fast ? e % TN : e / TK;
+      const int kk = d.b_n_fast ? e / TN : e % TK;
+      Bs[0][kk][nn] = rb_re[r];
+      Bs[1][kk][nn] = rb_im[r];
+    }
+  };
+
+  if (kbeg < kend) fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += TK) {
+    stage();
+    __syncthreads();
+    if (k0 + TK < kend) fetch(k0 + TK);      // in flight during the MFMAs below
+    // ---- this wave's 16 k values of the chunk, 4 per MFMA ----
+#pragma unroll
+    for (int ks = 0; ks < 16; ks += 4) {
+      const int kr = 16 * kw + ks + lk;
       R a_re[2], a_im[2], b_re[2], b_im[2];
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         const int mi = wm * 32 + s * 16 + li;
         const int nj = wn * 32 + s * 16 + li;
-        a_re[s] = As[0][ks + lk][mi];
-        a_im[s] = As[1][ks + lk][mi];
-        b_re[s] = Bs[0][ks + lk][nj];
-        b_im[s] = Bs[1][ks + lk][nj];
+        a_re[s] = As[0][kr][mi];
+        a_im[s] = As[1][kr][mi];
+        b_re[s] = Bs[0][kr][nj];
+        b_im[s] = Bs[1][kr][nj];
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
@@ -142,6 +186,37 @@ __global__ void __launch_bounds__(256) k_zgemm(GemmDesc d) {
         }
     }
     __syncthreads();
+  }
+  if (KW > 1) {
+    // waves kw > 0 hand their partial sums to wave 0 (the staging buffers
+    // are free after the last barrier of the loop)
+    if (kw > 0) {
+      R* red = smem + (kw - 1) * 64 * 32;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            red[((a * 2 + b) * 8 + r) * 64 + lane] = acc_re[a][b][r];
+            red[((a * 2 + b) * 8 + 4 + r) * 64 + lane] = acc_im[a][b][r];
+          }
+    }
+    __syncthreads();
+    if (kw > 0) return;
+#pragma unroll
+    for (int w = 0; w < KW - 1; ++w) {
+      const R* red = smem + w * 64 * 32;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            acc_re[a][b][r] += red[((a * 2 + b) * 8 + r) * 64 + lane];
+            acc_im[a][b][r] += red[((a * 2 + b) * 8 + 4 + r) * 64 + lane];
+          }
+    }
   }
   // ---- write back each 16x16 tile in the MFMA's output lane layout ----
 #pragma unroll
@@ -159,18 +234,55 @@ __global__ void __launch_bounds__(256) k_zgemm(GemmDesc d) {
       }
 }
 
-template <typename SA, typename SB, typename SC, typename R>
-hipError_t launch_zgemm_t(GemmDesc d, int batch, hipStream_t st) {
+// Output tile shape chosen for a problem: 64 x 64 in general, 128 x 32 or
+// 32 x 128 when one side is at most 32, 32 x 32 with the K chunk split over
+// the four waves when both are.
+enum TileCfg { TILE_64x64 = 0, TILE_128x32 = 1, TILE_32x128 = 2, TILE_32x32 = 3 };
+static int tile_cfg(int M, int N) {
+  if (M <= 32 && N <= 32) return TILE_32x32;
+  if (N <= 32) return TILE_128x32;
+  if (M <= 32) return TILE_32x128;
+  return TILE_64x64;
+}
+static void tile_dims(int cfg, int* tm, int* tn) {
+  switch (cfg) {
+    case TILE_128x32: *tm = 128; *tn = 32; return;
+    case TILE_32x128: *tm = 32; *tn = 128; return;
+    case TILE_32x32: *tm = 32; *tn = 32; return;
+    default: *tm = 64; *tn = 64; return;
+  }
+}
+
+long long zgemm_tiles(const GemmDesc& d) {
+  int tm, tn;
+  tile_dims(tile_cfg(d.M, d.N), &tm, &tn);
+  return (long long)((d.M + tm - 1) / tm) * ((d.N + tn - 1) / tn);
+}
+
+template <typename SA, typename SB, typename SC, typename R, int WM, int WN, int KW>
+hipError_t launch_cfg(GemmDesc d, int batch, hipStream_t st) {
+  constexpr int TM = 32 * WM, TN = 32 * WN;
   d.tilesN = (d.N + TN - 1) / TN;
   const int tilesM = (d.M + TM - 1) / TM;
+  dim3 grid((unsigned)((long long)batch * d.G2 * d.H * d.tilesN), (unsigned)tilesM, (unsigned)d.ksplit);
+  hipLaunchKernelGGL((k_zgemm<SA, SB, SC, R, WM, WN, KW>), grid, dim3(256), 0, st, d);
+  return hipGetLastError();
+}
+
+template <typename SA, typename SB, typename SC, typename R>
+hipError_t launch_zgemm_t(GemmDesc d, int batch, hipStream_t st) {
   if (d.M <= 0 || d.N <= 0 || batch <= 0) return hipSuccess;
   if (d.K <= 0) return hipErrorInvalidValue;
   if (d.Kin <= 0) d.Kin = d.K;
   if (d.G2 < 1) d.G2 = 1;
-  if (d.H < 1) return hipErrorInvalidValue;
-  dim3 grid((unsigned)((long long)batch * d.G2 * d.H * d.tilesN), (unsigned)tilesM, 1);
-  hipLaunchKernelGGL((k_zgemm<SA, SB, SC, R>), grid, dim3(256), 0, st, d);
-  return hipGetLastError();
+  if (d.ksplit < 1) d.ksplit = 1;
+  if (d.H < 1 || d.ksplit > 64) return hipErrorInvalidValue;
+  switch (tile_cfg(d.M, d.N)) {
+    case TILE_128x32: return launch_cfg<SA, SB, SC, R, 4, 1, 1>(d, batch, st);
+    case TILE_32x128: return launch_cfg<SA, SB, SC, R, 1, 4, 1>(d, batch, st);
+    case TILE_32x32: return launch_cfg<SA, SB, SC, R, 1, 1, 4>(d, batch, st);
+    default: return launch_cfg<SA, SB, SC, R, 2, 2, 1>(d, batch, st);
+  }
 }
 
 hipError_t launch_zgemm(const GemmDesc& d, int batch, int kind, hipStream_t st) {

@@ -19,12 +19,16 @@ struct GemmDesc {
   long long sAt, sAh, sAi, sAl1, sAl2, sAg;
   long long sBt, sBh, sBl1, sBl2, sBj, sBg;
   long long sCt, sCh, sCi, sCj, sCg;
+  int ksplit;               // 0 or 1: one K range; k > 1: k partial products
+  long long sCz;            // element stride between the partial products of C
   int conjA, conjB;
   int a_m_fast, b_n_fast;   // operand dimension that is unit-stride on load
   int tilesN;               // filled by the launcher
 };
 
 hipError_t launch_zgemm(const GemmDesc& d, int batch, int kind, hipStream_t st);
+// output tiles per (t, g, h) of the tile shape the launcher picks for d
+long long zgemm_tiles(const GemmDesc& d);
 
 // ---------------------------------------------------------------- EIGH ----
 // Hermitian eigen-decomposition of the per-trajectory Gram matrix of one
@@ -58,6 +62,9 @@ struct EighDesc {
   double* scale_abs;    // [batch]
   int* nsteps;          // [batch]
   int* nk_out;          // [batch][4]: (non-zero eigenvalues, kept) of block 0, block 1 (may be null)
+  double tol;           // rotate a pair while |g_pq| > tol sqrt(g_pp g_qq) (0: 1e-15)
+  int gsplit;           // G is the sum of gsplit partial products (0 or 1: one)
+  long long gslice;     // element stride between them
 };
 hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st);
 int eigh_max_sweeps();

@@ -77,6 +77,7 @@ struct ttn_ctx {
   std::vector<Buf> bufs;
   int centre = 1;
   int nmax = 2;        // largest bond dimension a Gram can have
+  int gslices = 1;     // partial-product slices of the Gram workspace
   // workspaces
   double2* G = nullptr;
   void* Wi = nullptr;
@@ -226,7 +227,8 @@ static bool gemm_fits(const GemmDesc& g, int batch, long long capA, long long ca
   const long long eA = extent(batch, g.sAt, G2, g.sAg, g.H, g.sAh, g.M, g.sAi, g.K, g.Kin, g.sAl1, g.sAl2);
   const long long eB = extent(batch, g.sBt, G2, g.sBg, g.H, g.sBh, g.N, g.sBj, g.K, g.Kin, g.sBl1, g.sBl2);
   const long long eC = (long long)(batch - 1) * g.sCt + (long long)(G2 - 1) * g.sCg + (long long)(g.H - 1) * g.sCh +
-                       (long long)(g.M - 1) * g.sCi + (long long)(g.N - 1) * g.sCj + 1;
+                       (long long)(g.M - 1) * g.sCi + (long long)(g.N - 1) * g.sCj +
+                       (long long)(std::max(g.ksplit, 1) - 1) * g.sCz + 1;
   return eA <= capA && eB <= capB && eC <= capC;
 }
 
@@ -307,6 +309,9 @@ static void gram_split(GemmDesc& g) {
 }
 static long long buf_elems(const ttn_ctx* ctx, int b) { return (long long)(ctx->bufs[b].bytes / ctx->es); }
 static long long ws_elems(const ttn_ctx* ctx) { return (long long)ctx->B * ctx->nmax * ctx->nmax; }
+static long long gslice_elems(const ttn_ctx* ctx) { return ws_elems(ctx); }
+// a Gram launch with fewer workgroups than this splits its K range
+constexpr long long kGramTargetWgs = 1024;
 
 static inline void* offset_ptr(const void* p, long long elems, size_t es) {
   return (void*)((const char*)p + elems * (long long)es);
@@ -356,10 +361,20 @@ static ttn_status leg_apply(ttn_ctx* ctx, int src_buf, std::array<int, 3> d, int
   return TTN_OK;
 }
 
-static ttn_status gram(ttn_ctx* ctx, int src_buf, std::array<int, 3> d, int leg, int blocks = 1) {
+// The Gram matrix of leg `leg` of the node in src_buf into ctx->G.  When the
+// output has too few tiles to occupy the chip, K is split over up to
+// ctx->gslices workgroups per tile, each writing its partial product to its
+// own slice of G (the eigensolver sums the slices); *nsplit returns the count.
+static ttn_status gram(ttn_ctx* ctx, int src_buf, std::array<int, 3> d, int leg, int blocks, int* nsplit) {
   GemmDesc g = gram_desc(ctx->bufs[src_buf].p, d, leg, ctx->G);
   if (blocks > 1) gram_split(g);
-  if (!gemm_fits(g, ctx->B, buf_elems(ctx, src_buf), buf_elems(ctx, src_buf), ws_elems(ctx)))
+  const long long wgs = (long long)ctx->B * std::max(g.G2, 1) * zgemm_tiles(g);
+  int ks = (int)std::min<long long>((kGramTargetWgs + wgs - 1) / wgs, ctx->gslices);
+  ks = std::max(1, std::min(ks, g.K / 256));
+  g.ksplit = ks;
+  g.sCz = gslice_elems(ctx);
+  *nsplit = ks;
+  if (!gemm_fits(g, ctx->B, buf_elems(ctx, src_buf), buf_elems(ctx, src_buf), ws_elems(ctx) * ctx->gslices))
     return fail(ctx, TTN_EINVAL, "internal: Gram exceeds its buffers");
   ctx->gram_flops += 8.0 * (double)g.M * g.N * g.K * std::max(g.G2, 1) * ctx->B;
   ++ctx->launches;
@@ -394,9 +409,11 @@ static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int ne
   if (n > ctx->nmax || new_pad > ctx->nmax)
     return fail(ctx, TTN_EINVAL, "internal: bond dimension exceeds workspace");
   if (blocks > 1 && ((n & 1) || (new_pad & 1))) return fail(ctx, TTN_EINVAL, "internal: odd block size");
-  TTN_TRY(gram(ctx, ctx->node_buf[x], dx, lx, blocks));
+  int gsplit = 1;
+  TTN_TRY(gram(ctx, ctx->node_buf[x], dx, lx, blocks, &gsplit));
   EighDesc ed{};
   ed.G = ctx->G; ed.n = n; ed.new_pad = new_pad; ed.cap = cap; ed.cutoff = cutoff;
+  ed.gsplit = gsplit; ed.gslice = gslice_elems(ctx);
   ed.W_iso = ctx->Wi; ed.W_abs = ctx->Wa; ed.out_c128 = ctx->c128;
   ed.blocks = blocks;
   ed.rank_out = blocks > 1 ? nullptr : ctx->rank_table + e;
@@ -408,6 +425,9 @@ static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int ne
   ed.rot_log = ctx->rot_log; ed.max_steps = ctx->max_steps; ed.lam_sorted = ctx->lam_sorted;
   ed.order = ctx->order; ed.kept = ctx->kept; ed.scale_abs = ctx->scale_abs; ed.nsteps = ctx->nsteps;
   ed.nk_out = ctx->nk;
+  // complex64 factors carry ~1e-7 relative error, so off-diagonal Gram
+  // entries below 1e-12 of the diagonal change nothing they hold
+  ed.tol = ctx->c128 ? 1e-15 : 1e-12;
   ctx->launches += large ? 2 : 1;
   {
     ProfScope ps(ctx, large ? CLS_EIGH_LARGE : CLS_EIGH_SMALL);
@@ -865,7 +885,8 @@ ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {
   const int n2 = nmax;
   ctx->max_steps = eigh_max_sweeps() * (n2 - 1);
   bool ok = true;
-  ok &= hipMalloc((void**)&ctx->G, Bz * n2 * n2 * sizeof(double2)) == hipSuccess;
+  ctx->gslices = (int)std::max<long long>(1, std::min<long long>(8, 2048 / ctx->B));
+  ok &= hipMalloc((void**)&ctx->G, ctx->gslices * Bz * n2 * n2 * sizeof(double2)) == hipSuccess;
   ok &= hipMalloc(&ctx->Wi, Bz * n2 * n2 * ctx->es) == hipSuccess;
   ok &= hipMalloc(&ctx->Wa, Bz * n2 * n2 * ctx->es) == hipSuccess;
   if (n2 > 64) ok &= hipMalloc((void**)&ctx->rot_log, Bz * ctx->max_steps * (n2 / 2) * 3 * sizeof(double)) == hipSuccess;
@@ -1355,12 +1376,15 @@ ttn_status ttn_test_leg_apply(ttn_ctx* ctx, int32_t rows, const int32_t* dims3, 
 }
 
 ttn_status ttn_test_gram(ttn_ctx* ctx, int32_t rows, const int32_t* dims3, int32_t leg, const void* T,
-                         int64_t t_elems, double* G, int64_t g_elems) {
+                         int64_t t_elems, double* G, int64_t g_elems, int32_t ksplit) {
   if (!ctx) return TTN_EINVAL;
-  if (rows < 1 || !dims3 || leg < 0 || leg > 2 || !T || !G) return fail(ctx, TTN_EINVAL, "bad arguments");
+  if (rows < 1 || !dims3 || leg < 0 || leg > 2 || !T || !G || ksplit < 1 || ksplit > 64)
+    return fail(ctx, TTN_EINVAL, "bad arguments");
   std::array<int, 3> d{dims3[0], dims3[1], dims3[2]};
   if (d[0] < 1 || d[1] < 1 || d[2] < 1) return fail(ctx, TTN_EINVAL, "bad dims");
   GemmDesc g = gram_desc(T, d, leg, (double2*)G);
+  g.ksplit = ksplit;
+  g.sCz = (long long)rows * d[leg] * d[leg];
   if (!gemm_fits(g, rows, t_elems, t_elems, g_elems)) return fail(ctx, TTN_EINVAL, "buffers too small for the Gram");
   TTN_CHECK_HIP(launch_zgemm(g, rows, ctx->c128 ? GEMM_GRAM_C128 : GEMM_GRAM_C64, ctx->st));
   TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));

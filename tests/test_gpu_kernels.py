@@ -35,18 +35,21 @@ def test_device_uniforms_match_oracle_stream():
     eng.close()
 
 
-SHAPES = [(2, 2, 4), (3, 5, 7), (16, 16, 64), (64, 64, 16), (1, 70, 33)]
+SHAPES = [(2, 2, 4), (3, 5, 7), (16, 16, 64), (64, 64, 16), (1, 70, 33), (8, 40, 48), (4, 130, 20)]
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("leg", [0, 1, 2])
-def test_leg_contraction(dtype, shape, leg):
+@pytest.mark.parametrize("newd", [1, 5, 40, 100])
+def test_leg_contraction(dtype, shape, leg, newd):
+    # newd and the shapes cover every output tile shape (32 x 32 with the K
+    # chunk split over the waves, 128 x 32, 32 x 128, 64 x 64), ragged edges
+    # and K ranges of several chunks
     from paper_2511_05719_amd._abi import lib, check
-    g = np.random.default_rng(zlib.crc32(repr((dtype, shape, leg)).encode()))
+    g = np.random.default_rng(zlib.crc32(repr((dtype, shape, leg, newd)).encode()))
     rows = 3
     n = shape[leg]
-    newd = [1, 5, 64][hash(shape) % 3]
     T = g.normal(size=(rows,) + shape) + 1j * g.normal(size=(rows,) + shape)
     W = g.normal(size=(rows, newd, n)) + 1j * g.normal(size=(rows, newd, n))
     eng = _engine(dtype)
@@ -71,7 +74,8 @@ def test_leg_contraction(dtype, shape, leg):
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("leg", [0, 1, 2])
-def test_gram_fp64(dtype, shape, leg):
+@pytest.mark.parametrize("ksplit", [1, 3])
+def test_gram_fp64(dtype, shape, leg, ksplit):
     from paper_2511_05719_amd._abi import lib, check
     g = np.random.default_rng(7 + zlib.crc32(repr((dtype, shape, leg)).encode()))
     rows = 2
@@ -81,13 +85,14 @@ def test_gram_fp64(dtype, shape, leg):
         T = T.astype(np.complex64).astype(np.complex128)     # the kernel sees these exact values
     eng = _engine(dtype)
     Td = _dev_complex(T, dtype)
-    G = torch.zeros(rows, n, n, 2, dtype=torch.float64, device="cuda")
+    # slices start as NaN: every slice (an empty K part too) must be written
+    G = torch.full((ksplit, rows, n, n, 2), float("nan"), dtype=torch.float64, device="cuda")
     dims = (C.c_int32 * 3)(*shape)
-    check(lib().ttn_test_gram(eng._ctx, rows, dims, leg, Td.data_ptr(), T.size, G.data_ptr(), rows * n * n),
-          eng._ctx)
+    check(lib().ttn_test_gram(eng._ctx, rows, dims, leg, Td.data_ptr(), T.size, G.data_ptr(),
+                              ksplit * rows * n * n, ksplit), eng._ctx)
     Tm = np.moveaxis(T, 1 + leg, -1).reshape(rows, -1, n)
     ref = np.einsum("tmi,tmj->tij", Tm.conj(), Tm)
-    got = _host_complex(G)
+    got = _host_complex(G).sum(axis=0)
     # FP64 accumulation of exact products: rounding only
     assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
     eng.close()
