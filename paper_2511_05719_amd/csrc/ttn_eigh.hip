@@ -89,9 +89,9 @@ __device__ inline Problem problem_of(const EighDesc& d, long long bid) {
   return p;
 }
 
-template <typename S>
+template <typename S, typename VT>
 __device__ void write_factors(const EighDesc& d, const Problem& pb, int row_lo, int row_hi,
-                              const double2* Vrows /* rows [row_lo,row_hi) x n2 */, int n2, const int* order,
+                              const VT* Vrows /* rows [row_lo,row_hi) x n2 */, int n2, const int* order,
                               const double* lam_sorted, int k, double scale_abs) {
   S* Wi = (S*)d.W_iso + pb.t * (long long)d.new_pad * d.n;
   S* Wa = (S*)d.W_abs + pb.t * (long long)d.new_pad * d.n;
@@ -102,7 +102,7 @@ __device__ void write_factors(const EighDesc& d, const Problem& pb, int row_lo, 
     const int i = row_lo + idx % nrows;
     double2 wi = make_double2(0.0, 0.0), wa = make_double2(0.0, 0.0);
     if (a < k) {
-      const double2 v = Vrows[(long long)(i - row_lo) * n2 + order[a]];
+      const double2 v = to_d2(Vrows[(long long)(i - row_lo) * n2 + order[a]]);
       const double s = sqrt(lam_sorted[a]);
       wi = cscale(v, 1.0 / s);
       wa = cscale(cconj(v), s * scale_abs);
@@ -129,7 +129,10 @@ __device__ void write_factors(const EighDesc& d, const Problem& pb, int row_lo, 
 // sweep whose largest rotated ratio |g_pq| / sqrt(g_pp g_qq) stayed below
 // sqrt(tol) / 4 leaves off-diagonal entries far below tol: the solver stops
 // after it instead of spending one more sweep to find nothing to rotate.
-template <bool kVinLds, int NT>
+// VT: element type of the eigenvector matrix kept in LDS (kVinLds).  Runs
+// whose factors are complex64 accumulate it in complex64, which halves its
+// LDS footprint so that two problems share a CU.
+template <bool kVinLds, int NT, typename VT>
 __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
   extern __shared__ double2 smem[];
   const Problem pb = problem_of(d, blockIdx.x);
@@ -140,7 +143,7 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
   const int npk = n2 * (n2 + 1) / 2;
   const int nblk = h * (h + 1) / 2;
   double2* Gp = smem;                                  // packed G
-  double2* V = smem + npk;                             // [n2][n2] if kVinLds
+  VT* V = reinterpret_cast<VT*>(smem + npk);           // [n2][n2] if kVinLds
   __shared__ Rot rot[64];
   __shared__ unsigned short blk[2080];                 // (P, Q) of the upper 2x2 blocks
   __shared__ double lam[128];
@@ -164,7 +167,7 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
   }
   if (kVinLds)
     for (int idx = threadIdx.x; idx < n2 * n2; idx += blockDim.x)
-      V[idx] = make_double2((idx / n2 == idx % n2) ? 1.0 : 0.0, 0.0);
+      V[idx] = from_d2<VT>(make_double2((idx / n2 == idx % n2) ? 1.0 : 0.0, 0.0));
   // trace of the whole matrix (both blocks in block-diagonal mode)
   double part = 0.0;
   for (int i = threadIdx.x; i < d.n; i += blockDim.x) part += gram_at(d, G, (long long)i * d.n + i).x;
@@ -262,9 +265,9 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
             if (rP.delta == 0.0) continue;
             int p, q;
             pair_of(n2, s, P, &p, &q);
-            const double2 vp = V[r * n2 + p], vq = V[r * n2 + q];
-            V[r * n2 + p] = csub(cscale(vp, rP.c), cmul(cconj(rP.s), vq));
-            V[r * n2 + q] = cadd(cmul(rP.s, vp), cscale(vq, rP.c));
+            const double2 vp = to_d2(V[r * n2 + p]), vq = to_d2(V[r * n2 + q]);
+            V[r * n2 + p] = from_d2<VT>(csub(cscale(vp, rP.c), cmul(cconj(rP.s), vq)));
+            V[r * n2 + q] = from_d2<VT>(cadd(cmul(rP.s, vp), cscale(vq, rP.c)));
           }
         }
         ++step_count;
@@ -668,10 +671,12 @@ hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st) {
   if (d.n < 1 || d.n > 128 || d.new_pad < 1 || (nb == 2 && ((d.n & 1) || (d.new_pad & 1))))
     return hipErrorInvalidValue;
   if (!g_attr_done) {
-    hipFuncSetAttribute((const void*)k_jacobi<true, kThreadsSmall>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        140 * 1024);
-    hipFuncSetAttribute((const void*)k_jacobi<false, kThreadsLarge>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        140 * 1024);
+    hipFuncSetAttribute((const void*)k_jacobi<true, kThreadsSmall, double2>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
+    hipFuncSetAttribute((const void*)k_jacobi<true, kThreadsSmall, float2>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
+    hipFuncSetAttribute((const void*)k_jacobi<false, kThreadsLarge, double2>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
     g_attr_done = true;
   }
   const int nsub = d.n / nb;
@@ -689,16 +694,20 @@ hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st) {
     return hipGetLastError();
   }
   if (n2 <= kVLdsMax) {
-    const size_t bytes = gbytes + (size_t)n2 * n2 * sizeof(double2);
-    hipLaunchKernelGGL((k_jacobi<true, kThreadsSmall>), dim3((unsigned)((long long)batch * nb)), dim3(kThreadsSmall),
-                       bytes, st, d);
+    const dim3 grid((unsigned)((long long)batch * nb));
+    if (d.out_c128)
+      hipLaunchKernelGGL((k_jacobi<true, kThreadsSmall, double2>), grid, dim3(kThreadsSmall),
+                         gbytes + (size_t)n2 * n2 * sizeof(double2), st, d);
+    else
+      hipLaunchKernelGGL((k_jacobi<true, kThreadsSmall, float2>), grid, dim3(kThreadsSmall),
+                         gbytes + (size_t)n2 * n2 * sizeof(float2), st, d);
     return hipGetLastError();
   }
   if (nb != 1) return hipErrorInvalidValue;
   if (!d.rot_log || !d.order || !d.lam_sorted || !d.kept || !d.scale_abs || !d.nsteps)
     return hipErrorInvalidValue;
   if ((long long)d.max_steps < (long long)kMaxSweeps * (n2 - 1)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_jacobi<false, kThreadsLarge>), dim3(batch), dim3(kThreadsLarge), gbytes, st, d);
+  hipLaunchKernelGGL((k_jacobi<false, kThreadsLarge, double2>), dim3(batch), dim3(kThreadsLarge), gbytes, st, d);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_jacobi_vectors, dim3((unsigned)batch), dim3(kVecWaves * 64), 0, st, d);
