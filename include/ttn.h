@@ -178,6 +178,31 @@ ttn_status ttn_log_prob(ttn_ctx* ctx, const ttn_oplist* ol, const uint8_t* recor
                         const int8_t* branches, const double* theta, const double* gamma,
                         int64_t params_stride, double* logp, ttn_stats* st);
 
+/* [sync] log P(record) as ttn_log_prob and its derivatives by every
+ * location's parameters: dtheta[row][l] = d log P / d theta_l (the SRX angle
+ * of Eq. 1 at location l), dgamma[row][l] = d log P / d gamma_l (the damping
+ * of Eq. 2-3; the recorded Kraus branch is held fixed: a jump contributes
+ * 1/gamma, no jump the derivative of K0).  Reverse mode: the adjoint state
+ * A_>^dagger psi_N is carried backwards through the adjoint of every op
+ * (SRX(-theta), CNOT, the recorded projector, K^dagger, the inverse reset)
+ * in a second context of the same configuration (allocated on first use),
+ * and every layer of noise ops between two other ops is differentiated
+ * through the leaf environments of the contraction <lambda| N |psi>; the
+ * state before each layer is recomputed from at most 16 snapshots taken on
+ * the forward pass (device memory: the second context, the snapshots and one
+ * environment per bond are allocated for the call).  Exact for untruncated
+ * runs; with truncation it is the derivative of the same approximation
+ * applied to both states.  The op list must not hold twirled (PAULI) ops.
+ * theta, gamma: as for ttn_batch_run_circuit (both required; pass zeros for
+ * an absent channel); logp device float64 [rows] (out); dtheta, dgamma
+ * device float64 [rows][n_loc] (out, overwritten).  Returns TTN_EPROB when a
+ * forced outcome had probability < 1e-300 or an overlap vanished (those rows
+ * are flagged). */
+ttn_status ttn_log_prob_grad(ttn_ctx* ctx, const ttn_oplist* ol, const uint8_t* records,
+                             const int8_t* branches, const double* theta, const double* gamma,
+                             int64_t params_stride, double* logp, double* dtheta, double* dgamma,
+                             ttn_stats* st);
+
 /* Logical readout (final-data lookup decoder): fail[row] = parity of the
  * data bits XOR parity of the minimum-weight correction of their Z-check
  * syndrome.  data_rec: host int32 [n_data] record columns of the final data

@@ -15,7 +15,8 @@ STATUS_NAMES = {0: "TTN_OK", -1: "TTN_EINVAL", -2: "TTN_ENOMEM", -3: "TTN_EDEVIC
 # every symbol the header declares
 SYMBOLS = ("ttn_create", "ttn_destroy", "ttn_last_error", "ttn_init_product", "ttn_apply_1q",
            "ttn_apply_2q", "ttn_measure_project", "ttn_kraus_jump", "ttn_oplist_upload",
-           "ttn_oplist_free", "ttn_batch_run_circuit", "ttn_log_prob", "ttn_decode", "ttn_compress",
+           "ttn_oplist_free", "ttn_batch_run_circuit", "ttn_log_prob", "ttn_log_prob_grad", "ttn_decode",
+           "ttn_compress",
            "ttn_to_statevector", "ttn_bond_dims", "ttn_uniforms", "ttn_philox_uniform_host",
            "ttn_version", "ttn_test_leg_apply", "ttn_test_gram", "ttn_test_eigh",
            "ttn_profile_enable", "ttn_profile_read")
@@ -64,6 +65,7 @@ def lib() -> C.CDLL:
         "ttn_oplist_free": (i32, [vp]),
         "ttn_batch_run_circuit": (i32, [vp, vp, vp, vp, i64, u64, vp, vp, vp, C.POINTER(Stats)]),
         "ttn_log_prob": (i32, [vp, vp, vp, vp, vp, vp, i64, vp, C.POINTER(Stats)]),
+        "ttn_log_prob_grad": (i32, [vp, vp, vp, vp, vp, vp, i64, vp, vp, vp, C.POINTER(Stats)]),
         "ttn_decode": (i32, [vp, vp, i32, vp, i32, vp, i32, vp]),
         "ttn_compress": (i32, [vp]),
         "ttn_to_statevector": (i32, [vp, i32, vp]),

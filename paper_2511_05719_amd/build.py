@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libttn.so")
-SOURCES = ["ttn_gemm.hip", "ttn_eigh.hip", "ttn_leaf.hip", "ttn_runtime.cpp"]
+SOURCES = ["ttn_gemm.hip", "ttn_eigh.hip", "ttn_leaf.hip", "ttn_adjoint.hip", "ttn_runtime.cpp"]
 ARCH = os.environ.get("TTN_OFFLOAD_ARCH", "gfx950")
 
 

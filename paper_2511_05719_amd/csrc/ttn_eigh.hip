@@ -125,10 +125,13 @@ __device__ void write_factors(const EighDesc& d, const Problem& pb, int row_lo, 
 }
 
 // Convergence.  A pair is rotated while |g_pq| > tol sqrt(g_pp g_qq) (and
-// above 0.1 tol of the trace).  Cyclic Jacobi converges quadratically, so a
-// sweep whose largest rotated ratio |g_pq| / sqrt(g_pp g_qq) stayed below
-// sqrt(tol) / 4 leaves off-diagonal entries far below tol: the solver stops
-// after it instead of spending one more sweep to find nothing to rotate.
+// above 0.1 tol of the trace); the solver stops after a sweep that rotated
+// nothing.  With early_stop it also stops after a sweep whose largest rotated
+// ratio |g_pq| / sqrt(g_pp g_qq) stayed below sqrt(tol) / 4: cyclic Jacobi
+// converges quadratically, so the next sweep would typically find nothing
+// above tol, but a rotation between nearly equal diagonal entries moves
+// off-diagonal mass at first order, so this bound on what is left is
+// sqrt(tol) / 4, not tol (used for complex64 runs only).
 // VT: element type of the eigenvector matrix kept in LDS (kVinLds).  Runs
 // whose factors are complex64 accumulate it in complex64, which halves its
 // LDS footprint so that two problems share a CU.
@@ -185,7 +188,7 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
   int step_count = 0, sweeps_done = 0;
   double* log = d.rot_log ? d.rot_log + t * (long long)d.max_steps * h * 3 : nullptr;
   const double tol = d.tol > 0.0 ? d.tol : 1e-15;
-  const double stop_ratio = 0.25 * sqrt(tol);
+  const double stop_ratio = d.early_stop ? 0.25 * sqrt(tol) : 0.0;
   if (n2 >= 2 && finite) {
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
       if (threadIdx.x == 0) any_rot = 0;
@@ -499,7 +502,7 @@ __global__ void __launch_bounds__(256) k_jacobi_wave(EighDesc d, long long nprob
   __builtin_amdgcn_wave_barrier();
   int sweeps_done = 0;
   const double tol = d.tol > 0.0 ? d.tol : 1e-15;
-  const double stop_ratio = 0.25 * sqrt(tol);
+  const double stop_ratio = d.early_stop ? 0.25 * sqrt(tol) : 0.0;
   if (n2 >= 2 && finite) {
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
       bool rotated = false;

@@ -63,6 +63,7 @@ struct EighDesc {
   int* nsteps;          // [batch]
   int* nk_out;          // [batch][4]: (non-zero eigenvalues, kept) of block 0, block 1 (may be null)
   double tol;           // rotate a pair while |g_pq| > tol sqrt(g_pp g_qq) (0: 1e-15)
+  int early_stop;       // 1: stop after a sweep whose rotated ratios all stayed below sqrt(tol) / 4
   int gsplit;           // G is the sum of gsplit partial products (0 or 1: one)
   long long gslice;     // element stride between them
 };
@@ -114,6 +115,8 @@ struct LeafBatch {
   int* flags;
   uint64_t seed;
   uint64_t traj_offset;
+  int adjoint;         // 1: apply each op's adjoint (SRX, INIT, CNOT, forced MEAS and
+                       //    KRAUS_AD), rescaled to unit norm; no log P, records or branches
 };
 hipError_t launch_leaf_ops(const LeafBatch& b, hipStream_t st);
 
@@ -148,6 +151,8 @@ struct InitDesc {
 hipError_t launch_init_product(const InitDesc& d, int batch, hipStream_t st);
 hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t st);
 hipError_t launch_fill_f64(double* p, double value, long long n, hipStream_t st);
+// n complex ones (complex64 or complex128)
+hipError_t launch_fill_cone(void* p, int c128, long long n, hipStream_t st);
 
 // logical readout: fail[t] = parity(data) ^ parity(leader(syndrome(data)))
 hipError_t launch_decode(const uint8_t* records, long long rec_stride, const int* data_rec, int n_data,
@@ -172,6 +177,41 @@ hipError_t launch_ledger_reset(int* adim, int L, int batch, hipStream_t st);
 
 // out[c] = max over rows t of nk[t][c], c = 0..3 (one workgroup)
 hipError_t launch_nk_max(const int* nk, int batch, int* out, hipStream_t st);
+
+// ------------------------------------------------------------ ADJOINT ----
+// Noise ops of one leaf inside one layer of the adjoint gradient (applied in
+// list order), and the bottom-node environment kernels (ttn_adjoint.hip).
+enum NoiseKind { NOISE_SRX = 0, NOISE_AD = 1 };
+constexpr int kMaxLeafNoise = 8;
+struct LeafNoise {
+  int n;
+  int kind[kMaxLeafNoise];
+  int loc[kMaxLeafNoise];      // parameter column
+  int branch[kMaxLeafNoise];   // NOISE_AD: branch column of the record
+};
+struct EnvParams {
+  const double* theta;
+  const double* gamma;
+  long long pstride;           // row stride of theta / gamma (0: shared)
+  const int8_t* branches;      // [rows][br_stride] recorded Kraus branches
+  long long br_stride;
+};
+struct EnvBottom {
+  const void* lam;             // adjoint tree's bottom node [rows][2][2][ul]
+  const void* psi;             // state tree's bottom node [rows][2][2][up]
+  int ul, up;                  // up-bond dimensions (<= 4)
+  void* out;                   // up environment [rows][ul][up] (k_env_bottom_up)
+  const void* down;            // down environment [rows][ul][up] (k_env_leaf_grad)
+  LeafNoise nz[2];             // noise ops on leaf 0 (leg a) and leaf 1 (leg b)
+  EnvParams par;
+  double* dtheta;              // [rows][gstride] += d log P / d theta
+  double* dgamma;              // [rows][gstride] += d log P / d gamma
+  long long gstride;
+  int* flags;                  // [rows] |= 8 on a vanishing overlap
+  int c128;
+};
+hipError_t launch_env_bottom_up(const EnvBottom& d, int batch, hipStream_t st);
+hipError_t launch_env_leaf_grad(const EnvBottom& d, int batch, hipStream_t st);
 
 // uniform draws for tests
 hipError_t launch_philox_uniforms(uint64_t seed, uint64_t traj_offset, int n_draws, double* out, int batch,

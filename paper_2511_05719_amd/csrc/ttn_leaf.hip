@@ -72,6 +72,28 @@ __global__ void __launch_bounds__(256) k_leaf_ops(LeafBatch b) {
     const int U = b.node_u[k];
     S* T = (S*)b.node_ptr[k] + (long long)row * 4 * U;
     double2 m[2][2];
+    if (b.adjoint && op.kind != LOP_SRX && op.kind != LOP_INIT && op.kind != LOP_CNOT && op.kind != LOP_MEAS &&
+        op.kind != LOP_KRAUS_AD) {
+      b.flags[row] |= 4;
+      continue;
+    }
+    if (b.adjoint && op.kind == LOP_KRAUS_AD) {
+      // K_j^T of the recorded branch (both Kraus matrices are real), then
+      // back to unit norm (the centre is on this node)
+      const double g = b.gamma[(long long)row * b.gamma_row_stride + op.loc];
+      const int jump = b.forced_br ? (b.forced_br[(long long)row * b.forced_br_stride + op.branch] ? 1 : 0) : 0;
+      if (jump) set_m(m, 0, 0, sqrt(g), 0);
+      else set_m(m, 1, 0, 0, sqrt(1.0 - g));
+      apply2(T, U, op.leg, m);
+      double n0, n1;
+      half_norms(T, U, op.leg, 0, &n0, &n1);
+      const double tot = n0 + n1;
+      if (!(tot > 0.0) || !isfinite(tot)) { b.flags[row] |= 1; continue; }
+      const double sc = 1.0 / sqrt(tot);
+      set_m(m, sc, 0, 0, sc);
+      apply2(T, U, op.leg, m);
+      continue;
+    }
     switch (op.kind) {
       case LOP_MATRIX: {
         const double* p = b.mat + (long long)row * b.mat_row_stride + (long long)op.loc * 8;
@@ -81,7 +103,8 @@ __global__ void __launch_bounds__(256) k_leaf_ops(LeafBatch b) {
         break;
       }
       case LOP_SRX: {
-        const double th = b.theta[(long long)row * b.theta_row_stride + op.loc];
+        const double th0 = b.theta[(long long)row * b.theta_row_stride + op.loc];
+        const double th = b.adjoint ? -th0 : th0;
         const double c = cos(0.5 * th), s = sin(0.5 * th);
         m[0][0] = make_double2(c, 0); m[0][1] = make_double2(0, -s);
         m[1][0] = make_double2(0, -s); m[1][1] = make_double2(c, 0);
@@ -123,7 +146,9 @@ __global__ void __launch_bounds__(256) k_leaf_ops(LeafBatch b) {
         // from |0> (prev none / Z) or |+> (prev X) to the requested basis state
         if ((op.arg == 1) != had_x) set_m(prep, r2, r2, r2, -r2);
         else set_m(prep, 1, 0, 0, 1);
-        matmul2(m, prep, undo);
+        // both factors are real symmetric: the adjoint is the reversed product
+        if (b.adjoint) matmul2(m, undo, prep);
+        else matmul2(m, prep, undo);
         apply2(T, U, op.leg, m);
         break;
       }
@@ -163,8 +188,8 @@ __global__ void __launch_bounds__(256) k_leaf_ops(LeafBatch b) {
         if (b.forced_rec) mres = b.forced_rec[(long long)row * b.forced_rec_stride + op.rec] ? 1 : 0;
         else mres = (philox_uniform(b.seed, traj, (uint64_t)op.draw) >= p0) ? 1 : 0;
         const double p = mres ? 1.0 - p0 : p0;
-        if (p < 1e-300) { b.flags[row] |= 2; b.logp[row] = -INFINITY; }
-        else b.logp[row] += log(p);
+        if (p < 1e-300) { b.flags[row] |= 2; if (!b.adjoint) b.logp[row] = -INFINITY; }
+        else if (!b.adjoint) b.logp[row] += log(p);
         const double sc = (p > 0.0) ? 1.0 / sqrt(p * tot) : 0.0;
         // projector onto the outcome, rescaled to unit norm
         if (op.arg == 0) {
@@ -174,7 +199,7 @@ __global__ void __launch_bounds__(256) k_leaf_ops(LeafBatch b) {
           if (mres == 0) set_m(m, hs, hs, hs, hs); else set_m(m, hs, -hs, -hs, hs);
         }
         apply2(T, U, op.leg, m);
-        if (b.records) b.records[(long long)row * b.rec_stride + op.rec] = (uint8_t)mres;
+        if (b.records && !b.adjoint) b.records[(long long)row * b.rec_stride + op.rec] = (uint8_t)mres;
         break;
       }
       case LOP_KRAUS_AD:
@@ -407,6 +432,18 @@ __global__ void __launch_bounds__(256) k_nk_max(const int* nk, int batch, int* o
 hipError_t launch_nk_max(const int* nk, int batch, int* out, hipStream_t st) {
   if (batch <= 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_nk_max, dim3(1), dim3(256), 0, st, nk, batch, out);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_cone(void* p, int c128, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (c128) ((double2*)p)[i] = make_double2(1.0, 0.0);
+  else ((float2*)p)[i] = make_float2(1.0f, 0.0f);
+}
+hipError_t launch_fill_cone(void* p, int c128, long long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_cone, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, c128, n);
   return hipGetLastError();
 }
 

@@ -59,6 +59,7 @@ inline int ilog2(int x) { int r = 0; while ((1 << r) < x) ++r; return r; }
 struct ttn_oplist {
   ttn_ctx* ctx = nullptr;
   std::vector<int32_t> ops;
+  std::vector<int> ad_col;     // per op: branch column of an AD op (-1 otherwise)
   int n_ops = 0, n_loc = 0, n_rec = 0, n_draws = 0, n_ad = 0;
 };
 
@@ -114,6 +115,7 @@ struct ttn_ctx {
   int* nk_host = nullptr;                   // [4] pinned host copy
   // stats
   int64_t hops = 0, launches = 0, block_hops = 0;
+  ttn_ctx* adj = nullptr;      // twin context holding the adjoint state (created on first use)
   double gemm_flops = 0.0, gram_flops = 0.0;
   std::string err;
 };
@@ -428,6 +430,7 @@ static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int ne
   // complex64 factors carry ~1e-7 relative error, so off-diagonal Gram
   // entries below 1e-12 of the diagonal change nothing they hold
   ed.tol = ctx->c128 ? 1e-15 : 1e-12;
+  ed.early_stop = ctx->c128 ? 0 : 1;
   ctx->launches += large ? 2 : 1;
   {
     ProfScope ps(ctx, large ? CLS_EIGH_LARGE : CLS_EIGH_SMALL);
@@ -714,15 +717,10 @@ static ttn_status fill_stats(ttn_ctx* ctx, ttn_stats* st) {
   return TTN_OK;
 }
 
-static ttn_status run_oplist(ttn_ctx* ctx, const ttn_oplist* ol, const double* theta, const double* gamma,
-                             int64_t pstride, uint64_t traj_offset, uint8_t* records, int8_t* branches,
-                             double* logp, const uint8_t* forced_rec, const int8_t* forced_br, ttn_stats* st) {
-  if (!ol || ol->ctx != ctx) return fail(ctx, TTN_EINVAL, "op list belongs to another context");
-  if (!records || !logp) return fail(ctx, TTN_EINVAL, "records and logp are required");
-  if (ol->n_ad > 0 && !branches && !forced_br) return fail(ctx, TTN_EINVAL, "branches required (AD ops)");
-  ctx->hops = 0; ctx->launches = 0; ctx->block_hops = 0; ctx->gemm_flops = 0.0; ctx->gram_flops = 0.0;
-  TTN_TRY(reset_state(ctx, nullptr));
-  TTN_CHECK_HIP(launch_fill_f64(logp, 0.0, ctx->B, ctx->st));
+// Run-level pointers of an op-list execution (see LeafBatch).
+static void setup_run(ttn_ctx* ctx, const ttn_oplist* ol, const double* theta, const double* gamma, int64_t pstride,
+                      uint64_t traj_offset, uint8_t* records, int8_t* branches, double* logp,
+                      const uint8_t* forced_rec, const int8_t* forced_br, int adjoint) {
   LeafBatch& r = ctx->run;
   r = LeafBatch{};
   r.theta = theta; r.theta_row_stride = pstride;
@@ -733,52 +731,70 @@ static ttn_status run_oplist(ttn_ctx* ctx, const ttn_oplist* ol, const double* t
   r.forced_br = forced_br; r.forced_br_stride = ol->n_ad;
   r.logp = logp;
   r.traj_offset = traj_offset;
-  int ad_col = 0;
-  for (int k = 0; k < ol->n_ops; ++k) {
-    const int32_t* o = &ol->ops[(size_t)k * 9];
-    const int op = o[0], q0 = o[1], q1 = o[2], arg = o[3], loc = o[4], draw = o[5], rec = o[6], prev = o[7];
-    int leg;
-    const int node = bottom_of(ctx, q0, &leg);
-    switch (op) {
-      case TTN_OP_INIT: {
-        LeafOp l = leaf_op(LOP_INIT, leg);
-        l.arg = arg; l.prev = prev; l.rec = rec;
-        push_leaf(ctx, node, l);
-        break;
-      }
-      case TTN_OP_CNOT:
-        TTN_TRY(cnot(ctx, q0, q1));
-        break;
-      case TTN_OP_SRX: {
-        LeafOp l = leaf_op(LOP_SRX, leg);
-        l.loc = loc;
-        push_leaf(ctx, node, l);
-        break;
-      }
-      case TTN_OP_PAULI: {
-        LeafOp l = leaf_op(arg == 0 ? LOP_PAULI_SRX : LOP_PAULI_AD, leg);
-        l.loc = loc; l.draw = draw;
-        push_leaf(ctx, node, l);
-        break;
-      }
-      case TTN_OP_AD: {
-        TTN_TRY(move_centre(ctx, node));
-        LeafOp l = leaf_op(LOP_KRAUS_AD, leg);
-        l.loc = loc; l.draw = draw; l.branch = ad_col++;
-        push_leaf(ctx, node, l);
-        break;
-      }
-      case TTN_OP_MEAS: {
-        TTN_TRY(move_centre(ctx, node));
-        LeafOp l = leaf_op(LOP_MEAS, leg);
-        l.arg = arg; l.rec = rec; l.draw = draw;
-        push_leaf(ctx, node, l);
-        break;
-      }
-      default:
-        return fail(ctx, TTN_EINVAL, "unknown op code");
+  r.adjoint = adjoint;
+}
+
+// Op k of the list on the context's state (its adjoint when the run is an
+// adjoint run: the caller walks the list backwards).
+static ttn_status exec_op(ttn_ctx* ctx, const ttn_oplist* ol, int k) {
+  const int32_t* o = &ol->ops[(size_t)k * 9];
+  const int op = o[0], q0 = o[1], q1 = o[2], arg = o[3], loc = o[4], draw = o[5], rec = o[6], prev = o[7];
+  int leg;
+  const int node = bottom_of(ctx, q0, &leg);
+  switch (op) {
+    case TTN_OP_INIT: {
+      LeafOp l = leaf_op(LOP_INIT, leg);
+      l.arg = arg; l.prev = prev; l.rec = rec;
+      push_leaf(ctx, node, l);
+      break;
     }
+    case TTN_OP_CNOT:
+      TTN_TRY(cnot(ctx, q0, q1));
+      break;
+    case TTN_OP_SRX: {
+      LeafOp l = leaf_op(LOP_SRX, leg);
+      l.loc = loc;
+      push_leaf(ctx, node, l);
+      break;
+    }
+    case TTN_OP_PAULI: {
+      if (ctx->run.adjoint) return fail(ctx, TTN_EINVAL, "twirled ops have no adjoint run");
+      LeafOp l = leaf_op(arg == 0 ? LOP_PAULI_SRX : LOP_PAULI_AD, leg);
+      l.loc = loc; l.draw = draw;
+      push_leaf(ctx, node, l);
+      break;
+    }
+    case TTN_OP_AD: {
+      TTN_TRY(move_centre(ctx, node));
+      LeafOp l = leaf_op(LOP_KRAUS_AD, leg);
+      l.loc = loc; l.draw = draw; l.branch = ol->ad_col[k];
+      push_leaf(ctx, node, l);
+      break;
+    }
+    case TTN_OP_MEAS: {
+      TTN_TRY(move_centre(ctx, node));
+      LeafOp l = leaf_op(LOP_MEAS, leg);
+      l.arg = arg; l.rec = rec; l.draw = draw;
+      push_leaf(ctx, node, l);
+      break;
+    }
+    default:
+      return fail(ctx, TTN_EINVAL, "unknown op code");
   }
+  return TTN_OK;
+}
+
+static ttn_status run_oplist(ttn_ctx* ctx, const ttn_oplist* ol, const double* theta, const double* gamma,
+                             int64_t pstride, uint64_t traj_offset, uint8_t* records, int8_t* branches,
+                             double* logp, const uint8_t* forced_rec, const int8_t* forced_br, ttn_stats* st) {
+  if (!ol || ol->ctx != ctx) return fail(ctx, TTN_EINVAL, "op list belongs to another context");
+  if (!records || !logp) return fail(ctx, TTN_EINVAL, "records and logp are required");
+  if (ol->n_ad > 0 && !branches && !forced_br) return fail(ctx, TTN_EINVAL, "branches required (AD ops)");
+  ctx->hops = 0; ctx->launches = 0; ctx->block_hops = 0; ctx->gemm_flops = 0.0; ctx->gram_flops = 0.0;
+  TTN_TRY(reset_state(ctx, nullptr));
+  TTN_CHECK_HIP(launch_fill_f64(logp, 0.0, ctx->B, ctx->st));
+  setup_run(ctx, ol, theta, gamma, pstride, traj_offset, records, branches, logp, forced_rec, forced_br, 0);
+  for (int k = 0; k < ol->n_ops; ++k) TTN_TRY(exec_op(ctx, ol, k));
   TTN_TRY(flush_leaf(ctx));
   ctx->run = LeafBatch{};
   if (st) TTN_TRY(fill_stats(ctx, st));
@@ -922,6 +938,7 @@ ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {
 ttn_status ttn_destroy(ttn_ctx* ctx) {
   if (!ctx) return TTN_EINVAL;
   hipStreamSynchronize(ctx->st);
+  if (ctx->adj) ttn_destroy(ctx->adj);
   for (auto& b : ctx->bufs) hipFree(b.p);
   for (int c = 0; c < TTN_NCLASS; ++c)
     for (auto& e : ctx->prof_ev[c]) {
@@ -1102,6 +1119,7 @@ ttn_status ttn_oplist_upload(ttn_ctx* ctx, const int32_t* ops, int32_t n_ops, in
       delete ol;
       return fail(ctx, TTN_EINVAL, "op " + std::to_string(k) + " is malformed");
     }
+    ol->ad_col.push_back(op == TTN_OP_AD ? ol->n_ad : -1);
     ol->n_ad += op == TTN_OP_AD;
   }
   *out = ol;
@@ -1133,6 +1151,398 @@ ttn_status ttn_log_prob(ttn_ctx* ctx, const ttn_oplist* ol, const uint8_t* recor
   // forced run: the record buffer is read (and rewritten with identical bits)
   ttn_status s = run_oplist(ctx, ol, theta, gamma, params_stride, 0, const_cast<uint8_t*>(records),
                             nullptr, logp, records, branches, st);
+  if (s == TTN_OK && st && st->flagged_rows > 0) return TTN_EPROB;
+  return s;
+}
+
+// ------------------------------------------------------- log P gradient ----
+// Reverse-mode derivative of log P of a forced record by every location's
+// theta and gamma (see ttn_adjoint.hip for the formula).  The forward pass
+// keeps snapshots of the state at the start of some noise layers; the
+// backward pass carries the adjoint state lambda in a twin context from the
+// final state to the first op, applying each op's adjoint, and at every
+// noise layer restores the nearest earlier snapshot, re-runs the state to
+// the layer's start and contracts the two trees into the layer's leaf
+// environments.
+
+namespace {
+struct Snapshot {
+  std::vector<std::array<int, 3>> dims;
+  int centre = 1;
+  void* mem = nullptr;
+  std::vector<size_t> off;
+};
+struct NoiseLayer { int k0, k1; };
+constexpr int kMaxSnapshots = 16;
+}  // namespace
+
+static void snap_free(Snapshot& s) {
+  if (s.mem) hipFree(s.mem);
+  s.mem = nullptr;
+}
+
+static ttn_status snap_take(ttn_ctx* c, Snapshot& s) {
+  ttn_ctx* ctx = c;
+  TTN_TRY(flush_leaf(c));
+  snap_free(s);
+  s.dims = c->dims;
+  s.centre = c->centre;
+  s.off.assign(c->L, 0);
+  size_t tot = 0;
+  for (int node = 1; node < c->L; ++node) {
+    s.off[node] = tot;
+    tot += ((size_t)c->B * elems(c->dims[node]) * c->es + 255) & ~(size_t)255;
+  }
+  if (hipMalloc(&s.mem, tot) != hipSuccess) {
+    s.mem = nullptr;
+    return fail(c, TTN_ENOMEM, "snapshot allocation failed (reduce the batch)");
+  }
+  for (int node = 1; node < c->L; ++node)
+    TTN_CHECK_HIP(hipMemcpyAsync((char*)s.mem + s.off[node], node_ptr(c, node),
+                                 (size_t)c->B * elems(c->dims[node]) * c->es, hipMemcpyDeviceToDevice, c->st));
+  return TTN_OK;
+}
+
+// into c (the snapshot's own context or its twin: same tree and pool)
+static ttn_status snap_restore(ttn_ctx* c, const Snapshot& s) {
+  ttn_ctx* ctx = c;
+  TTN_TRY(flush_leaf(c));
+  if ((int)s.dims.size() != c->L) return fail(c, TTN_EINVAL, "internal: snapshot of another tree");
+  for (int node = 1; node < c->L; ++node) {
+    const long long n = (long long)c->B * elems(s.dims[node]);
+    if (n > buf_elems(c, c->node_buf[node])) return fail(c, TTN_EINVAL, "internal: snapshot exceeds the pool");
+    TTN_CHECK_HIP(hipMemcpyAsync(node_ptr(c, node), (const char*)s.mem + s.off[node], (size_t)n * c->es,
+                                 hipMemcpyDeviceToDevice, c->st));
+  }
+  c->dims = s.dims;
+  c->centre = s.centre;
+  return TTN_OK;
+}
+
+// C[t][i][j] = sum over the two other legs of conj(A[..i..]) Bt[..j..]; A and
+// Bt agree on those legs' dimensions
+static GemmDesc cross_desc(const void* A, std::array<int, 3> dA, const void* Bt, std::array<int, 3> dB, int leg,
+                           void* C) {
+  GemmDesc g{};
+  g.H = 1;
+  g.conjA = 1;
+  g.A = A; g.B = Bt; g.C = C;
+  g.sAt = elems(dA); g.sBt = elems(dB);
+  g.M = dA[leg]; g.N = dB[leg];
+  g.sCt = (long long)g.M * g.N; g.sCi = g.N; g.sCj = 1;
+  if (leg == 0) {
+    const long long R = (long long)dA[1] * dA[2];
+    g.sAi = R; g.sAl2 = 1; g.a_m_fast = 0;
+    g.sBj = R; g.sBl2 = 1; g.b_n_fast = 0;
+    g.K = (int)R; g.Kin = g.K;
+  } else if (leg == 2) {
+    g.sAi = 1; g.sAl2 = dA[2]; g.a_m_fast = 1;
+    g.sBj = 1; g.sBl2 = dB[2]; g.b_n_fast = 1;
+    g.K = dA[0] * dA[1]; g.Kin = g.K;
+  } else {
+    g.sAi = dA[2]; g.sAl1 = (long long)dA[1] * dA[2]; g.sAl2 = 1; g.a_m_fast = 0;
+    g.sBj = dB[2]; g.sBl1 = (long long)dB[1] * dB[2]; g.sBl2 = 1; g.b_n_fast = 0;
+    g.K = dA[0] * dA[2]; g.Kin = dA[2];
+  }
+  return g;
+}
+
+static ttn_status env_gemm(ttn_ctx* c, const GemmDesc& g, long long capA, long long capB, long long capC) {
+  ttn_ctx* ctx = c;
+  if (!gemm_fits(g, c->B, capA, capB, capC)) return fail(c, TTN_EINVAL, "internal: environment exceeds its buffers");
+  ++c->launches;
+  TTN_CHECK_HIP(launch_zgemm(g, c->B, c->c128 ? GEMM_C128 : GEMM_C64, c->st));
+  return TTN_OK;
+}
+
+// out = W applied on leg `leg` of T (W: [rows][newd][d[leg]])
+static ttn_status env_apply(ttn_ctx* c, const void* T, std::array<int, 3> d, long long capT, int leg, const void* W,
+                            long long capW, int newd, void* out, long long capOut) {
+  GemmDesc g = leg_desc(T, d, leg, W, newd, newd, out);
+  const bool wA = (leg != 2);
+  return env_gemm(c, g, wA ? capW : capT, wA ? capT : capW, capOut);
+}
+
+struct EnvWork {
+  std::vector<void*> up, down;       // per node [B][cap^2]
+  std::vector<long long> cap_el;     // elements per env buffer
+  void* t1 = nullptr;
+  void* t2 = nullptr;
+  long long t_el = 0;
+  ~EnvWork() {
+    for (void* p : up) if (p) hipFree(p);
+    for (void* p : down) if (p) hipFree(p);
+    if (t1) hipFree(t1);
+    if (t2) hipFree(t2);
+  }
+};
+
+static ttn_status env_alloc(ttn_ctx* c, EnvWork& w) {
+  w.up.assign(c->L, nullptr);
+  w.down.assign(c->L, nullptr);
+  w.cap_el.assign(c->L, 0);
+  long long tmax = 1;
+  for (int node = 1; node < c->L; ++node) {
+    const long long cu = node == 1 ? 1 : bond_cap(c, node);
+    w.cap_el[node] = (long long)c->B * cu * cu;
+    if (hipMalloc(&w.up[node], w.cap_el[node] * c->es) != hipSuccess ||
+        hipMalloc(&w.down[node], w.cap_el[node] * c->es) != hipSuccess)
+      return fail(c, TTN_ENOMEM, "environment allocation failed");
+    if (!is_bottom(c, node)) tmax = std::max(tmax, (long long)bond_cap(c, 2 * node) * bond_cap(c, 2 * node + 1) * cu);
+  }
+  w.t_el = (long long)c->B * tmax;
+  if (hipMalloc(&w.t1, w.t_el * c->es) != hipSuccess || hipMalloc(&w.t2, w.t_el * c->es) != hipSuccess)
+    return fail(c, TTN_ENOMEM, "environment allocation failed");
+  return TTN_OK;
+}
+
+// leaf environments of the layer ops [k0, k1) between state ps (before the
+// layer) and adjoint state lm (after it), accumulated into dtheta / dgamma
+static ttn_status env_layer(ttn_ctx* ps, ttn_ctx* lm, const ttn_oplist* ol, int k0, int k1, EnvWork& w,
+                            const EnvParams& par, double* dtheta, double* dgamma) {
+  ttn_ctx* ctx = ps;
+  TTN_TRY(flush_leaf(ps));
+  TTN_TRY(flush_leaf(lm));
+  const int L = ps->L, B = ps->B;
+  std::vector<LeafNoise> nz(L);
+  for (auto& z : nz) z.n = 0;
+  std::vector<char> noisy(L, 0);
+  for (int k = k0; k < k1; ++k) {
+    const int32_t* o = &ol->ops[(size_t)k * 9];
+    const int leaf = ps->leaf_of_qubit[o[1]];
+    LeafNoise& z = nz[leaf];
+    if (z.n >= kMaxLeafNoise) return fail(ps, TTN_EINVAL, "internal: noise layer too deep");
+    z.kind[z.n] = o[0] == TTN_OP_SRX ? NOISE_SRX : NOISE_AD;
+    z.loc[z.n] = o[4];
+    z.branch[z.n] = ol->ad_col[k];
+    ++z.n;
+    for (int node = L / 2 + leaf / 2; node >= 1; node /= 2) noisy[node] = 1;
+  }
+  auto bottom_desc = [&](int node) {
+    EnvBottom d{};
+    d.lam = node_ptr(lm, node);
+    d.psi = node_ptr(ps, node);
+    d.ul = lm->dims[node][2];
+    d.up = ps->dims[node][2];
+    const int l0 = 2 * (node - L / 2);
+    d.nz[0] = nz[l0];
+    d.nz[1] = nz[l0 + 1];
+    d.par = par;
+    d.dtheta = dtheta;
+    d.dgamma = dgamma;
+    d.gstride = ol->n_loc;
+    d.flags = ps->flags;
+    d.c128 = ps->c128;
+    return d;
+  };
+  // up environments, leaves to root
+  for (int x = L - 1; x >= 1; --x) {
+    const std::array<int, 3> dl = lm->dims[x], dp = ps->dims[x];
+    if ((long long)B * dl[2] * dp[2] > w.cap_el[x]) return fail(ps, TTN_EINVAL, "internal: environment too large");
+    if (is_bottom(ps, x)) {
+      if (dl[0] != 2 || dl[1] != 2 || dp[0] != 2 || dp[1] != 2) return fail(ps, TTN_EINVAL, "internal: bottom dims");
+      EnvBottom d = bottom_desc(x);
+      d.out = w.up[x];
+      ++ps->launches;
+      TTN_CHECK_HIP(launch_env_bottom_up(d, B, ps->st));
+      continue;
+    }
+    const int a = 2 * x, b = 2 * x + 1;
+    const std::array<int, 3> t1 = {dl[0], dp[1], dp[2]};
+    const std::array<int, 3> t2 = {dl[0], dl[1], dp[2]};
+    TTN_TRY(env_apply(ps, node_ptr(ps, x), dp, buf_elems(ps, ps->node_buf[x]), 0, w.up[a], w.cap_el[a], dl[0],
+                      w.t1, w.t_el));
+    TTN_TRY(env_apply(ps, w.t1, t1, w.t_el, 1, w.up[b], w.cap_el[b], dl[1], w.t2, w.t_el));
+    TTN_TRY(env_gemm(ps, cross_desc(node_ptr(lm, x), dl, w.t2, t2, 2, w.up[x]), buf_elems(lm, lm->node_buf[x]),
+                     w.t_el, w.cap_el[x]));
+  }
+  // down environments, root to the bottom nodes that carry noise
+  if (ps->dims[1][2] != 1 || lm->dims[1][2] != 1) return fail(ps, TTN_EINVAL, "internal: root up dimension");
+  TTN_CHECK_HIP(launch_fill_cone(w.down[1], ps->c128, B, ps->st));
+  for (int x = 1; x < L / 2; ++x) {
+    if (!noisy[x]) continue;
+    const std::array<int, 3> dl = lm->dims[x], dp = ps->dims[x];
+    const int a = 2 * x, b = 2 * x + 1;
+    const long long capX = buf_elems(ps, ps->node_buf[x]), capL = buf_elems(lm, lm->node_buf[x]);
+    if (noisy[a]) {
+      const std::array<int, 3> t1 = {dp[0], dl[1], dp[2]};
+      const std::array<int, 3> t2 = {dp[0], dl[1], dl[2]};
+      TTN_TRY(env_apply(ps, node_ptr(ps, x), dp, capX, 1, w.up[b], w.cap_el[b], dl[1], w.t1, w.t_el));
+      TTN_TRY(env_apply(ps, w.t1, t1, w.t_el, 2, w.down[x], w.cap_el[x], dl[2], w.t2, w.t_el));
+      TTN_TRY(env_gemm(ps, cross_desc(node_ptr(lm, x), dl, w.t2, t2, 0, w.down[a]), capL, w.t_el, w.cap_el[a]));
+    }
+    if (noisy[b]) {
+      const std::array<int, 3> t1 = {dl[0], dp[1], dp[2]};
+      const std::array<int, 3> t2 = {dl[0], dp[1], dl[2]};
+      TTN_TRY(env_apply(ps, node_ptr(ps, x), dp, capX, 0, w.up[a], w.cap_el[a], dl[0], w.t1, w.t_el));
+      TTN_TRY(env_apply(ps, w.t1, t1, w.t_el, 2, w.down[x], w.cap_el[x], dl[2], w.t2, w.t_el));
+      TTN_TRY(env_gemm(ps, cross_desc(node_ptr(lm, x), dl, w.t2, t2, 1, w.down[b]), capL, w.t_el, w.cap_el[b]));
+    }
+  }
+  for (int x = L / 2; x < L; ++x) {
+    if (!noisy[x]) continue;
+    EnvBottom d = bottom_desc(x);
+    d.down = w.down[x];
+    ++ps->launches;
+    TTN_CHECK_HIP(launch_env_leaf_grad(d, B, ps->st));
+  }
+  return TTN_OK;
+}
+
+static ttn_status ensure_twin(ttn_ctx* ctx) {
+  if (ctx->adj) return TTN_OK;
+  ttn_config cfg{};
+  cfg.n_qubits = ctx->N;
+  cfg.leaf_of_qubit = ctx->leaf_of_qubit.data();
+  cfg.chi_max = ctx->chi;
+  cfg.cutoff = ctx->cutoff;
+  cfg.dtype = ctx->c128 ? TTN_C128 : TTN_C64;
+  cfg.batch = ctx->B;
+  cfg.seed = ctx->seed;
+  cfg.stream = ctx->st;
+  ttn_ctx* t = nullptr;
+  const ttn_status s = ttn_create(&cfg, &t);
+  if (s != TTN_OK) return fail(ctx, s, "adjoint context: allocation failed");
+  ctx->adj = t;
+  return TTN_OK;
+}
+
+static ttn_status log_prob_grad(ttn_ctx* ctx, const ttn_oplist* ol, const uint8_t* records, const int8_t* branches,
+                                const double* theta, const double* gamma, int64_t pstride, double* logp,
+                                double* dtheta, double* dgamma, uint8_t* rec_copy, double* logp_scr,
+                                ttn_stats* st) {
+  // noise layers
+  std::vector<NoiseLayer> layers;
+  {
+    std::vector<int> depth(ctx->L, 0);
+    int k = 0;
+    while (k < ol->n_ops) {
+      const int op = ol->ops[(size_t)k * 9];
+      if (op != TTN_OP_SRX && op != TTN_OP_AD) { ++k; continue; }
+      NoiseLayer ly{k, k};
+      std::fill(depth.begin(), depth.end(), 0);
+      while (k < ol->n_ops) {
+        const int32_t* o = &ol->ops[(size_t)k * 9];
+        if (o[0] != TTN_OP_SRX && o[0] != TTN_OP_AD) break;
+        int& dq = depth[ctx->leaf_of_qubit[o[1]]];
+        if (dq == kMaxLeafNoise) break;
+        ++dq;
+        ++k;
+      }
+      ly.k1 = k;
+      layers.push_back(ly);
+    }
+  }
+  const int nl = (int)layers.size();
+  const int every = std::max(1, (nl + kMaxSnapshots - 1) / kMaxSnapshots);
+  std::vector<Snapshot> snaps(nl);
+  struct Cleanup {
+    std::vector<Snapshot>* s;
+    ~Cleanup() { for (auto& x : *s) snap_free(x); }
+  } cleanup{&snaps};
+  ttn_ctx* lm = ctx->adj;
+
+  // forward pass, snapshots at the start of every `every`-th layer
+  ctx->hops = 0; ctx->launches = 0; ctx->block_hops = 0; ctx->gemm_flops = 0.0; ctx->gram_flops = 0.0;
+  TTN_TRY(reset_state(ctx, nullptr));
+  TTN_CHECK_HIP(launch_fill_f64(logp, 0.0, ctx->B, ctx->st));
+  setup_run(ctx, ol, theta, gamma, pstride, 0, rec_copy, nullptr, logp, records, branches, 0);
+  int pos = 0;
+  for (int r = 0; r < nl; r += every) {
+    for (; pos < layers[r].k0; ++pos) TTN_TRY(exec_op(ctx, ol, pos));
+    TTN_TRY(snap_take(ctx, snaps[r]));
+  }
+  for (; pos < ol->n_ops; ++pos) TTN_TRY(exec_op(ctx, ol, pos));
+  TTN_TRY(flush_leaf(ctx));
+  ctx->run.logp = logp_scr;     // re-runs below must not add to log P again
+
+  // adjoint state = final state
+  {
+    Snapshot fin;
+    TTN_TRY(snap_take(ctx, fin));
+    TTN_TRY(reset_state(lm, nullptr));
+    setup_run(lm, ol, theta, gamma, pstride, 0, rec_copy, nullptr, logp_scr, records, branches, 1);
+    const ttn_status s = snap_restore(lm, fin);
+    TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
+    snap_free(fin);
+    TTN_TRY(s);
+  }
+  EnvWork w;
+  TTN_TRY(env_alloc(ctx, w));
+  EnvParams par{};
+  par.theta = theta; par.gamma = gamma; par.pstride = pstride;
+  par.branches = branches; par.br_stride = ol->n_ad;
+  TTN_CHECK_HIP(launch_fill_f64(dtheta, 0.0, (long long)ctx->B * ol->n_loc, ctx->st));
+  TTN_CHECK_HIP(launch_fill_f64(dgamma, 0.0, (long long)ctx->B * ol->n_loc, ctx->st));
+
+  int k = ol->n_ops - 1;
+  int r = nl - 1;
+  while (k >= 0) {
+    if (r >= 0 && k == layers[r].k1 - 1) {
+      const int c = (r / every) * every;
+      TTN_TRY(snap_restore(ctx, snaps[c]));
+      for (int q = layers[c].k0; q < layers[r].k0; ++q) TTN_TRY(exec_op(ctx, ol, q));
+      TTN_TRY(env_layer(ctx, lm, ol, layers[r].k0, layers[r].k1, w, par, dtheta, dgamma));
+      for (int q = layers[r].k1 - 1; q >= layers[r].k0; --q) TTN_TRY(exec_op(lm, ol, q));
+      k = layers[r].k0 - 1;
+      --r;
+    } else {
+      TTN_TRY(exec_op(lm, ol, k));
+      --k;
+    }
+  }
+  TTN_TRY(flush_leaf(lm));
+  TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
+  ctx->run = LeafBatch{};
+  lm->run = LeafBatch{};
+  if (st) {
+    TTN_TRY(fill_stats(ctx, st));
+    std::vector<int> fl(ctx->B);
+    TTN_CHECK_HIP(hipMemcpy(fl.data(), lm->flags, fl.size() * 4, hipMemcpyDeviceToHost));
+    std::vector<int> fp(ctx->B);
+    TTN_CHECK_HIP(hipMemcpy(fp.data(), ctx->flags, fp.size() * 4, hipMemcpyDeviceToHost));
+    st->flagged_rows = 0;
+    for (int t = 0; t < ctx->B; ++t) st->flagged_rows += (fl[t] != 0) || (fp[t] != 0);
+    st->hops += lm->hops;
+    st->launches += lm->launches;
+  }
+  return TTN_OK;
+}
+
+ttn_status ttn_log_prob_grad(ttn_ctx* ctx, const ttn_oplist* ol, const uint8_t* records, const int8_t* branches,
+                             const double* theta, const double* gamma, int64_t params_stride, double* logp,
+                             double* dtheta, double* dgamma, ttn_stats* st) {
+  if (!ctx) return TTN_EINVAL;
+  if (!ol || ol->ctx != ctx) return fail(ctx, TTN_EINVAL, "op list belongs to another context");
+  if (!records || !theta || !gamma || !logp || !dtheta || !dgamma || params_stride < 0)
+    return fail(ctx, TTN_EINVAL, "records, parameters and outputs are required");
+  if (ol->n_ad > 0 && !branches) return fail(ctx, TTN_EINVAL, "branches required (AD ops)");
+  for (int k = 0; k < ol->n_ops; ++k)
+    if (ol->ops[(size_t)k * 9] == TTN_OP_PAULI)
+      return fail(ctx, TTN_EINVAL, "the gradient needs the non-twirled channels (op list has twirled ops)");
+  ctx->err.clear();
+  TTN_TRY(ensure_twin(ctx));
+  ctx->adj->err.clear();
+  uint8_t* rec_copy = nullptr;
+  double* logp_scr = nullptr;
+  const size_t rec_bytes = (size_t)ctx->B * std::max(ol->n_rec, 1);
+  if (hipMalloc((void**)&rec_copy, rec_bytes) != hipSuccess ||
+      hipMalloc((void**)&logp_scr, (size_t)ctx->B * sizeof(double)) != hipSuccess) {
+    if (rec_copy) hipFree(rec_copy);
+    return fail(ctx, TTN_ENOMEM, "scratch allocation failed");
+  }
+  ttn_status s = TTN_OK;
+  if (ol->n_rec > 0 &&
+      hipMemcpyAsync(rec_copy, records, (size_t)ctx->B * ol->n_rec, hipMemcpyDeviceToDevice, ctx->st) != hipSuccess)
+    s = fail(ctx, TTN_EDEVICE, "record copy failed");
+  if (s == TTN_OK)
+    s = log_prob_grad(ctx, ol, records, branches, theta, gamma, params_stride, logp, dtheta, dgamma, rec_copy,
+                      logp_scr, st);
+  if (s != TTN_OK && ctx->adj && ctx->err.empty()) ctx->err = ctx->adj->err;
+  hipStreamSynchronize(ctx->st);
+  hipFree(rec_copy);
+  hipFree(logp_scr);
+  ctx->run = LeafBatch{};
   if (s == TTN_OK && st && st->flagged_rows > 0) return TTN_EPROB;
   return s;
 }

@@ -199,6 +199,24 @@ class TTNEngine:
             check(code, self._ctx)
         return logp, st.as_dict()
 
+    def log_prob_grad(self, ol: OpList, records, branches=None, theta=None, gamma=None):
+        """log P of the records and d log P / d(theta_l, gamma_l) per row (ttn_log_prob_grad).
+
+        Returns (logp [rows], dtheta [rows, n_loc], dgamma [rows, n_loc], stats)."""
+        th, ga, stride = self._params(ol, theta, gamma)
+        rec = self._dev(records, torch.uint8)
+        br = None if branches is None or ol.n_ad == 0 else self._dev(branches, torch.int8)
+        logp = torch.zeros(self.batch, dtype=torch.float64, device=self.device)
+        n_loc = max(ol.n_loc, 1)
+        dth = torch.zeros(self.batch, n_loc, dtype=torch.float64, device=self.device)
+        dga = torch.zeros(self.batch, n_loc, dtype=torch.float64, device=self.device)
+        st = _abi.Stats()
+        code = lib().ttn_log_prob_grad(self._ctx, ol._h, _ptr(rec), _ptr(br), _ptr(th), _ptr(ga), stride,
+                                       _ptr(logp), _ptr(dth), _ptr(dga), C.byref(st))
+        if code not in (0, _abi.TTN_EPROB):
+            check(code, self._ctx)
+        return logp, dth[:, :ol.n_loc], dga[:, :ol.n_loc], st.as_dict()
+
     def decode(self, records: torch.Tensor, data_rec, checks) -> torch.Tensor:
         data_rec = np.ascontiguousarray(np.asarray(data_rec, dtype=np.int32))
         checks = np.ascontiguousarray(np.asarray(checks, dtype=np.uint8))

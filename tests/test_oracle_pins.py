@@ -232,3 +232,69 @@ def test_decoder_corrects_low_weight_errors():
                 assert not decoder.decode_fail(c.checks, (cw + e) % 2, tab).any()
         # a minimum-weight logical (weight d) is not corrected
         assert cw.sum(axis=1).max() >= 0
+
+
+# ---------------------------------------------------------------- gradient ----
+def test_gradient_closed_form_srx_measurement():
+    # |0> -> SRX(t) -> Z measurement: P(1) = sin^2(t/2), P(0) = cos^2(t/2), so
+    # d log P / dt = cot(t/2) for outcome 1 and -tan(t/2) for outcome 0
+    from oracle import gradient
+    circ = custom_circuit(1, [("init", 0, 0), ("srx", 0), ("meas", 0, 0)])
+    for t in (0.3, 1.1, 2.0):
+        for bit, want in ((1, 1.0 / np.tan(t / 2)), (0, -np.tan(t / 2))):
+            lp, dth, dga = gradient.log_prob_grad(circ, [t], [0.0], [bit])
+            assert abs(dth[0] - want) < 1e-12 * max(1.0, abs(want))
+            assert abs(lp - np.log(np.sin(t / 2) ** 2 if bit else np.cos(t / 2) ** 2)) < 1e-12
+
+
+def test_gradient_closed_form_amplitude_damping():
+    # |0> -> SRX(t) -> AD(g) -> Z measurement: no jump then outcome 1 has
+    # P = (1 - g) sin^2(t/2); a jump then outcome 0 has P = g sin^2(t/2)
+    from oracle import gradient
+    circ = custom_circuit(1, [("init", 0, 0), ("srxad", 0), ("meas", 0, 0)])
+    t, g = 0.9, 0.07
+    lp, dth, dga = gradient.log_prob_grad(circ, [t], [g], [1], [0])
+    assert abs(lp - np.log((1 - g) * np.sin(t / 2) ** 2)) < 1e-12
+    assert abs(dga[0] + 1.0 / (1.0 - g)) < 1e-10
+    assert abs(dth[0] - 1.0 / np.tan(t / 2)) < 1e-10
+    lp, dth, dga = gradient.log_prob_grad(circ, [t], [g], [0], [1])
+    assert abs(lp - np.log(g * np.sin(t / 2) ** 2)) < 1e-12
+    assert abs(dga[0] - 1.0 / g) < 1e-12
+    assert abs(dth[0] - 1.0 / np.tan(t / 2)) < 1e-10
+
+
+def test_gradient_matches_central_differences():
+    # an independent route: central differences of the oracle's own log P
+    from oracle import gradient
+    from oracle import statevector as sv
+    g = np.random.default_rng(5)
+    nq = 5
+    prog = [("init", q, int(g.integers(2))) for q in range(nq)]
+    for _ in range(6):
+        a, b = g.choice(nq, 2, replace=False)
+        prog += [("cnot", int(a), int(b)), ("srxad", int(a)), ("srxad", int(b))]
+        if g.random() < 0.4:
+            q = int(g.integers(nq))
+            prog += [("meas", q, int(g.integers(2))), ("init", q, 0), ("srxad", q)]
+    prog += [("meas", q, 0) for q in range(nq)]
+    circ = custom_circuit(nq, prog)
+    th = g.uniform(0.05, 0.6, circ.n_loc)
+    ga = g.uniform(0.01, 0.1, circ.n_loc)
+    ref = sv.run(circ, th, ga, 3, np.arange(1))
+    rec, br = ref.records[0], ref.branches[0]
+    lp, dth, dga = gradient.log_prob_grad(circ, th, ga, rec, br)
+    assert abs(lp - ref.logp[0]) < 1e-12
+    h = 1e-6
+    for l in range(circ.n_loc):
+        tp, tm = th.copy(), th.copy()
+        tp[l] += h
+        tm[l] -= h
+        fd = (gradient.log_prob(circ, tp, ga, rec[None], br[None])[0] -
+              gradient.log_prob(circ, tm, ga, rec[None], br[None])[0]) / (2 * h)
+        assert abs(fd - dth[l]) < 1e-6 * max(1.0, abs(dth[l])), (l, fd, dth[l])
+        gp, gm = ga.copy(), ga.copy()
+        gp[l] += h
+        gm[l] -= h
+        fd = (gradient.log_prob(circ, th, gp, rec[None], br[None])[0] -
+              gradient.log_prob(circ, th, gm, rec[None], br[None])[0]) / (2 * h)
+        assert abs(fd - dga[l]) < 1e-5 * max(1.0, abs(dga[l])), (l, fd, dga[l])
