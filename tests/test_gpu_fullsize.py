@@ -1,0 +1,83 @@
+"""Parity at the full d=5 size, in the batched launch configuration of the
+benchmark (complex64, 256 trajectories, chi_max = 64, cutoff 1e-10, theta on
+the 8-point grid over the rows), through the C ABI.
+
+The non-Pauli d=5 circuits have no dense oracle (28 live qubits), so the
+parity case at this size is the Pauli-twirled twin of the same channel: its
+states are stabilizer states, which the tableau oracle reproduces exactly.
+With the clustered layout (App. B) the circuit's exact bond dimension is 16,
+so chi_max = 64 truncates nothing and every record must agree bit for bit,
+except where a draw falls within the complex64 resolution of a probability
+(such rows are excluded and counted)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from workload import build_circuit, exact_bond_dim  # noqa: E402
+from oracle import chp, rng  # noqa: E402
+
+THETAS = np.array([0.02 + i * (0.2 - 0.02) / 7 for i in range(8)])
+
+
+def _theta_rows(circ, rows):
+    return np.repeat(THETAS[np.arange(rows) % 8][:, None], circ.n_loc, axis=1)
+
+
+def _near_ties(circ, seed, rows, eps=1e-6):
+    # rows with any draw within eps of 1/2 (the probability of every random
+    # stabilizer outcome) or of a twirl threshold cos^2(theta/2)
+    U = rng.uniforms(seed, np.arange(rows), circ.n_draws)
+    th = THETAS[np.arange(rows) % 8]
+    bad = np.any(np.abs(U - 0.5) < eps, axis=1)
+    bad |= np.any(np.abs(U - np.cos(th / 2)[:, None] ** 2) < eps, axis=1)
+    return bad
+
+
+@pytest.mark.parametrize("dtype,rows", [("c64", 256), ("c128", 16)])
+def test_d5_twirled_records_match_tableau(dtype, rows):
+    from paper_2511_05719_amd import TTNEngine
+    circ = build_circuit(5, 5, "pta_srx", leaf_of_qubit="optimized")
+    assert exact_bond_dim(circ.ops, circ.n_qubits, circ.leaf_of_qubit) <= 64
+    seed = 2
+    th = _theta_rows(circ, rows)
+    eng = TTNEngine(circ.n_qubits, rows, circ.leaf_of_qubit, chi_max=64, cutoff=1e-10, dtype=dtype, seed=seed)
+    res = eng.run_circuit(eng.upload(circ), theta=th, gamma=0.0)
+    recs, _ = chp.run(circ, th, 0.0, seed, np.arange(rows))
+    got = res.records.cpu().numpy()
+    same = np.all(got == recs, axis=1)
+    ties = _near_ties(circ, seed, rows)
+    assert np.all(same | ties), np.nonzero(~same & ~ties)[0]
+    assert same.mean() >= 0.99
+    assert res.stats["flagged_rows"] == 0
+    assert res.stats["max_rank"] <= 16
+    # log P: every random outcome has probability 1/2, every other one 1
+    lp = res.logp.cpu().numpy()
+    k = np.round(-lp / np.log(2.0))
+    assert np.all(np.abs(lp + k * np.log(2.0)) < (1e-5 if dtype == "c64" else 1e-10))
+    eng.close()
+
+
+def test_d5_srx_complex64_matches_complex128():
+    # the non-Pauli channel at d=5, one round, clustered layout, the bench's
+    # theta grid: the batched complex64 run and a complex128 run of the same
+    # trajectories must draw the same records except where a draw lands
+    # within the complex64 resolution of a probability (here <= 2% of rows),
+    # with log P equal to complex64 precision on the rows that agree
+    from paper_2511_05719_amd import TTNEngine
+    circ = build_circuit(5, 1, "srx", leaf_of_qubit="optimized")
+    rows = 256
+    th = _theta_rows(circ, rows)
+    out = {}
+    for dtype in ("c64", "c128"):
+        eng = TTNEngine(circ.n_qubits, rows, circ.leaf_of_qubit, chi_max=64, cutoff=1e-10, dtype=dtype, seed=2)
+        res = eng.run_circuit(eng.upload(circ), theta=th, gamma=0.0)
+        assert res.stats["flagged_rows"] == 0
+        out[dtype] = (res.records.cpu().numpy(), res.logp.cpu().numpy(), res.stats)
+        eng.close()
+    (r64, l64, s64), (r128, l128, s128) = out["c64"], out["c128"]
+    same = np.all(r64 == r128, axis=1)
+    assert same.mean() >= 0.98, same.mean()
+    assert np.abs(l64[same] - l128[same]).max() < 1e-4
+    assert np.all(np.isfinite(l128)) and np.all(l128 <= 1e-9)

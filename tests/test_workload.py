@@ -105,3 +105,45 @@ def test_indices_dense():
     recs = ops[ops[:, C_OP] == OP_MEAS][:, C_REC]
     assert sorted(recs.tolist()) == list(range(circ.n_rec))
     assert circ.n_ad == circ.count(OP_AD) == circ.n_loc
+
+
+# ------------------------------------------------------------------ layout ----
+def test_layout_exact_bond_dims_match_table_iii():
+    # App. B, Table III (C = 1): d=3 default 8 / optimized 8; d=5 default 512 /
+    # optimized 16 (the Clifford skeleton already needs the tabulated values)
+    from workload import exact_bond_dim, optimized_layout
+    for d, want_def, want_opt in ((3, 8, 8), (5, 512, 16)):
+        circ = build_circuit(d, 1, "none")
+        assert exact_bond_dim(circ.ops, circ.n_qubits, circ.leaf_of_qubit) == want_def
+        lay, chi = optimized_layout(circ.ops, circ.n_qubits)
+        assert chi <= want_opt
+        assert sorted(set(lay.tolist())) == sorted(lay.tolist())
+        assert lay.min() >= 0 and lay.max() < circ.n_leaves
+        assert exact_bond_dim(circ.ops, circ.n_qubits, lay) == chi
+
+
+def test_layout_exact_bond_dim_matches_oracle_stabilizer_ranks():
+    # the compile-time scorer against the oracle's tableau + Schmidt ranks,
+    # on random layouts, over every op of the circuit
+    from workload import exact_bond_dim
+    from oracle import chp, stabrank
+    g = np.random.default_rng(3)
+    for trial in range(3):
+        circ0 = build_circuit(3, 1, "none")
+        lay = g.permutation(circ0.n_leaves)[:circ0.n_qubits].astype(np.int32)
+        circ = build_circuit(3, 1, "none", leaf_of_qubit=lay)
+        best = 1
+        for k in range(circ.n_ops):
+            _, tab = chp.run(circ, 0.0, 0.0, 0, np.arange(1), stop_after_op=k)
+            r = stabrank.tree_bond_ranks(tab.stabilizers(), circ.leaf_of_qubit, circ.n_leaves)
+            best = max(best, max(r.values()))
+        assert exact_bond_dim(circ.ops, circ.n_qubits, circ.leaf_of_qubit) == best
+
+
+def test_optimized_layout_keeps_the_circuit():
+    # the layout moves qubits between leaves; the op list is the same circuit
+    a = build_circuit(5, 2, "srx")
+    b = build_circuit(5, 2, "srx", leaf_of_qubit="optimized")
+    assert a.n_ops == b.n_ops and a.n_loc == b.n_loc and a.n_rec == b.n_rec
+    key = lambda ops: sorted(map(tuple, ops[:, [0, 1, 2, 3, 8]].tolist()))
+    assert key(a.ops) == key(b.ops)

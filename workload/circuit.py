@@ -133,14 +133,21 @@ def n_leaves_for(n_qubits: int) -> int:
 
 
 def build_circuit(d: int, rounds: int, channel: str,
-                  leaf_of_qubit: np.ndarray | None = None) -> Circuit:
+                  leaf_of_qubit: np.ndarray | str | None = None) -> Circuit:
+    """leaf_of_qubit: an explicit qubit -> leaf map, "default" / None (qubit i
+    on leaf i), or "optimized" (App. B, Algorithm 1: best of 8 clustered
+    layouts by the exact bond dimension of the circuit's Clifford skeleton)."""
     if channel not in CHANNELS:
         raise ValueError(f"unknown channel {channel!r}")
     if rounds < 1:
         raise ValueError("rounds must be >= 1")
     code = build_color_code(d)
     N = code.n_qubits
-    if leaf_of_qubit is None:
+    if isinstance(leaf_of_qubit, str) and leaf_of_qubit == "optimized":
+        from .layout import optimized_layout
+        skeleton = build_circuit(d, rounds, "none")
+        leaf_of_qubit, _ = optimized_layout(skeleton.ops, N)
+    elif leaf_of_qubit is None or (isinstance(leaf_of_qubit, str) and leaf_of_qubit == "default"):
         leaf_of_qubit = default_layout(code)
     leaf_of_qubit = np.asarray(leaf_of_qubit, dtype=np.int32)
     L = n_leaves_for(N)
