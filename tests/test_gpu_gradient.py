@@ -120,3 +120,38 @@ def test_twirled_op_list_is_rejected():
     with pytest.raises(TTNError):
         eng.log_prob_grad(eng.upload(circ), rec, None, theta=0.1, gamma=0.0)
     eng.close()
+
+
+def test_d5_gradient_matches_central_differences():
+    # d=5 colour code (37 qubits), one round, amplitude damping gamma = 5e-3
+    # at every location, clustered layout: the exact bond dimension (32) is
+    # within chi_max = 64, so the run is untruncated and the adjoint must
+    # equal central differences (step 1e-4) of the engine's own complex128
+    # log P.  (With SRX added the state needs more than 64 Schmidt values at
+    # d=5, the log P being differentiated is then a truncated one, and the
+    # theta derivatives are checked against the oracle at d=3 instead.)
+    circ = build_circuit(5, 1, "ad", leaf_of_qubit="optimized")
+    rows = 8
+    eng = _engine(circ, rows, "c128", seed=4)
+    ol = eng.upload(circ)
+    res = eng.run_circuit(ol, theta=0.0, gamma=5e-3)
+    assert abs(res.stats["discarded_weight"]) < 1e-12 * rows
+    rec, br = res.records.clone(), res.branches.clone()
+    lp, dth, dga, st = eng.log_prob_grad(ol, rec, br, theta=0.0, gamma=5e-3)
+    assert st["flagged_rows"] == 0
+    assert np.abs(lp.cpu().numpy() - res.logp.cpu().numpy()).max() < 1e-9
+    dga = dga.cpu().numpy()
+    h = 1e-4
+    g = np.random.default_rng(17)
+    for l in g.choice(circ.n_loc, 6, replace=False):
+        ga = np.full((rows, circ.n_loc), 5e-3)
+        ga[:, l] += h
+        lpp, _ = eng.log_prob(ol, rec, br, theta=0.0, gamma=ga)
+        ga[:, l] -= 2 * h
+        lpm, _ = eng.log_prob(ol, rec, br, theta=0.0, gamma=ga)
+        fd = ((lpp - lpm) / (2 * h)).cpu().numpy()
+        # central-difference error (h^2 times the third derivative) plus the
+        # rounding of log P divided by h
+        err = np.max(np.abs(fd - dga[:, l]) / np.maximum(1.0, np.abs(dga[:, l])))
+        assert err < 1e-6, (l, fd, dga[:, l])
+    eng.close()
