@@ -94,6 +94,60 @@ def run_plain(args, circ):
     return (t1 - t0) / args.plain_shots
 
 
+def run_optimized(args):
+    """The same workload with the clustered qubit-to-leaf layout (App. B)."""
+    import torch
+    from paper_2511_05719_amd import TTNEngine
+    from workload import build_circuit, exact_bond_dim
+    circ = build_circuit(5, args.rounds, "srx", leaf_of_qubit="optimized")
+    B = args.batch
+    eng = TTNEngine(circ.n_qubits, B, circ.leaf_of_qubit, chi_max=64, cutoff=1e-10, dtype="c64", seed=args.seed)
+    ol = eng.upload(circ)
+    eng.run_circuit(ol, theta=theta_rows(circ, B, 0), traj_offset=0, stats=False)
+    torch.cuda.synchronize()
+    steps = 2
+    t0 = time.perf_counter()
+    for k in range(steps):
+        res = eng.run_circuit(ol, theta=theta_rows(circ, B, (k + 1) * B), traj_offset=(k + 1) * B, stats=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = eng.run_circuit(ol, theta=theta_rows(circ, B, B), traj_offset=B, stats=True).stats
+    p_fail = float(eng.decode(res.records, circ.data_rec, circ.code.checks).float().mean().item())
+    eng.close()
+    shots = steps * B / dt
+    return {"layout": "clustered (App. B, Algorithm 1)", "batch": B, "steps": steps,
+            "shots_per_s": shots, "trajectory_gates_per_s": shots * circ.n_ops,
+            "chi_exact_clifford_skeleton": exact_bond_dim(build_circuit(5, args.rounds, "none",
+                                                                        leaf_of_qubit=circ.leaf_of_qubit).ops,
+                                                          circ.n_qubits, circ.leaf_of_qubit),
+            "p_fail": p_fail, "mean_discarded_weight": st.get("discarded_weight", 0.0) / B,
+            "max_rank": st.get("max_rank")}
+
+
+def run_gradient(args):
+    """log P and its adjoint gradient for records of the differentiation
+    workload (d=5, 3 rounds, SRX theta = 0.1 and AD gamma = 5e-3 at every
+    location, records sampled from the forward model), clustered layout."""
+    import torch
+    from paper_2511_05719_amd import TTNEngine
+    from workload import build_circuit
+    circ = build_circuit(5, 3, "srx+ad", leaf_of_qubit="optimized")
+    B = args.grad_records
+    eng = TTNEngine(circ.n_qubits, B, circ.leaf_of_qubit, chi_max=64, cutoff=1e-10, dtype="c64", seed=4)
+    ol = eng.upload(circ)
+    res = eng.run_circuit(ol, theta=0.1, gamma=5e-3, stats=False)
+    rec, br = res.records.clone(), res.branches.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lp, dth, dga, st = eng.log_prob_grad(ol, rec, br, theta=0.1, gamma=5e-3)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    eng.close()
+    return {"workload": "d=5 colour code, 3 rounds, SRX theta=0.1 + AD gamma=5e-3, chi_max=64, complex64, "
+                        "clustered layout", "records": B, "parameters_per_record": 2 * circ.n_loc,
+            "seconds": dt, "records_per_s": B / dt, "flagged_rows": st.get("flagged_rows")}
+
+
 def cpu_oracle(circ, seed):
     """The FP64 oracle (lazy-ancilla state vector, numpy, one thread) on the
     same circuit: ops 47-54 of one trajectory, all on the full 28-qubit live
@@ -125,9 +179,11 @@ def main():
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--rounds", type=int, default=5)
     ap.add_argument("--seed", type=int, default=2)
-    ap.add_argument("--plain-shots", type=int, default=2)
+    ap.add_argument("--plain-shots", type=int, default=4)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the clustered-layout and gradient legs")
+    ap.add_argument("--grad-records", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (trajectories shard "
@@ -185,6 +241,12 @@ def main():
         sec = run_plain(args, circ)
         plain = {"dtype": "c128", "batch": 1, "s_per_shot": sec, "shots_per_s": 1.0 / sec,
                  "trajectory_gates_per_s": ops / sec, "shots": args.plain_shots}
+    optimized = grad = None
+    if not args.no_extra:
+        optimized = run_optimized(args)
+        log(f"clustered layout: {optimized['shots_per_s']:.1f} shots/s")
+        grad = run_gradient(args)
+        log(f"gradient: {grad['records_per_s']:.1f} records/s")
     cpu = None
     if not args.no_cpu:
         rate, wall = cpu_oracle(circ, args.seed)
@@ -217,6 +279,8 @@ def main():
         "speedup_vs_plain_c128": (shots_per_s * plain["s_per_shot"]) if plain else None,
         "kernel_time_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
         "kernel_classes": classes,
+        "clustered_layout": optimized,
+        "log_prob_grad": grad,
         "run_stats": {"p_fail": p_fail, "max_rank": st.get("max_rank"),
                       "mean_discarded_weight": st.get("discarded_weight", 0.0) / args.batch,
                       "hops_per_batch": st.get("hops"), "block_hops_per_batch": st.get("block_hops"),

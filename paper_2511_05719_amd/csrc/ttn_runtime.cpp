@@ -429,7 +429,7 @@ static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int ne
   ed.nk_out = ctx->nk;
   // complex64 factors carry ~1e-7 relative error, so off-diagonal Gram
   // entries below 1e-12 of the diagonal change nothing they hold
-  ed.tol = ctx->c128 ? 1e-15 : 1e-12;
+  ed.tol = ctx->c128 ? 1e-15 : 1e-10;
   ed.early_stop = ctx->c128 ? 0 : 1;
   ctx->launches += large ? 2 : 1;
   {
