@@ -13,7 +13,9 @@ A step is one batched run of the whole circuit (2427 ops per trajectory:
 CNOTs, noise ops, initialisations, measurements) for `--batch` trajectories.
 The metric is trajectory-gates/s = trajectories/s x ops per trajectory; the
 same run in complex128, one trajectory at a time (the plain path), and the
-FP64 CPU oracle on a bounded sample are reported beside it.
+FP64 CPU oracle on a bounded sample are reported beside it.  Extra legs: the
+same workload with the clustered qubit-to-leaf layout (App. B), and log P
+with its adjoint gradient for records of the differentiation workload.
 
 Prints one JSON line.  --gpus N > 1 is not supported (one GPU per box).
 """
@@ -174,9 +176,9 @@ def cpu_oracle(circ, seed):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--rounds", type=int, default=5)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--plain-shots", type=int, default=4)

@@ -73,7 +73,7 @@ typedef struct ttn_oplist ttn_oplist;
 typedef struct {
   int32_t n_qubits;              /* N >= 1 */
   const int32_t* leaf_of_qubit;  /* host [n_qubits], injective into [0, L), L = smallest power of 2 >= N (>= 2) */
-  int32_t chi_max;               /* bond-dimension cap (>= 1) */
+  int32_t chi_max;               /* bond-dimension cap (1 .. 128: bonds double to 2 chi_max while a controlled gate rides on them) */
   double cutoff;                 /* keep Schmidt values with s^2 / sum s^2 > cutoff (>= 0) */
   int32_t dtype;                 /* TTN_C64 or TTN_C128 */
   int32_t batch;                 /* B trajectories held by the context (>= 1) */
@@ -248,7 +248,12 @@ double ttn_philox_uniform_host(uint64_t seed, uint64_t traj, uint64_t draw);
  *    ttn_ctx's hops): W_iso[t][a][i] = V[i][a] / s_a, W_abs[t][a][i] =
  *    conj(V[i][a]) s_a / |s_kept|, a < rank[t] in descending s, zero beyond;
  *    rows <= batch, n <= 2 * min(chi_max, ...) of the context; sweeps
- *    (device int32 [rows] or NULL) receives the Jacobi sweep count. */
+ *    (device int32 [rows] or NULL) receives the Jacobi sweep count.
+ *    blocks = 2: G is block diagonal with two n/2 blocks, solved apart; the
+ *    cutoff refers to the whole trace, block b fills rows [b new_pad/2,
+ *    (b+1) new_pad/2) and columns [b n/2, (b+1) n/2) of the factors (zeros
+ *    in the other block's columns), at most cap values per block; rank and
+ *    sweeps are not written. */
 ttn_status ttn_test_leg_apply(ttn_ctx* ctx, int32_t rows, const int32_t* dims3, int32_t leg, const void* T,
                               int64_t t_elems, const void* W, int64_t w_elems, int32_t newd, void* out,
                               int64_t out_elems);
@@ -256,7 +261,7 @@ ttn_status ttn_test_gram(ttn_ctx* ctx, int32_t rows, const int32_t* dims3, int32
                          int64_t t_elems, double* G, int64_t g_elems, int32_t ksplit);
 ttn_status ttn_test_eigh(ttn_ctx* ctx, int32_t rows, int32_t n, int32_t new_pad, int32_t cap, double cutoff,
                          const double* G, int64_t g_elems, void* W_iso, void* W_abs, int64_t w_elems,
-                         int32_t* rank, int32_t* sweeps);
+                         int32_t* rank, int32_t* sweeps, int32_t blocks);
 
 /* Profiling.  While enabled, every kernel launch of the context is
  * bracketed by HIP events on its stream, grouped by kernel class, and the

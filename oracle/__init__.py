@@ -15,6 +15,8 @@ Contents (each module cites the passage of the paper it follows):
   stabrank     Schmidt rank of a stabilizer state across a cut
   closed_forms values the paper's equations fix in closed form
   decoder      final-data lookup decoder and the logical readout
+  gradient     exact derivatives of log P(record) by each location's theta
+               and gamma (shift rules on the state-vector log P)
 
 Every function is plain, slow and written to be checked against the paper by
 eye; precision is float64 / complex128 throughout.

@@ -135,23 +135,28 @@ __device__ void write_factors(const EighDesc& d, const Problem& pb, int row_lo, 
 // VT: element type of the eigenvector matrix kept in LDS (kVinLds).  Runs
 // whose factors are complex64 accumulate it in complex64, which halves its
 // LDS footprint so that two problems share a CU.
-template <bool kVinLds, int NT, typename VT>
+// NMAX: largest problem size; above 128 the packed G (526 KB at 256) lives in
+// device memory (d.gpk) instead of LDS.
+template <bool kVinLds, int NT, typename VT, int NMAX>
 __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
   extern __shared__ double2 smem[];
-  const Problem pb = problem_of(d, blockIdx.x);
+  const long long pid = blockIdx.x;                    // problem: a row, or (row, block)
+  const Problem pb = problem_of(d, pid);
   const long long t = pb.t;
   const int n = pb.n;
   const int n2 = n + (n & 1);          // even size, a zero dummy index if odd
   const int h = n2 / 2;
   const int npk = n2 * (n2 + 1) / 2;
   const int nblk = h * (h + 1) / 2;
-  double2* Gp = smem;                                  // packed G
+  constexpr bool kGlobalG = NMAX > 128;
+  double2* Gp = kGlobalG ? d.gpk + pid * (long long)(NMAX * (NMAX + 1) / 2) : smem;   // packed G
   VT* V = reinterpret_cast<VT*>(smem + npk);           // [n2][n2] if kVinLds
-  __shared__ Rot rot[64];
-  __shared__ unsigned short blk[2080];                 // (P, Q) of the upper 2x2 blocks
-  __shared__ double lam[128];
-  __shared__ int order_s[128];
+  __shared__ Rot rot[NMAX / 2];
+  __shared__ unsigned short blk[(NMAX / 2) * (NMAX / 2 + 1) / 2];   // (P, Q) of the upper 2x2 blocks
+  __shared__ double lam[NMAX];
+  __shared__ int order_s[NMAX];
   __shared__ double red[NT];
+  __shared__ double wave_ratio[NT / 64];
   __shared__ int any_rot;
   __shared__ double sweep_ratio;
   __shared__ double trace_s;
@@ -186,7 +191,7 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
   const bool finite = isfinite(tr) && tr > 0.0;
 
   int step_count = 0, sweeps_done = 0;
-  double* log = d.rot_log ? d.rot_log + t * (long long)d.max_steps * h * 3 : nullptr;
+  double* log = d.rot_log ? d.rot_log + pid * d.log_stride : nullptr;
   const double tol = d.tol > 0.0 ? d.tol : 1e-15;
   const double stop_ratio = d.early_stop ? 0.25 * sqrt(tol) : 0.0;
   if (n2 >= 2 && finite) {
@@ -277,11 +282,17 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
         __syncthreads();
       }
       ++sweeps_done;
-      // the rotation threads are wavefront 0 (h <= 64)
-      if (threadIdx.x < 64) {
+      // the rotation threads are the first h <= NMAX / 2 (one or two wavefronts)
+      if (threadIdx.x < NMAX / 2) {
         double m = my_ratio;
         for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
-        if (threadIdx.x == 0) sweep_ratio = m;
+        if ((threadIdx.x & 63) == 0) wave_ratio[threadIdx.x >> 6] = m;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int w = 0; w * 64 < NMAX / 2 && w < NT / 64; ++w) m = fmax(m, wave_ratio[w]);
+        sweep_ratio = m;
       }
       __syncthreads();
       if (any_rot == 0 || sweep_ratio < stop_ratio) break;
@@ -356,14 +367,14 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
     k_s = k;
     if (d.sweeps_out) d.sweeps_out[t] = sweeps_done;
     if (!kVinLds) {
-      d.kept[t] = k;
-      d.scale_abs[t] = scale_s;
-      d.nsteps[t] = step_count;
+      d.kept[pid] = k;
+      d.scale_abs[pid] = scale_s;
+      d.nsteps[pid] = step_count;
     }
   }
   __syncthreads();
   if (kVinLds) {
-    __shared__ double lam_sorted[128];
+    __shared__ double lam_sorted[NMAX];
     for (int a = threadIdx.x; a < n; a += blockDim.x) lam_sorted[a] = lam[order_s[a]];
     __syncthreads();
     if (d.out_c128)
@@ -372,63 +383,69 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
       write_factors<float2>(d, pb, 0, n, V, n2, order_s, lam_sorted, k_s, scale_s);
   } else {
     for (int a = threadIdx.x; a < n; a += blockDim.x) {
-      d.order[t * n + a] = order_s[a];
-      d.lam_sorted[t * n + a] = lam[order_s[a]];
+      d.order[pid * n + a] = order_s[a];
+      d.lam_sorted[pid * n + a] = lam[order_s[a]];
     }
   }
 }
 
-// Kept eigenvectors of a single-block problem of size > 64 from the rotation
-// log.  V = J_1 J_2 ... J_S, so column c of V is J_1 (J_2 (... (J_S e_c))):
-// the log is replayed in reverse on the unit vectors of the kept columns
-// only.  Columns are independent, so each wavefront owns a few of them in
-// LDS and runs through the log with no workgroup barrier; lane j applies the
-// rotation of pair j of every step.
-constexpr int kVecWaves = 16;
-constexpr int kVecCols = 4;     // columns per wave: 16 x 4 = 64 >= kept count
-__global__ void __launch_bounds__(kVecWaves * 64) k_jacobi_vectors(EighDesc d) {
-  __shared__ double2 X[kVecWaves][kVecCols][128];
-  __shared__ int order_s[128];
-  __shared__ double lam_s[128];
-  const int n = d.n;
+// Kept eigenvectors of a problem of size > 64 from the rotation log.
+// V = J_1 J_2 ... J_S, so column c of V is J_1 (J_2 (... (J_S e_c))): the log
+// is replayed in reverse on the unit vectors of the kept columns only.
+// Columns are independent, so each wavefront owns a few of them in LDS and
+// runs through the log with no workgroup barrier; lane j applies the
+// rotations of pairs j and j + 64 of every step (disjoint index pairs).
+// One workgroup per problem (a row, or one diagonal block of a row).
+constexpr int kVecCols = 4;     // columns per wave and pass
+template <int NMAX>
+__global__ void __launch_bounds__(1024) k_jacobi_vectors(EighDesc d) {
+  constexpr int W = NMAX > 128 ? 8 : 16;       // waves: W * 4 columns of NMAX entries in 128 KB
+  __shared__ double2 X[W][kVecCols][NMAX];
+  __shared__ int order_s[NMAX];
+  __shared__ double lam_s[NMAX];
+  const long long pid = blockIdx.x;
+  const Problem pb = problem_of(d, pid);
+  const long long t = pb.t;
+  const int n = pb.n;
   const int n2 = n + (n & 1);
   const int h = n2 / 2;
-  const long long t = blockIdx.x;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int k = d.kept[t];
-  for (int a = threadIdx.x; a < n; a += blockDim.x) {
-    order_s[a] = d.order[t * n + a];
-    lam_s[a] = d.lam_sorted[t * n + a];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;   // launched with W waves
+  const int k = d.kept[pid];
+  for (int a = threadIdx.x; a < n; a += W * 64) {
+    order_s[a] = d.order[pid * n + a];
+    lam_s[a] = d.lam_sorted[pid * n + a];
   }
   __syncthreads();
-  const int steps = d.nsteps[t];
-  const double* log = d.rot_log + t * (long long)d.max_steps * h * 3;
-  const double sc = d.scale_abs[t];
+  const int steps = d.nsteps[pid];
+  const double* log = d.rot_log + pid * d.log_stride;
+  const double sc = d.scale_abs[pid];
   const bool c128 = d.out_c128 != 0;
-  const int per_pass = kVecWaves * kVecCols;
-  for (int base = 0; base < d.new_pad; base += per_pass) {
+  const int per_pass = W * kVecCols;
+  for (int base = 0; base < pb.pad; base += per_pass) {
     int ncol = 0;
     for (int cc = 0; cc < kVecCols; ++cc) {
-      const int a = base + wave + cc * kVecWaves;
+      const int a = base + wave + cc * W;
       if (a < k) ncol = cc + 1;
       for (int i = lane; i < n2; i += 64)
         X[wave][cc][i] = make_double2((a < k && i == order_s[a]) ? 1.0 : 0.0, 0.0);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
-    if (ncol > 0 && lane < h) {
+    if (ncol > 0) {
       int s = (steps - 1) % (n2 - 1);
       for (int st = steps - 1; st >= 0; --st) {
-        const double* e = log + ((long long)st * h + lane) * 3;
-        const double c = e[0];
-        const double2 sv = make_double2(e[1], e[2]);
-        if (!(c == 1.0 && sv.x == 0.0 && sv.y == 0.0)) {
-          int p, q;
-          pair_of(n2, s, lane, &p, &q);
-          for (int cc = 0; cc < ncol; ++cc) {
-            const double2 xp = X[wave][cc][p], xq = X[wave][cc][q];
-            X[wave][cc][p] = cadd(cscale(xp, c), cmul(sv, xq));
-            X[wave][cc][q] = csub(cscale(xq, c), cmul(cconj(sv), xp));
+        for (int P = lane; P < h; P += 64) {
+          const double* e = log + ((long long)st * h + P) * 3;
+          const double c = e[0];
+          const double2 sv = make_double2(e[1], e[2]);
+          if (!(c == 1.0 && sv.x == 0.0 && sv.y == 0.0)) {
+            int p, q;
+            pair_of(n2, s, P, &p, &q);
+            for (int cc = 0; cc < ncol; ++cc) {
+              const double2 xp = X[wave][cc][p], xq = X[wave][cc][q];
+              X[wave][cc][p] = cadd(cscale(xp, c), cmul(sv, xq));
+              X[wave][cc][q] = csub(cscale(xq, c), cmul(cconj(sv), xp));
+            }
           }
         }
         // the next (earlier) step touches entries other lanes just wrote
@@ -438,19 +455,25 @@ __global__ void __launch_bounds__(kVecWaves * 64) k_jacobi_vectors(EighDesc d) {
       }
     }
     __syncthreads();
-    // W_iso[a][i] = V[i][order a] / s_a,  W_abs[a][i] = conj(V[i][order a]) s_a scale
-    const int rows = min(per_pass, d.new_pad - base);
-    for (int idx = threadIdx.x; idx < rows * n; idx += blockDim.x) {
-      const int al = idx / n, i = idx - (idx / n) * n;
+    // rows pad_off + a of W: W_iso[a][off + i] = V[i][order a] / s_a,
+    // W_abs[a][off + i] = conj(V[i][order a]) s_a scale; zeros in the other
+    // block's columns
+    const int rows = min(per_pass, pb.pad - base);
+    const int ncols = d.blocks > 1 ? 2 * n : n;
+    for (int idx = threadIdx.x; idx < rows * ncols; idx += W * 64) {
+      const int al = idx / ncols, ic = idx - (idx / ncols) * ncols;
       const int a = base + al;
+      const bool own = ic < n;
+      const int i = own ? ic : ic - n;
       double2 wi = make_double2(0.0, 0.0), wa = make_double2(0.0, 0.0);
-      if (a < k) {
-        const double2 v = X[al % kVecWaves][al / kVecWaves][i];
+      if (own && a < k) {
+        const double2 v = X[al % W][al / W][i];
         const double sv = sqrt(lam_s[a]);
         wi = cscale(v, 1.0 / sv);
         wa = cscale(cconj(v), sv * sc);
       }
-      const long long o = t * (long long)d.new_pad * n + (long long)a * n + i;
+      const int col = own ? pb.off + i : (1 - pb.k) * pb.n + i;
+      const long long o = t * (long long)d.new_pad * d.n + (long long)(pb.pad_off + a) * d.n + col;
       if (c128) {
         ((double2*)d.W_iso)[o] = wi;
         ((double2*)d.W_abs)[o] = wa;
@@ -671,14 +694,14 @@ static bool g_attr_done = false;
 hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st) {
   if (batch <= 0) return hipSuccess;
   const int nb = d.blocks > 1 ? 2 : 1;
-  if (d.n < 1 || d.n > 128 || d.new_pad < 1 || (nb == 2 && ((d.n & 1) || (d.new_pad & 1))))
+  if (d.n < 1 || d.n > 256 || d.new_pad < 1 || (nb == 2 && ((d.n & 1) || (d.new_pad & 1))))
     return hipErrorInvalidValue;
   if (!g_attr_done) {
-    hipFuncSetAttribute((const void*)k_jacobi<true, kThreadsSmall, double2>,
+    hipFuncSetAttribute((const void*)k_jacobi<true, kThreadsSmall, double2, 128>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
-    hipFuncSetAttribute((const void*)k_jacobi<true, kThreadsSmall, float2>,
+    hipFuncSetAttribute((const void*)k_jacobi<true, kThreadsSmall, float2, 128>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
-    hipFuncSetAttribute((const void*)k_jacobi<false, kThreadsLarge, double2>,
+    hipFuncSetAttribute((const void*)k_jacobi<false, kThreadsLarge, double2, 128>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
     g_attr_done = true;
   }
@@ -696,24 +719,34 @@ hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st) {
     else hipLaunchKernelGGL(k_jacobi_wave<32>, dim3(grid), dim3(256), 0, st, d, nprob);
     return hipGetLastError();
   }
+  const dim3 grid((unsigned)nprob);
   if (n2 <= kVLdsMax) {
-    const dim3 grid((unsigned)((long long)batch * nb));
     if (d.out_c128)
-      hipLaunchKernelGGL((k_jacobi<true, kThreadsSmall, double2>), grid, dim3(kThreadsSmall),
+      hipLaunchKernelGGL((k_jacobi<true, kThreadsSmall, double2, 128>), grid, dim3(kThreadsSmall),
                          gbytes + (size_t)n2 * n2 * sizeof(double2), st, d);
     else
-      hipLaunchKernelGGL((k_jacobi<true, kThreadsSmall, float2>), grid, dim3(kThreadsSmall),
+      hipLaunchKernelGGL((k_jacobi<true, kThreadsSmall, float2, 128>), grid, dim3(kThreadsSmall),
                          gbytes + (size_t)n2 * n2 * sizeof(float2), st, d);
     return hipGetLastError();
   }
-  if (nb != 1) return hipErrorInvalidValue;
+  // problems above 64: rotation log, then the kept columns replayed from it
   if (!d.rot_log || !d.order || !d.lam_sorted || !d.kept || !d.scale_abs || !d.nsteps)
     return hipErrorInvalidValue;
-  if ((long long)d.max_steps < (long long)kMaxSweeps * (n2 - 1)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_jacobi<false, kThreadsLarge, double2>), dim3(batch), dim3(kThreadsLarge), gbytes, st, d);
+  if ((long long)d.max_steps < (long long)kMaxSweeps * (n2 - 1) ||
+      d.log_stride < (long long)kMaxSweeps * (n2 - 1) * (n2 / 2) * 3)
+    return hipErrorInvalidValue;
+  if (n2 <= 128) {
+    hipLaunchKernelGGL((k_jacobi<false, kThreadsLarge, double2, 128>), grid, dim3(kThreadsLarge), gbytes, st, d);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_jacobi_vectors<128>, grid, dim3(16 * 64), 0, st, d);
+    return hipGetLastError();
+  }
+  if (n2 > 256 || !d.gpk) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_jacobi<false, kThreadsLarge, double2, 256>), grid, dim3(kThreadsLarge), 0, st, d);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_jacobi_vectors, dim3((unsigned)batch), dim3(kVecWaves * 64), 0, st, d);
+  hipLaunchKernelGGL(k_jacobi_vectors<256>, grid, dim3(8 * 64), 0, st, d);
   return hipGetLastError();
 }
 

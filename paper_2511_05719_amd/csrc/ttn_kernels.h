@@ -53,8 +53,8 @@ struct EighDesc {
   double* disc_acc;     // [batch] += discarded weight fraction
   int* flags;           // [batch] |= 1 on non-finite / zero norm
   int* degen_acc;       // [batch] += 1 on a cut inside a near-degenerate cluster
-  // workspace for n > 64
-  double* rot_log;      // [batch][max_steps][n/2][3]
+  // workspace for n > 64 (per problem: a row, or a diagonal block of a row)
+  double* rot_log;      // [problems][log_stride]: per step, (c, s) of each pair
   int max_steps;
   double* lam_sorted;   // [batch][n]
   int* order;           // [batch][n]
@@ -66,6 +66,8 @@ struct EighDesc {
   int early_stop;       // 1: stop after a sweep whose rotated ratios all stayed below sqrt(tol) / 4
   int gsplit;           // G is the sum of gsplit partial products (0 or 1: one)
   long long gslice;     // element stride between them
+  long long log_stride; // doubles of rot_log per problem (problem = row, or (row, block))
+  double2* gpk;         // problems of size > 128: packed G in device memory, [batch][256 * 257 / 2]
 };
 hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st);
 int eigh_max_sweeps();

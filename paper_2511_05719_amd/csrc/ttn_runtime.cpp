@@ -85,6 +85,8 @@ struct ttn_ctx {
   void* Wa = nullptr;
   double* rot_log = nullptr;
   int max_steps = 0;
+  long long log_stride = 0;    // doubles of rot_log per eigen-problem
+  double2* gpk = nullptr;      // packed Gram matrices of problems above 128 (device memory)
   double* lam_sorted = nullptr;
   int* order = nullptr;
   int* kept = nullptr;
@@ -385,6 +387,13 @@ static ttn_status gram(ttn_ctx* ctx, int src_buf, std::array<int, 3> d, int leg,
   return TTN_OK;
 }
 
+// eigensolver workspaces of the context
+static void eigh_ws(const ttn_ctx* ctx, EighDesc& ed) {
+  ed.rot_log = ctx->rot_log; ed.max_steps = ctx->max_steps; ed.log_stride = ctx->log_stride;
+  ed.lam_sorted = ctx->lam_sorted; ed.order = ctx->order; ed.kept = ctx->kept;
+  ed.scale_abs = ctx->scale_abs; ed.nsteps = ctx->nsteps; ed.gpk = ctx->gpk;
+}
+
 // Move the isometry centre from x to its neighbour y (Sec. III.B: the
 // canonical form that makes local Schmidt values and Born probabilities
 // local): factor x = (x V S^-1)(S V^H) across the bond, keep the first factor
@@ -424,8 +433,7 @@ static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int ne
   const bool large = (n / blocks + ((n / blocks) & 1)) > 64;
   ed.flops_acc = ctx->ledger[large ? CLS_EIGH_LARGE : CLS_EIGH_SMALL];
   ed.disc_acc = ctx->disc_acc; ed.flags = ctx->flags; ed.degen_acc = ctx->degen_acc;
-  ed.rot_log = ctx->rot_log; ed.max_steps = ctx->max_steps; ed.lam_sorted = ctx->lam_sorted;
-  ed.order = ctx->order; ed.kept = ctx->kept; ed.scale_abs = ctx->scale_abs; ed.nsteps = ctx->nsteps;
+  eigh_ws(ctx, ed);
   ed.nk_out = ctx->nk;
   // complex64 factors carry ~1e-7 relative error, so off-diagonal Gram
   // entries below 1e-12 of the diagonal change nothing they hold
@@ -853,9 +861,9 @@ ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {
   int nmax = 2;
   for (int e = 2; e < L; ++e) nmax = std::max(nmax, 2 * bond_cap(ctx, e));
   ctx->nmax = nmax;
-  if (nmax > 128) {
+  if (nmax > 256) {
     delete ctx;
-    return TTN_EINVAL;   // the FP64 Jacobi workspace holds bonds up to 128 (chi_max <= 64)
+    return TTN_EINVAL;   // the FP64 Jacobi solver takes bonds up to 256 (chi_max <= 128)
   }
   // node capacities and size classes
   std::vector<size_t> cap_el(L, 0);
@@ -905,12 +913,18 @@ ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {
   ok &= hipMalloc((void**)&ctx->G, ctx->gslices * Bz * n2 * n2 * sizeof(double2)) == hipSuccess;
   ok &= hipMalloc(&ctx->Wi, Bz * n2 * n2 * ctx->es) == hipSuccess;
   ok &= hipMalloc(&ctx->Wa, Bz * n2 * n2 * ctx->es) == hipSuccess;
-  if (n2 > 64) ok &= hipMalloc((void**)&ctx->rot_log, Bz * ctx->max_steps * (n2 / 2) * 3 * sizeof(double)) == hipSuccess;
+  // eigen-problems above 64 keep a rotation log: one per row, or one per
+  // diagonal block when the blocks themselves exceed 64 (bonds above 128)
+  ctx->log_stride = (long long)ctx->max_steps * (n2 / 2) * 3;
+  const size_t log_problems = n2 > 128 ? 2 * Bz : Bz;
+  if (n2 > 64) ok &= hipMalloc((void**)&ctx->rot_log, log_problems * ctx->log_stride * sizeof(double)) == hipSuccess;
+  // (the solver strides the packed matrices by the size of a 256-wide one)
+  if (n2 > 128) ok &= hipMalloc((void**)&ctx->gpk, Bz * (size_t)(256 * 257 / 2) * sizeof(double2)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->lam_sorted, Bz * n2 * sizeof(double)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->order, Bz * n2 * sizeof(int)) == hipSuccess;
-  ok &= hipMalloc((void**)&ctx->kept, Bz * sizeof(int)) == hipSuccess;
-  ok &= hipMalloc((void**)&ctx->scale_abs, Bz * sizeof(double)) == hipSuccess;
-  ok &= hipMalloc((void**)&ctx->nsteps, Bz * sizeof(int)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->kept, 2 * Bz * sizeof(int)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->scale_abs, 2 * Bz * sizeof(double)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->nsteps, 2 * Bz * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->rank_table, Bz * L * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->rank_max, Bz * L * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->ledger_mem, 4 * Bz * sizeof(double)) == hipSuccess;
@@ -945,7 +959,7 @@ ttn_status ttn_destroy(ttn_ctx* ctx) {
       hipEventDestroy(e.first);
       hipEventDestroy(e.second);
     }
-  void* ws[] = {ctx->G, ctx->Wi, ctx->Wa, ctx->rot_log, ctx->lam_sorted, ctx->order, ctx->kept,
+  void* ws[] = {ctx->G, ctx->Wi, ctx->Wa, ctx->rot_log, ctx->gpk, ctx->lam_sorted, ctx->order, ctx->kept,
                 ctx->scale_abs, ctx->nsteps, ctx->rank_table, ctx->rank_max, ctx->ledger_mem,
                 ctx->adim, ctx->nk, ctx->nk_max,
                 ctx->disc_acc, ctx->flags,
@@ -1803,21 +1817,21 @@ ttn_status ttn_test_gram(ttn_ctx* ctx, int32_t rows, const int32_t* dims3, int32
 
 ttn_status ttn_test_eigh(ttn_ctx* ctx, int32_t rows, int32_t n, int32_t new_pad, int32_t cap, double cutoff,
                          const double* G, int64_t g_elems, void* W_iso, void* W_abs, int64_t w_elems,
-                         int32_t* rank, int32_t* sweeps) {
+                         int32_t* rank, int32_t* sweeps, int32_t blocks) {
   if (!ctx) return TTN_EINVAL;
   if (rows < 1 || rows > ctx->B || n < 1 || n > ctx->nmax || new_pad < 1 || new_pad > ctx->nmax || cap < 1 || !G ||
-      !W_iso || !W_abs || !rank)
+      !W_iso || !W_abs || (blocks != 1 && blocks != 2) || (blocks == 1 && !rank) ||
+      (blocks == 2 && ((n & 1) || (new_pad & 1))))
     return fail(ctx, TTN_EINVAL, "bad arguments (rows <= batch, n and new_pad <= workspace)");
   if (g_elems < (int64_t)rows * n * n || w_elems < (int64_t)rows * new_pad * n)
     return fail(ctx, TTN_EINVAL, "buffers too small for the eigen-decomposition");
   EighDesc ed{};
   ed.G = (const double2*)G; ed.n = n; ed.new_pad = new_pad; ed.cap = cap; ed.cutoff = cutoff;
   ed.W_iso = W_iso; ed.W_abs = W_abs; ed.out_c128 = ctx->c128;
-  ed.blocks = 1;
-  ed.sweeps_out = sweeps;
-  ed.rank_out = rank; ed.rank_stride = 1;
-  ed.rot_log = ctx->rot_log; ed.max_steps = ctx->max_steps; ed.lam_sorted = ctx->lam_sorted;
-  ed.order = ctx->order; ed.kept = ctx->kept; ed.scale_abs = ctx->scale_abs; ed.nsteps = ctx->nsteps;
+  ed.blocks = blocks;
+  ed.sweeps_out = blocks == 1 ? sweeps : nullptr;
+  ed.rank_out = blocks == 1 ? rank : nullptr; ed.rank_stride = 1;
+  eigh_ws(ctx, ed);
   ed.nk_out = ctx->prof ? ctx->nk : nullptr;
   TTN_CHECK_HIP(launch_eigh(ed, rows, ctx->st));
   TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));

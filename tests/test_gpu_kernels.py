@@ -99,8 +99,10 @@ def test_gram_fp64(dtype, shape, leg, ksplit):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("n,rank", [(1, 1), (2, 2), (4, 3), (16, 16), (64, 40), (64, 64), (128, 128), (128, 77)])
+@pytest.mark.parametrize("n,rank", [(1, 1), (2, 2), (4, 3), (16, 16), (64, 40), (64, 64), (128, 128), (128, 77),
+                                    (200, 150), (256, 256), (256, 90)])
 def test_eigh_centre_move_factors(dtype, n, rank):
+    # n > 128: chi_max = 128 contexts, packed Gram matrix in device memory
     from paper_2511_05719_amd._abi import lib, check
     g = np.random.default_rng(n * 1000 + rank)
     rows, m = 4, max(n, 8) * 3
@@ -109,7 +111,7 @@ def test_eigh_centre_move_factors(dtype, n, rank):
     M *= (10.0 ** (-np.arange(n) / 12.0))[None, None, :]          # graded spectrum
     M /= np.linalg.norm(M.reshape(rows, -1), axis=1)[:, None, None]
     G = np.einsum("tmi,tmj->tij", M.conj(), M)
-    eng = _engine(dtype)
+    eng = _engine(dtype, chi=128 if n > 128 else 64)
     Gd = torch.view_as_real(torch.as_tensor(G)).contiguous().cuda()
     wdt = torch.float64 if dtype == "c128" else torch.float32
     Wi = torch.zeros(rows, n, n, 2, dtype=wdt, device="cuda")
@@ -117,7 +119,7 @@ def test_eigh_centre_move_factors(dtype, n, rank):
     rk = torch.zeros(rows, dtype=torch.int32, device="cuda")
     cutoff = 1e-13
     check(lib().ttn_test_eigh(eng._ctx, rows, n, n, n, cutoff, Gd.data_ptr(), rows * n * n, Wi.data_ptr(),
-                              Wa.data_ptr(), rows * n * n, rk.data_ptr(), None), eng._ctx)
+                              Wa.data_ptr(), rows * n * n, rk.data_ptr(), None, 1), eng._ctx)
     Wi, Wa, rk = _host_complex(Wi), _host_complex(Wa), rk.cpu().numpy()
     for t in range(rows):
         s = np.linalg.svd(M[t], compute_uv=False)
@@ -157,7 +159,7 @@ def test_eigh_truncation_cap():
     Wa = torch.zeros(rows, cap, n, 2, dtype=torch.float64, device="cuda")
     rk = torch.zeros(rows, dtype=torch.int32, device="cuda")
     check(lib().ttn_test_eigh(eng._ctx, rows, n, cap, cap, 1e-10, Gd.data_ptr(), rows * n * n, Wi.data_ptr(),
-                              Wa.data_ptr(), rows * cap * n, rk.data_ptr(), None), eng._ctx)
+                              Wa.data_ptr(), rows * cap * n, rk.data_ptr(), None, 1), eng._ctx)
     Wi, Wa = _host_complex(Wi), _host_complex(Wa)
     assert (rk.cpu().numpy() == cap).all()
     for t in range(rows):
@@ -166,4 +168,56 @@ def test_eigh_truncation_cap():
         best /= np.linalg.norm(best)
         got = (M[t] @ Wi[t].T) @ Wa[t]                        # renormalised rank-cap truncation
         assert np.abs(got - best).max() < 1e-10
+    eng.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("m", [20, 40, 100, 128])
+def test_eigh_block_diagonal(dtype, m):
+    # a controlled gate's bond: G = diag(G0, G1), each half solved apart
+    # (m <= 64: vectors in LDS; m > 64: rotation log and replay per block);
+    # the cutoff refers to the whole trace, the normalisation is the trace's
+    from paper_2511_05719_amd._abi import lib, check
+    g = np.random.default_rng(m)
+    rows, K, n = 3, 3 * m, 2 * m
+    Ms = []
+    for b in range(2):
+        rank = m if b == 0 else max(1, m // 3)
+        Mb = (g.normal(size=(rows, K, rank)) + 1j * g.normal(size=(rows, K, rank))) @ \
+             (g.normal(size=(rows, rank, m)) + 1j * g.normal(size=(rows, rank, m)))
+        Mb *= (10.0 ** (-np.arange(m) / 15.0))[None, None, :]
+        Ms.append(Mb * (0.8 if b == 0 else 0.3))
+    tot = sum(np.linalg.norm(x.reshape(rows, -1), axis=1) ** 2 for x in Ms)
+    Ms = [x / np.sqrt(tot)[:, None, None] for x in Ms]
+    G = np.zeros((rows, n, n), complex)
+    G[:, :m, :m] = np.einsum("tki,tkj->tij", Ms[0].conj(), Ms[0])
+    G[:, m:, m:] = np.einsum("tki,tkj->tij", Ms[1].conj(), Ms[1])
+    eng = _engine(dtype, chi=128 if n > 128 else 64)
+    Gd = torch.view_as_real(torch.as_tensor(G)).contiguous().cuda()
+    wdt = torch.float64 if dtype == "c128" else torch.float32
+    Wi = torch.full((rows, n, n, 2), 7.0, dtype=wdt, device="cuda")
+    Wa = torch.full((rows, n, n, 2), 7.0, dtype=wdt, device="cuda")
+    cutoff = 1e-12
+    check(lib().ttn_test_eigh(eng._ctx, rows, n, n, m, cutoff, Gd.data_ptr(), rows * n * n, Wi.data_ptr(),
+                              Wa.data_ptr(), rows * n * n, None, None, 2), eng._ctx)
+    Wi, Wa = _host_complex(Wi), _host_complex(Wa)
+    tol = 1e-9 if dtype == "c128" else 3e-5
+    for t in range(rows):
+        for b in range(2):
+            Mb = Ms[b][t]
+            s = np.linalg.svd(Mb, compute_uv=False)
+            k = int((s ** 2 > cutoff).sum())          # the trace is 1
+            rws = slice(b * m, (b + 1) * m)
+            own = slice(b * m, (b + 1) * m)
+            other = slice((1 - b) * m, (2 - b) * m)
+            assert np.all(Wi[t, rws, other] == 0) and np.all(Wa[t, rws, other] == 0)
+            wi, wa = Wi[t, rws, own], Wa[t, rws, own]
+            kept = int(np.sum(np.linalg.norm(wa, axis=1) > 0))
+            assert kept == k, (b, kept, k)
+            assert np.all(wi[k:] == 0) and np.all(wa[k:] == 0)
+            u_, s_, vh_ = np.linalg.svd(Mb, full_matrices=False)
+            Mk = (u_[:, :k] * s_[:k]) @ vh_[:k]
+            U = Mb @ wi[:k].T
+            assert np.abs(U @ wa[:k] - Mk).max() < tol * max(1.0, s[0])
+            assert np.abs(np.linalg.norm(wa[:k], axis=1) - s[:k]).max() < tol * s[0]
     eng.close()

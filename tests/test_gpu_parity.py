@@ -228,3 +228,32 @@ def test_profile_ledger_bounded_by_executed_work():
     assert prof["eigh_small"]["alg_flops"] + prof["eigh_large"]["alg_flops"] > 0
     assert all(v["ms"] >= 0 for v in prof.values())
     eng.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_chi128_random_circuit_amplitudes(dtype):
+    # 15 qubits on 16 leaves with chi_max = 128: the root bond (8 | 7 qubits)
+    # reaches 128, so a controlled gate across it rides a 256-wide bond:
+    # forward moves solve two 128-wide diagonal blocks (rotation log and
+    # replay per block), the truncating sweep back a dense 256-wide problem
+    # (packed Gram matrix in device memory).  chi_max bounds no bond of this
+    # tree, so the run is untruncated.
+    g = np.random.default_rng(31)
+    nq = 15
+    prog = random_program(nq, 24, g, noise=("srx",), measure_every=8)[:-nq]
+    circ = custom_circuit(nq, prog)
+    rows = 2
+    th = g.uniform(0.2, 1.4, (rows, circ.n_loc))
+    eng = _engine(circ, rows, dtype, chi=128, seed=6)
+    res = eng.run_circuit(eng.upload(circ), theta=th, gamma=0.0)
+    assert res.stats["block_hops"] > 0
+    assert res.stats["max_rank"] > 64
+    ref_res, st = sv.run(circ, th, 0.0, 6, np.arange(rows), stop_after_op=circ.n_ops - 1)
+    full = st.full_state(nq)
+    if circ.n_rec:
+        assert np.array_equal(res.records.cpu().numpy(), ref_res.records)
+    tol = _amp_tol(dtype, res.stats["discarded_weight"])
+    for r in range(rows):
+        amp = eng.statevector(r)
+        assert np.abs(amp - full[r]).max() < tol, (r, np.abs(amp - full[r]).max())
+    eng.close()
