@@ -47,7 +47,11 @@ template <> struct MfmaAcc<double> {
   }
 };
 
-constexpr int PADL = 1;
+// LDS row padding of the staged tiles: a 4-byte row stride of 17 (mod 32
+// banks) keeps both the 16 x 4 read pattern of the MFMA operands and a
+// column of 16 staged stores free of bank conflicts; 8-byte elements use 1
+template <typename R> struct Pad { static constexpr int value = 17; };
+template <> struct Pad<double> { static constexpr int value = 1; };
 
 template <typename S> __device__ inline void load_c(const S* p, long long off, double& re, double& im) {
   S v = p[off];
@@ -60,6 +64,7 @@ __global__ void __launch_bounds__(256) k_zgemm(GemmDesc d) {
   static_assert(WM * WN * KW == 4, "four waves per workgroup");
   constexpr int TM = 32 * WM, TN = 32 * WN, TK = 16 * KW;
   constexpr int AE = TM * TK / 256, BE = TN * TK / 256;   // staged elements per thread
+  constexpr int PADL = Pad<R>::value;
   constexpr int STAGE = 2 * TK * (TM + PADL) + 2 * TK * (TN + PADL);
   constexpr int RED = (KW > 1) ? (KW - 1) * 64 * 32 : 0;   // partial accumulators of waves kw > 0
   __shared__ R smem[STAGE > RED ? STAGE : RED];
@@ -175,15 +180,26 @@ __global__ void __launch_bounds__(256) k_zgemm(GemmDesc d) {
         b_re[s] = Bs[0][kr][nj];
         b_im[s] = Bs[1][kr][nj];
       }
+      // the eight accumulators are independent: issue each of the four real
+      // products for all of them before the next, so that consecutive MFMAs
+      // never wait on one another's result
+      R na_im[2] = {-a_im[0], -a_im[1]};
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          acc_re[a][b] = MfmaAcc<R>::mma(a_re[a], b_re[b], acc_re[a][b]);
-          acc_re[a][b] = MfmaAcc<R>::mma(-a_im[a], b_im[b], acc_re[a][b]);
-          acc_im[a][b] = MfmaAcc<R>::mma(a_re[a], b_im[b], acc_im[a][b]);
-          acc_im[a][b] = MfmaAcc<R>::mma(a_im[a], b_re[b], acc_im[a][b]);
-        }
+        for (int b = 0; b < 2; ++b) acc_re[a][b] = MfmaAcc<R>::mma(a_re[a], b_re[b], acc_re[a][b]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc_im[a][b] = MfmaAcc<R>::mma(a_re[a], b_im[b], acc_im[a][b]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc_re[a][b] = MfmaAcc<R>::mma(na_im[a], b_im[b], acc_re[a][b]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc_im[a][b] = MfmaAcc<R>::mma(a_im[a], b_re[b], acc_im[a][b]);
     }
     __syncthreads();
   }
