@@ -89,20 +89,50 @@ __device__ inline Problem problem_of(const EighDesc& d, long long bid) {
   return p;
 }
 
+// Rows of a problem's block of G with a non-zero diagonal, in order.  A
+// Gram matrix with g_ii = 0 has row and column i exactly zero (padding of a
+// bond beyond this trajectory's dimension, or the unused rows of a block),
+// so the eigenproblem is solved on the compacted matrix of the m rows kept:
+// cidx[c] = original row of compacted index c (c < m), inv[i] = c or -1.
+// One original row per thread (pb.n <= blockDim.x); every thread returns m.
+template <int NW>
+__device__ int compact_rows(const EighDesc& d, const double2* G, const Problem& pb, int* cidx, int* inv,
+                            int* wcount) {
+  const int i = threadIdx.x, lane = i & 63, wave = i >> 6;
+  bool nz = false;
+  if (i < pb.n) nz = gram_at(d, G, (long long)(pb.off + i) * d.n + pb.off + i).x > 0.0;
+  const unsigned long long mask = __ballot(nz);
+  if (lane == 0) wcount[wave] = __popcll(mask);
+  __syncthreads();
+  int base = 0, m = 0;
+  for (int w = 0; w < NW; ++w) {
+    if (w < wave) base += wcount[w];
+    m += wcount[w];
+  }
+  if (i < pb.n) {
+    const int c = base + __popcll(mask & ((1ull << lane) - 1ull));
+    inv[i] = nz ? c : -1;
+    if (nz) cidx[c] = i;
+  }
+  __syncthreads();
+  return m;
+}
+
 template <typename S, typename VT>
-__device__ void write_factors(const EighDesc& d, const Problem& pb, int row_lo, int row_hi,
-                              const VT* Vrows /* rows [row_lo,row_hi) x n2 */, int n2, const int* order,
-                              const double* lam_sorted, int k, double scale_abs) {
+__device__ void write_factors(const EighDesc& d, const Problem& pb, const VT* V /* compacted n2 x n2 */,
+                              int n2, const int* inv, const int* order, const double* lam_sorted, int k,
+                              double scale_abs) {
   S* Wi = (S*)d.W_iso + pb.t * (long long)d.new_pad * d.n;
   S* Wa = (S*)d.W_abs + pb.t * (long long)d.new_pad * d.n;
-  const int nrows = row_hi - row_lo;
-  // own block: rows pad_off .. pad_off + pad, columns off + [row_lo, row_hi)
+  const int nrows = pb.n;
+  // own block: rows pad_off .. pad_off + pad, columns off + [0, n); rows of
+  // the block outside the compacted problem get zeros
   for (int idx = threadIdx.x; idx < pb.pad * nrows; idx += blockDim.x) {
     const int a = idx / nrows;
-    const int i = row_lo + idx % nrows;
+    const int i = idx % nrows;
     double2 wi = make_double2(0.0, 0.0), wa = make_double2(0.0, 0.0);
-    if (a < k) {
-      const double2 v = to_d2(Vrows[(long long)(i - row_lo) * n2 + order[a]]);
+    if (a < k && inv[i] >= 0) {
+      const double2 v = to_d2(V[(long long)inv[i] * n2 + order[a]]);
       const double s = sqrt(lam_sorted[a]);
       wi = cscale(v, 1.0 / s);
       wa = cscale(cconj(v), s * scale_abs);
@@ -116,7 +146,7 @@ __device__ void write_factors(const EighDesc& d, const Problem& pb, int row_lo, 
     const int other = (1 - pb.k) * pb.n;
     for (int idx = threadIdx.x; idx < pb.pad * nrows; idx += blockDim.x) {
       const int a = idx / nrows;
-      const int i = row_lo + idx % nrows;
+      const int i = idx % nrows;
       const long long o = (long long)(pb.pad_off + a) * d.n + other + i;
       Wi[o] = from_d2<S>(make_double2(0.0, 0.0));
       Wa[o] = from_d2<S>(make_double2(0.0, 0.0));
@@ -143,7 +173,11 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
   const long long pid = blockIdx.x;                    // problem: a row, or (row, block)
   const Problem pb = problem_of(d, pid);
   const long long t = pb.t;
-  const int n = pb.n;
+  const double2* G = d.G + t * (long long)d.n * d.n;
+  __shared__ int cidx[NMAX];
+  __shared__ int inv[NMAX];
+  __shared__ int wcount[NT / 64];
+  const int n = compact_rows<NT / 64>(d, G, pb, cidx, inv, wcount);   // compacted size
   const int n2 = n + (n & 1);          // even size, a zero dummy index if odd
   const int h = n2 / 2;
   const int npk = n2 * (n2 + 1) / 2;
@@ -160,13 +194,13 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
   __shared__ int any_rot;
   __shared__ double sweep_ratio;
   __shared__ double trace_s;
-  const double2* G = d.G + t * (long long)d.n * d.n;
 
   for (int idx = threadIdx.x; idx < npk; idx += blockDim.x) {
     int i = 0, rem = idx;
     while (rem >= n2 - i) { rem -= n2 - i; ++i; }
     const int j = i + rem;
-    Gp[idx] = (i < n && j < n) ? gram_at(d, G, (long long)(pb.off + i) * d.n + pb.off + j) : make_double2(0.0, 0.0);
+    Gp[idx] = (i < n && j < n) ? gram_at(d, G, (long long)(pb.off + cidx[i]) * d.n + pb.off + cidx[j])
+                               : make_double2(0.0, 0.0);
   }
   for (int idx = threadIdx.x; idx < nblk; idx += blockDim.x) {
     int P = 0, rem = idx;
@@ -378,13 +412,14 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
     for (int a = threadIdx.x; a < n; a += blockDim.x) lam_sorted[a] = lam[order_s[a]];
     __syncthreads();
     if (d.out_c128)
-      write_factors<double2>(d, pb, 0, n, V, n2, order_s, lam_sorted, k_s, scale_s);
+      write_factors<double2>(d, pb, V, n2, inv, order_s, lam_sorted, k_s, scale_s);
     else
-      write_factors<float2>(d, pb, 0, n, V, n2, order_s, lam_sorted, k_s, scale_s);
+      write_factors<float2>(d, pb, V, n2, inv, order_s, lam_sorted, k_s, scale_s);
   } else {
+    // (per problem pb.n slots; the compacted problem uses the first n)
     for (int a = threadIdx.x; a < n; a += blockDim.x) {
-      d.order[pid * n + a] = order_s[a];
-      d.lam_sorted[pid * n + a] = lam[order_s[a]];
+      d.order[pid * pb.n + a] = order_s[a];
+      d.lam_sorted[pid * pb.n + a] = lam[order_s[a]];
     }
   }
 }
@@ -406,14 +441,18 @@ __global__ void __launch_bounds__(1024) k_jacobi_vectors(EighDesc d) {
   const long long pid = blockIdx.x;
   const Problem pb = problem_of(d, pid);
   const long long t = pb.t;
-  const int n = pb.n;
+  // the same compaction as the solver's (G is unchanged)
+  __shared__ int cidx[NMAX];
+  __shared__ int inv[NMAX];
+  __shared__ int wcount[W];
+  const int n = compact_rows<W>(d, d.G + t * (long long)d.n * d.n, pb, cidx, inv, wcount);
   const int n2 = n + (n & 1);
   const int h = n2 / 2;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;   // launched with W waves
   const int k = d.kept[pid];
   for (int a = threadIdx.x; a < n; a += W * 64) {
-    order_s[a] = d.order[pid * n + a];
-    lam_s[a] = d.lam_sorted[pid * n + a];
+    order_s[a] = d.order[pid * pb.n + a];
+    lam_s[a] = d.lam_sorted[pid * pb.n + a];
   }
   __syncthreads();
   const int steps = d.nsteps[pid];
@@ -459,15 +498,15 @@ __global__ void __launch_bounds__(1024) k_jacobi_vectors(EighDesc d) {
     // W_abs[a][off + i] = conj(V[i][order a]) s_a scale; zeros in the other
     // block's columns
     const int rows = min(per_pass, pb.pad - base);
-    const int ncols = d.blocks > 1 ? 2 * n : n;
+    const int ncols = d.blocks > 1 ? 2 * pb.n : pb.n;
     for (int idx = threadIdx.x; idx < rows * ncols; idx += W * 64) {
       const int al = idx / ncols, ic = idx - (idx / ncols) * ncols;
       const int a = base + al;
-      const bool own = ic < n;
-      const int i = own ? ic : ic - n;
+      const bool own = ic < pb.n;
+      const int i = own ? ic : ic - pb.n;
       double2 wi = make_double2(0.0, 0.0), wa = make_double2(0.0, 0.0);
-      if (own && a < k) {
-        const double2 v = X[al % W][al / W][i];
+      if (own && a < k && inv[i] >= 0) {
+        const double2 v = X[al % W][al / W][inv[i]];
         const double sv = sqrt(lam_s[a]);
         wi = cscale(v, 1.0 / sv);
         wa = cscale(cconj(v), sv * sc);
@@ -500,20 +539,35 @@ __global__ void __launch_bounds__(256) k_jacobi_wave(EighDesc d, long long nprob
   __shared__ Rot rots[PER][NMAX / 2 > 0 ? NMAX / 2 : 1];
   __shared__ double lam_s[PER][NMAX];
   __shared__ int order_s[PER][NMAX];
+  __shared__ int cidx_s[PER][NMAX];
+  __shared__ int inv_s[PER][NMAX];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const long long bid = (long long)blockIdx.x * PER + wave;
   if (bid >= nprob) return;                    // whole wavefront leaves; no workgroup barriers below
   const Problem pb = problem_of(d, bid);
   const long long t = pb.t;
-  const int n = pb.n;
+  const double2* Gg = d.G + t * (long long)d.n * d.n;
+  // compaction to the rows with a non-zero diagonal (as compact_rows)
+  int* cidx = cidx_s[wave];
+  int* inv = inv_s[wave];
+  const bool nz = lane < pb.n && gram_at(d, Gg, (long long)(pb.off + lane) * d.n + pb.off + lane).x > 0.0;
+  const unsigned long long mask = __ballot(nz);
+  const int n = __popcll(mask);
+  if (lane < pb.n) {
+    const int c = __popcll(mask & ((1ull << lane) - 1ull));
+    inv[lane] = nz ? c : -1;
+    if (nz) cidx[c] = lane;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
   const int n2 = n + (n & 1);
   const int h = n2 / 2;
   double2* G = Gs[wave];
   double2* V = Vs[wave];
-  const double2* Gg = d.G + t * (long long)d.n * d.n;
   for (int idx = lane; idx < n2 * n2; idx += 64) {
     const int i = idx / n2, j = idx - (idx / n2) * n2;
-    G[idx] = (i < n && j < n) ? gram_at(d, Gg, (long long)(pb.off + i) * d.n + pb.off + j) : make_double2(0.0, 0.0);
+    G[idx] = (i < n && j < n) ? gram_at(d, Gg, (long long)(pb.off + cidx[i]) * d.n + pb.off + cidx[j])
+                              : make_double2(0.0, 0.0);
     V[idx] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   double part = 0.0;
@@ -668,11 +722,12 @@ __global__ void __launch_bounds__(256) k_jacobi_wave(EighDesc d, long long nprob
   }
   // factors: own block rows, and zeros in the other block's columns
   const int ncols = d.n;
-  for (int idx = lane; idx < pb.pad * n; idx += 64) {
-    const int a = idx / n, i = idx - (idx / n) * n;
+  const int nr = pb.n;
+  for (int idx = lane; idx < pb.pad * nr; idx += 64) {
+    const int a = idx / nr, i = idx - (idx / nr) * nr;
     double2 wi = make_double2(0.0, 0.0), wa = make_double2(0.0, 0.0);
-    if (a < k) {
-      const double2 v = V[i * n2 + order_s[wave][a]];
+    if (a < k && inv[i] >= 0) {
+      const double2 v = V[inv[i] * n2 + order_s[wave][a]];
       const double sv = sqrt(lam_s[wave][order_s[wave][a]]);
       wi = cscale(v, 1.0 / sv);
       wa = cscale(cconj(v), sv * scale);

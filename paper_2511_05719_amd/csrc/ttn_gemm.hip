@@ -93,11 +93,28 @@ __global__ void __launch_bounds__(256) k_zgemm(GemmDesc d) {
   const R sgnA = d.conjA ? (R)-1 : (R)1;
   const R sgnB = d.conjB ? (R)-1 : (R)1;
 
+  // this trajectory's extents: rows, columns and K terms that can be
+  // non-zero; a tile beyond them only writes its zeros
+  int Mt = d.M, Nt = d.N, Kt = d.K, Kin = d.Kin;
+  if (d.ext) {
+    const int* ex = d.ext + t * d.ext_stride;
+    const int kn = d.knew ? d.knew[t * 4] : 0;
+    auto extent = [&](int e) { return e < 0 ? kn : ex[e]; };
+    int ht = d.H, ko = d.K / d.Kin, ki = d.Kin;
+    if (d.eM) Mt = min(Mt, extent(d.eM) * d.mM);
+    if (d.eN) Nt = min(Nt, extent(d.eN) * d.mN);
+    if (d.eH) ht = min(ht, extent(d.eH));
+    if (d.eKo) ko = min(ko, extent(d.eKo));
+    if (d.eKi) ki = min(ki, extent(d.eKi));
+    Kin = max(ki, 1);
+    Kt = max(ko, 0) * max(ki, 0);
+    if (h >= ht || m0 >= Mt || n0 >= Nt) Kt = 0;
+  }
   // K slice of this split (an empty slice still writes its zero partials)
-  const int nchunks = (d.K + TK - 1) / TK;
+  const int nchunks = (Kt + TK - 1) / TK;
   const int per = (nchunks + d.ksplit - 1) / d.ksplit;
   const int kbeg = z * per * TK;
-  const int kend = min(d.K, kbeg + per * TK);
+  const int kend = min(Kt, kbeg + per * TK);
 
   acc_t acc_re[2][2], acc_im[2][2];
 #pragma unroll
@@ -118,9 +135,9 @@ __global__ void __launch_bounds__(256) k_zgemm(GemmDesc d) {
       const int kk = d.a_m_fast ? e / TM : e % TK;
       const int gm = m0 + mm, gk = k0 + kk;
       double re = 0.0, im = 0.0;
-      if (gm < d.M && gk < kend) {
-        const long long off = (long long)gm * d.sAi + (long long)(gk / d.Kin) * d.sAl1 +
-                              (long long)(gk % d.Kin) * d.sAl2;
+      if (gm < Mt && gk < kend) {
+        const long long off = (long long)gm * d.sAi + (long long)(gk / Kin) * d.sAl1 +
+                              (long long)(gk % Kin) * d.sAl2;
         load_c(A, off, re, im);
       }
       ra_re[r] = (R)re;
@@ -133,8 +150,8 @@ __global__ void __launch_bounds__(256) k_zgemm(GemmDesc d) {
       const int kk = d.b_n_fast ? e / TN : e % TK;
       const int gn = n0 + nn, gk = k0 + kk;
       double re = 0.0, im = 0.0;
-      if (gn < d.N && gk < kend) {
-        const long long off = (long long)(gk / d.Kin) * d.sBl1 + (long long)(gk % d.Kin) * d.sBl2 +
+      if (gn < Nt && gk < kend) {
+        const long long off = (long long)(gk / Kin) * d.sBl1 + (long long)(gk % Kin) * d.sBl2 +
                               (long long)gn * d.sBj;
         load_c(B, off, re, im);
       }
@@ -293,6 +310,8 @@ hipError_t launch_zgemm_t(GemmDesc d, int batch, hipStream_t st) {
   if (d.G2 < 1) d.G2 = 1;
   if (d.ksplit < 1) d.ksplit = 1;
   if (d.H < 1 || d.ksplit > 64) return hipErrorInvalidValue;
+  if (d.ext && (d.K % d.Kin != 0 || d.ext_stride < 1)) return hipErrorInvalidValue;
+  if (d.ext && (d.eM < 0 || d.eN < 0 || d.eH < 0 || d.eKo < 0 || d.eKi < 0) && !d.knew) return hipErrorInvalidValue;
   switch (tile_cfg(d.M, d.N)) {
     case TILE_128x32: return launch_cfg<SA, SB, SC, R, 4, 1, 1>(d, batch, st);
     case TILE_32x128: return launch_cfg<SA, SB, SC, R, 1, 4, 1>(d, batch, st);

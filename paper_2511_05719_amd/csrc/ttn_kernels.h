@@ -24,6 +24,21 @@ struct GemmDesc {
   int conjA, conjB;
   int a_m_fast, b_n_fast;   // operand dimension that is unit-stride on load
   int tilesN;               // filled by the launcher
+  // Per-trajectory extents (all optional).  A node tensor is stored padded
+  // to the batch's largest bond dimensions, and trajectory t's entries are
+  // zero beyond its own extent on each bond (a prefix).  With ext set, a
+  // field e > 0 names the bond whose extent ext[t * ext_stride + e] bounds
+  // that dimension, e < 0 the new bond of the move in progress, whose extent
+  // is knew[t * 4], and e = 0 leaves it padded.  Output tiles beyond the
+  // extent are written as zeros without K work; the K loop stops at
+  // extent(eKo) * extent(eKi) with l = (l / Kin_t, l % Kin_t), Kin_t =
+  // min(Kin, extent(eKi)).
+  const int* ext;
+  const int* knew;
+  long long ext_stride;
+  int eM, eN, eH;           // M <= extent(eM) * mM, N <= extent(eN) * mN, H <= extent(eH)
+  int mM, mN;
+  int eKo, eKi;             // outer (l / Kin) and inner (l % Kin) parts of K
 };
 
 hipError_t launch_zgemm(const GemmDesc& d, int batch, int kind, hipStream_t st);
@@ -179,6 +194,10 @@ hipError_t launch_ledger_reset(int* adim, int L, int batch, hipStream_t st);
 
 // out[c] = max over rows t of nk[t][c], c = 0..3 (one workgroup)
 hipError_t launch_nk_max(const int* nk, int batch, int* out, hipStream_t st);
+// per-row copy of one column: dst[t * dst_stride] = src[t * src_stride]
+// (a bond's per-row extents from the kept counts of its move)
+hipError_t launch_set_ext(int* dst, long long dst_stride, const int* src, long long src_stride, int batch,
+                          hipStream_t st);
 
 // ------------------------------------------------------------ ADJOINT ----
 // Noise ops of one leaf inside one layer of the adjoint gradient (applied in

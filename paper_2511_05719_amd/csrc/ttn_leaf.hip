@@ -435,6 +435,20 @@ hipError_t launch_nk_max(const int* nk, int batch, int* out, hipStream_t st) {
   return hipGetLastError();
 }
 
+// dst[t * dst_stride] = src[t * src_stride] for every row t
+__global__ void __launch_bounds__(256) k_set_ext(int* dst, long long dst_stride, const int* src,
+                                                 long long src_stride, int batch) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < batch) dst[t * dst_stride] = src[t * src_stride];
+}
+hipError_t launch_set_ext(int* dst, long long dst_stride, const int* src, long long src_stride, int batch,
+                          hipStream_t st) {
+  if (batch <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_set_ext, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, st, dst, dst_stride, src,
+                     src_stride, batch);
+  return hipGetLastError();
+}
+
 __global__ void k_fill_cone(void* p, int c128, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;

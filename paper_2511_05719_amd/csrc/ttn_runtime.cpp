@@ -93,6 +93,12 @@ struct ttn_ctx {
   double* scale_abs = nullptr;
   int* nsteps = nullptr;
   int* rank_table = nullptr;   // [B][L] bond above node e
+  // [B][L] per-row prefix extent of the bond above node e: the row's entries
+  // beyond it are zero on both nodes of the bond; trusted only where
+  // ext_ok[e] (a bond doubled by a controlled gate is not, until a plain
+  // move re-factors it)
+  int* ext = nullptr;
+  std::vector<char> ext_ok;
   int* rank_max = nullptr;     // [B][L] running maximum of rank_table
   double* disc_acc = nullptr;  // [B]
   int* flags = nullptr;        // [B]
@@ -282,14 +288,14 @@ static GemmDesc gram_desc(const void* T, std::array<int, 3> d, int leg, double2*
   g.M = n; g.N = n;
   if (leg == 0) {
     const long long R = (long long)d[1] * d[2];
-    g.sAi = R; g.sAl2 = 1; g.a_m_fast = 0;
-    g.sBl2 = 1; g.sBj = R; g.b_n_fast = 0;
-    g.K = (int)R; g.Kin = g.K;
+    g.sAi = R; g.sAl1 = d[2]; g.sAl2 = 1; g.a_m_fast = 0;
+    g.sBl1 = d[2]; g.sBl2 = 1; g.sBj = R; g.b_n_fast = 0;
+    g.K = (int)R; g.Kin = d[2];
   } else if (leg == 2) {
     const long long R = (long long)d[0] * d[1];
-    g.sAi = 1; g.sAl2 = n; g.a_m_fast = 1;
-    g.sBl2 = n; g.sBj = 1; g.b_n_fast = 1;
-    g.K = (int)R; g.Kin = g.K;
+    g.sAi = 1; g.sAl1 = (long long)d[1] * n; g.sAl2 = n; g.a_m_fast = 1;
+    g.sBl1 = (long long)d[1] * n; g.sBl2 = n; g.sBj = 1; g.b_n_fast = 1;
+    g.K = (int)R; g.Kin = d[1];
   } else {
     g.sAi = d[2]; g.sAl1 = (long long)n * d[2]; g.sAl2 = 1; g.a_m_fast = 0;
     g.sBl1 = (long long)n * d[2]; g.sBl2 = 1; g.sBj = d[2]; g.b_n_fast = 0;
@@ -311,6 +317,43 @@ static void gram_split(GemmDesc& g) {
   g.M = h;
   g.N = h;
 }
+// Bond id of leg `leg` of `node` whose per-row extents can be trusted, else
+// 0 (physical legs of bottom nodes, the root's dimension-1 leg, and bonds
+// doubled by a controlled gate).
+static int ext_bond(const ttn_ctx* ctx, int node, int leg) {
+  int e;
+  if (leg == 2) e = node;
+  else if (is_bottom(ctx, node)) return 0;
+  else e = 2 * node + leg;
+  return (e > 1 && e < ctx->L && ctx->ext_ok[e]) ? e : 0;
+}
+// Per-row extents of a contraction on `leg` of `node` whose new bond (the
+// output rows of W) has the per-row kept counts of the move in progress
+// (newb = true) or is padded.  The contracted leg's extent bounds K.
+static void ext_leg(const ttn_ctx* ctx, GemmDesc& g, int node, std::array<int, 3> d, int leg, bool newb,
+                    bool kb) {
+  g.ext = ctx->ext; g.knew = ctx->nk + 1; g.ext_stride = ctx->L;
+  const int bn = newb ? -1 : 0;
+  const int bk = kb ? ext_bond(ctx, node, leg) : 0;
+  if (leg == 0) {
+    g.eM = bn; g.mM = 1; g.eN = ext_bond(ctx, node, 1); g.mN = d[2];
+  } else if (leg == 2) {
+    g.eM = ext_bond(ctx, node, 0); g.mM = d[1]; g.eN = bn; g.mN = 1;
+  } else {
+    g.eH = ext_bond(ctx, node, 0); g.eM = bn; g.mM = 1; g.eN = ext_bond(ctx, node, 2); g.mN = 1;
+  }
+  g.eKi = bk;
+}
+// Per-row extents of the Gram matrix of `leg` of `node`: its rows and
+// columns run over that leg (unless split in blocks), K over the other two.
+static void ext_gram(const ttn_ctx* ctx, GemmDesc& g, int node, int leg, bool blocks) {
+  g.ext = ctx->ext; g.knew = nullptr; g.ext_stride = ctx->L;
+  const int bl = blocks ? 0 : ext_bond(ctx, node, leg);
+  g.eM = bl; g.mM = 1; g.eN = bl; g.mN = 1;
+  const int o = leg == 0 ? 1 : 0, i = leg == 2 ? 1 : 2;
+  g.eKo = ext_bond(ctx, node, o);
+  g.eKi = ext_bond(ctx, node, i);
+}
 static long long buf_elems(const ttn_ctx* ctx, int b) { return (long long)(ctx->bufs[b].bytes / ctx->es); }
 static long long ws_elems(const ttn_ctx* ctx) { return (long long)ctx->B * ctx->nmax * ctx->nmax; }
 static long long gslice_elems(const ttn_ctx* ctx) { return ws_elems(ctx); }
@@ -325,8 +368,8 @@ static inline void* offset_ptr(const void* p, long long elems, size_t es) {
 // that leg of dimension newd.  W is [rows][wrows][n].  blocks = 2: W is block
 // diagonal with diagonal blocks [wrows/2][n/2]; block b contributes kb[b]
 // rows, placed at new indices [kb[0] * b, kb[0] * b + kb[b]) (newd = kb[0] + kb[1]).
-static ttn_status leg_apply(ttn_ctx* ctx, int src_buf, std::array<int, 3> d, int leg, const void* W, int wrows,
-                            int newd, int dst_buf, int blocks = 1, const int* kb = nullptr) {
+static ttn_status leg_apply(ttn_ctx* ctx, int node, int src_buf, std::array<int, 3> d, int leg, const void* W,
+                            int wrows, int newd, int dst_buf, int blocks = 1, const int* kb = nullptr) {
   const int n = d[leg];
   const bool wA = (leg != 2);
   const long long capT = buf_elems(ctx, src_buf), capW = ws_elems(ctx), capC = buf_elems(ctx, dst_buf);
@@ -334,6 +377,9 @@ static ttn_status leg_apply(ttn_ctx* ctx, int src_buf, std::array<int, 3> d, int
   int off = 0;
   for (int b = 0; b < nb; ++b) {
     GemmDesc g = leg_desc(ctx->bufs[src_buf].p, d, leg, W, wrows, newd, ctx->bufs[dst_buf].p);
+    // rows of W beyond a row's kept count are zero: the new bond's extent is
+    // that count (for the two halves of a block move the padded bound)
+    ext_leg(ctx, g, node, d, leg, nb == 1, nb == 1);
     long long oT = 0, oW = 0, oC = 0;
     if (nb == 2) {
       const int rows_b = kb[b];
@@ -369,8 +415,10 @@ static ttn_status leg_apply(ttn_ctx* ctx, int src_buf, std::array<int, 3> d, int
 // output has too few tiles to occupy the chip, K is split over up to
 // ctx->gslices workgroups per tile, each writing its partial product to its
 // own slice of G (the eigensolver sums the slices); *nsplit returns the count.
-static ttn_status gram(ttn_ctx* ctx, int src_buf, std::array<int, 3> d, int leg, int blocks, int* nsplit) {
+static ttn_status gram(ttn_ctx* ctx, int node, int src_buf, std::array<int, 3> d, int leg, int blocks,
+                       int* nsplit) {
   GemmDesc g = gram_desc(ctx->bufs[src_buf].p, d, leg, ctx->G);
+  ext_gram(ctx, g, node, leg, blocks > 1);
   if (blocks > 1) gram_split(g);
   const long long wgs = (long long)ctx->B * std::max(g.G2, 1) * zgemm_tiles(g);
   int ks = (int)std::min<long long>((kGramTargetWgs + wgs - 1) / wgs, ctx->gslices);
@@ -421,7 +469,7 @@ static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int ne
     return fail(ctx, TTN_EINVAL, "internal: bond dimension exceeds workspace");
   if (blocks > 1 && ((n & 1) || (new_pad & 1))) return fail(ctx, TTN_EINVAL, "internal: odd block size");
   int gsplit = 1;
-  TTN_TRY(gram(ctx, ctx->node_buf[x], dx, lx, blocks, &gsplit));
+  TTN_TRY(gram(ctx, x, ctx->node_buf[x], dx, lx, blocks, &gsplit));
   EighDesc ed{};
   ed.G = ctx->G; ed.n = n; ed.new_pad = new_pad; ed.cap = cap; ed.cutoff = cutoff;
   ed.gsplit = gsplit; ed.gslice = gslice_elems(ctx);
@@ -455,12 +503,21 @@ static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int ne
   }
   const int bx = acquire(ctx, ctx->node_cls[x]);
   if (bx < 0) return fail(ctx, TTN_EINVAL, "internal: pool exhausted");
-  TTN_TRY(leg_apply(ctx, ctx->node_buf[x], dx, lx, ctx->Wi, new_pad, newd, bx, blocks, kb));
+  TTN_TRY(leg_apply(ctx, x, ctx->node_buf[x], dx, lx, ctx->Wi, new_pad, newd, bx, blocks, kb));
   adopt(ctx, x, bx);
   const int by = acquire(ctx, ctx->node_cls[y]);
   if (by < 0) return fail(ctx, TTN_EINVAL, "internal: pool exhausted");
-  TTN_TRY(leg_apply(ctx, ctx->node_buf[y], dy, ly, ctx->Wa, new_pad, newd, by, blocks, kb));
+  TTN_TRY(leg_apply(ctx, y, ctx->node_buf[y], dy, ly, ctx->Wa, new_pad, newd, by, blocks, kb));
   adopt(ctx, y, by);
+  // the bond's new per-row extents: the kept counts (a block move leaves
+  // them untrusted until the truncating sweep re-factors the bond)
+  if (blocks > 1) {
+    ctx->ext_ok[e] = 0;
+  } else {
+    ++ctx->launches;
+    TTN_CHECK_HIP(launch_set_ext(ctx->ext + e, ctx->L, ctx->nk + 1, 4, ctx->B, ctx->st));
+    ctx->ext_ok[e] = 1;
+  }
   ctx->dims[x][lx] = newd;
   ctx->dims[y][ly] = newd;
   ctx->centre = y;
@@ -577,6 +634,7 @@ static ttn_status controlled_gate(ttn_ctx* ctx, int qs, const double P[2][2][2][
     TTN_CHECK_HIP(launch_extend(x, ctx->B, ctx->st));
     adopt(ctx, ns, b);
     ctx->dims[ns][2] *= 2;
+    ctx->ext_ok[ns] = 0;
     if (ctx->prof) TTN_CHECK_HIP(launch_ledger_double(ctx->adim, ctx->L, ns, 2, -1, ctx->B, ctx->st));
   }
   for (int i = 0; i < m; ++i) {
@@ -611,6 +669,8 @@ static ttn_status controlled_gate(ttn_ctx* ctx, int qs, const double P[2][2][2][
     }
     adopt(ctx, y, b);
     ctx->dims[y] = e;
+    ctx->ext_ok[bond_node(x, y)] = 0;
+    if (y != ne) ctx->ext_ok[bond_node(y, path[i + 2])] = 0;
     if (ctx->prof)
       TTN_CHECK_HIP(launch_ledger_double(ctx->adim, ctx->L, y, ex.leg_in, ex.leg_out, ctx->B, ctx->st));
     // exact move across (x, y): the bond can hold the near side's full space
@@ -688,12 +748,14 @@ static ttn_status reset_state(ttn_ctx* ctx, const uint8_t* basis) {
   }
   ctx->centre = 1;
   TTN_CHECK_HIP(launch_fill_i32(ctx->rank_table, 1, (long long)ctx->B * ctx->L, ctx->st));
+  TTN_CHECK_HIP(launch_fill_i32(ctx->ext, 1, (long long)ctx->B * ctx->L, ctx->st));
+  ctx->ext_ok.assign(ctx->L, 1);
   TTN_CHECK_HIP(launch_fill_i32(ctx->rank_max, 1, (long long)ctx->B * ctx->L, ctx->st));
   TTN_CHECK_HIP(launch_ledger_reset(ctx->adim, ctx->L, ctx->B, ctx->st));
   TTN_CHECK_HIP(launch_fill_i32(ctx->flags, 0, ctx->B, ctx->st));
   TTN_CHECK_HIP(launch_fill_i32(ctx->degen_acc, 0, ctx->B, ctx->st));
   TTN_CHECK_HIP(launch_fill_f64(ctx->disc_acc, 0.0, ctx->B, ctx->st));
-  ctx->launches += 5;
+  ctx->launches += 6;
   return TTN_OK;
 }
 
@@ -926,6 +988,7 @@ ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {
   ok &= hipMalloc((void**)&ctx->scale_abs, 2 * Bz * sizeof(double)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->nsteps, 2 * Bz * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->rank_table, Bz * L * sizeof(int)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->ext, Bz * L * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->rank_max, Bz * L * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->ledger_mem, 4 * Bz * sizeof(double)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->adim, Bz * L * 3 * sizeof(int)) == hipSuccess;
@@ -960,7 +1023,7 @@ ttn_status ttn_destroy(ttn_ctx* ctx) {
       hipEventDestroy(e.second);
     }
   void* ws[] = {ctx->G, ctx->Wi, ctx->Wa, ctx->rot_log, ctx->gpk, ctx->lam_sorted, ctx->order, ctx->kept,
-                ctx->scale_abs, ctx->nsteps, ctx->rank_table, ctx->rank_max, ctx->ledger_mem,
+                ctx->scale_abs, ctx->nsteps, ctx->rank_table, ctx->ext, ctx->rank_max, ctx->ledger_mem,
                 ctx->adim, ctx->nk, ctx->nk_max,
                 ctx->disc_acc, ctx->flags,
                 ctx->degen_acc, ctx->leader, ctx->dec_datarec, ctx->dec_masks};
@@ -1182,6 +1245,7 @@ ttn_status ttn_log_prob(ttn_ctx* ctx, const ttn_oplist* ol, const uint8_t* recor
 namespace {
 struct Snapshot {
   std::vector<std::array<int, 3>> dims;
+  std::vector<char> ext_ok;
   int centre = 1;
   void* mem = nullptr;
   std::vector<size_t> off;
@@ -1200,13 +1264,16 @@ static ttn_status snap_take(ttn_ctx* c, Snapshot& s) {
   TTN_TRY(flush_leaf(c));
   snap_free(s);
   s.dims = c->dims;
+  s.ext_ok = c->ext_ok;
   s.centre = c->centre;
-  s.off.assign(c->L, 0);
+  s.off.assign(c->L + 1, 0);
   size_t tot = 0;
   for (int node = 1; node < c->L; ++node) {
     s.off[node] = tot;
     tot += ((size_t)c->B * elems(c->dims[node]) * c->es + 255) & ~(size_t)255;
   }
+  s.off[c->L] = tot;                      // the per-row bond extents
+  tot += (size_t)c->B * c->L * sizeof(int);
   if (hipMalloc(&s.mem, tot) != hipSuccess) {
     s.mem = nullptr;
     return fail(c, TTN_ENOMEM, "snapshot allocation failed (reduce the batch)");
@@ -1214,6 +1281,8 @@ static ttn_status snap_take(ttn_ctx* c, Snapshot& s) {
   for (int node = 1; node < c->L; ++node)
     TTN_CHECK_HIP(hipMemcpyAsync((char*)s.mem + s.off[node], node_ptr(c, node),
                                  (size_t)c->B * elems(c->dims[node]) * c->es, hipMemcpyDeviceToDevice, c->st));
+  TTN_CHECK_HIP(hipMemcpyAsync((char*)s.mem + s.off[c->L], c->ext, (size_t)c->B * c->L * sizeof(int),
+                               hipMemcpyDeviceToDevice, c->st));
   return TTN_OK;
 }
 
@@ -1228,7 +1297,10 @@ static ttn_status snap_restore(ttn_ctx* c, const Snapshot& s) {
     TTN_CHECK_HIP(hipMemcpyAsync(node_ptr(c, node), (const char*)s.mem + s.off[node], (size_t)n * c->es,
                                  hipMemcpyDeviceToDevice, c->st));
   }
+  TTN_CHECK_HIP(hipMemcpyAsync(c->ext, (const char*)s.mem + s.off[c->L], (size_t)c->B * c->L * sizeof(int),
+                               hipMemcpyDeviceToDevice, c->st));
   c->dims = s.dims;
+  c->ext_ok = s.ext_ok;
   c->centre = s.centre;
   return TTN_OK;
 }

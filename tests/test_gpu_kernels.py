@@ -146,6 +146,87 @@ def test_eigh_centre_move_factors(dtype, n, rank):
     eng.close()
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,blocks", [(24, 1), (64, 1), (100, 1), (128, 1), (200, 1), (64, 2), (128, 2), (256, 2)])
+def test_eigh_zero_rows_are_compacted(dtype, n, blocks):
+    # a bond padded beyond this row's dimension: columns of M (rows and
+    # columns of G) exactly zero, as a prefix or scattered (the unused rows of
+    # a block), down to one live row and none; the solver works on the live
+    # rows only and must return the factors of the full problem, with exact
+    # zeros in the dead columns
+    from paper_2511_05719_amd._abi import lib, check
+    g = np.random.default_rng(n * 7 + blocks)
+    rows, K = 6, 2 * n
+    h = n // blocks
+    live = np.zeros((rows, n), bool)
+    for b in range(blocks):
+        sl = slice(b * h, (b + 1) * h)
+        live[0, sl] = np.arange(h) < h // 2                     # prefix
+        live[1, sl] = g.random(h) < 0.6                          # scattered
+        live[2, sl] = np.arange(h) < 1                           # one live row
+        live[3, sl] = True                                       # none dead
+        live[4, sl] = (np.arange(h) % 3) != 1                    # regular holes
+        live[5, sl] = False                                      # all dead
+    live[5, 0] = blocks == 2                                     # block 0 of row 5 keeps one row
+    M = np.zeros((rows, K, n), complex)
+    for t in range(rows):
+        for b in range(blocks):
+            idx = np.nonzero(live[t, b * h:(b + 1) * h])[0] + b * h
+            if len(idx) == 0:
+                continue
+            r = max(1, (2 * len(idx)) // 3)
+            A = (g.normal(size=(K, r)) + 1j * g.normal(size=(K, r))) @ \
+                (g.normal(size=(r, len(idx))) + 1j * g.normal(size=(r, len(idx))))
+            A *= (10.0 ** (-np.arange(len(idx)) / 12.0))[None, :]
+            M[t][:, idx] = A
+        nrm = np.linalg.norm(M[t])
+        if nrm > 0:
+            M[t] /= nrm
+    G = np.zeros((rows, n, n), complex)
+    for b in range(blocks):
+        sl = slice(b * h, (b + 1) * h)
+        G[:, sl, sl] = np.einsum("tki,tkj->tij", M[:, :, sl].conj(), M[:, :, sl])
+    eng = _engine(dtype, chi=128 if n > 128 else 64)
+    Gd = torch.view_as_real(torch.as_tensor(G)).contiguous().cuda()
+    wdt = torch.float64 if dtype == "c128" else torch.float32
+    Wi = torch.full((rows, n, n, 2), 7.0, dtype=wdt, device="cuda")
+    Wa = torch.full((rows, n, n, 2), 7.0, dtype=wdt, device="cuda")
+    rk = torch.full((rows,), -1, dtype=torch.int32, device="cuda")
+    cutoff = 1e-12
+    check(lib().ttn_test_eigh(eng._ctx, rows, n, n, n // blocks, cutoff, Gd.data_ptr(), rows * n * n,
+                              Wi.data_ptr(), Wa.data_ptr(), rows * n * n,
+                              rk.data_ptr() if blocks == 1 else None, None, blocks), eng._ctx)
+    Wi, Wa, rk = _host_complex(Wi), _host_complex(Wa), rk.cpu().numpy()
+    tol = 1e-9 if dtype == "c128" else 3e-5
+    for t in range(rows):
+        assert np.all(Wi[t][:, ~live[t]] == 0) and np.all(Wa[t][:, ~live[t]] == 0)
+        for b in range(blocks):
+            sl = slice(b * h, (b + 1) * h)
+            Mb = M[t][:, sl]
+            s = np.linalg.svd(Mb, compute_uv=False)
+            tot = np.linalg.norm(M[t]) ** 2
+            k = int((s ** 2 > cutoff * tot).sum()) if tot > 0 else 0
+            wi, wa = Wi[t, sl, sl], Wa[t, sl, sl]
+            assert int(np.sum(np.linalg.norm(wa, axis=1) > 0)) == k, (t, b, k)
+            if blocks == 1:
+                assert rk[t] == k
+            assert np.all(wi[k:] == 0) and np.all(wa[k:] == 0)
+            if blocks == 2:
+                other = slice((1 - b) * h, (2 - b) * h)
+                assert np.all(Wi[t, sl, other] == 0) and np.all(Wa[t, sl, other] == 0)
+            if k == 0:
+                continue
+            u_, s_, vh_ = np.linalg.svd(Mb, full_matrices=False)
+            Mk = (u_[:, :k] * s_[:k]) @ vh_[:k]
+            if blocks == 1:
+                Mk /= np.linalg.norm(Mk)
+            U = Mb @ wi[:k].T
+            assert np.abs(U @ wa[:k] - Mk).max() < tol * max(1.0, s[0])
+            sa = np.linalg.norm(wa[:k], axis=1)          # descending kept values
+            assert np.all(np.diff(sa) <= (1e-12 if dtype == "c128" else 1e-6) * sa[0])
+    eng.close()
+
+
 def test_eigh_truncation_cap():
     from paper_2511_05719_amd._abi import lib, check
     g = np.random.default_rng(3)
