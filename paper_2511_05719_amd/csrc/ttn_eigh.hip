@@ -39,12 +39,16 @@ int eigh_max_sweeps() { return kMaxSweeps; }
 __device__ inline int pidx(int i, int j, int n) {   // packed upper triangle, i <= j
   return i * (2 * n - i + 1) / 2 + (j - i);
 }
+// entry (i, j) of the Hermitian matrix from its packed upper triangle, and
+// its store; branch-free (lanes of one wave take both triangles at once)
 __device__ inline double2 gget(const double2* Gp, int i, int j, int n) {
-  return (i <= j) ? Gp[pidx(i, j, n)] : cconj(Gp[pidx(j, i, n)]);
+  double2 v = Gp[pidx(min(i, j), max(i, j), n)];
+  v.y = (i <= j) ? v.y : -v.y;
+  return v;
 }
 __device__ inline void gset(double2* Gp, int i, int j, int n, double2 v) {
-  if (i <= j) Gp[pidx(i, j, n)] = v;
-  else Gp[pidx(j, i, n)] = cconj(v);
+  v.y = (i <= j) ? v.y : -v.y;
+  Gp[pidx(min(i, j), max(i, j), n)] = v;
 }
 // circle-method pairing for step s of an even size n (no integer division)
 __device__ inline void pair_of(int n, int s, int j, int* p, int* q) {
@@ -186,6 +190,7 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
   double2* Gp = kGlobalG ? d.gpk + pid * (long long)(NMAX * (NMAX + 1) / 2) : smem;   // packed G
   VT* V = reinterpret_cast<VT*>(smem + npk);           // [n2][n2] if kVinLds
   __shared__ Rot rot[NMAX / 2];
+  __shared__ int pq_s[NMAX / 2];                                    // this step's pairs, p | q << 16
   __shared__ unsigned short blk[(NMAX / 2) * (NMAX / 2 + 1) / 2];   // (P, Q) of the upper 2x2 blocks
   __shared__ double lam[NMAX];
   __shared__ int order_s[NMAX];
@@ -228,31 +233,39 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
   double* log = d.rot_log ? d.rot_log + pid * d.log_stride : nullptr;
   const double tol = d.tol > 0.0 ? d.tol : 1e-15;
   const double stop_ratio = d.early_stop ? 0.25 * sqrt(tol) : 0.0;
+  const double stop_ratio2 = stop_ratio * stop_ratio;
+  const double floor2 = (0.1 * tol * tr) * (0.1 * tol * tr);
   if (n2 >= 2 && finite) {
+    const int vgroups = NT / h;                 // V update: row groups of h threads
+    const int vP = threadIdx.x % h, vr0 = threadIdx.x / h;
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
       if (threadIdx.x == 0) any_rot = 0;
       __syncthreads();
-      double my_ratio = 0.0;     // rotation threads: largest rotated ratio this sweep
+      double my_ratio = 0.0;     // rotation threads: largest rotated squared ratio this sweep
       for (int s = 0; s < n2 - 1; ++s) {
-        // -- rotation parameters of the n2/2 pairs --
+        // -- rotation parameters of the n2/2 pairs (the tests on squares,
+        //    one reciprocal square root for |b| and one for c: the serial
+        //    part of every step) --
         if (threadIdx.x < h) {
           int p, q;
           pair_of(n2, s, threadIdx.x, &p, &q);
+          pq_s[threadIdx.x] = p | (q << 16);
           const double a = Gp[pidx(p, p, n2)].x, dd = Gp[pidx(q, q, n2)].x;
           const double2 b = Gp[pidx(p, q, n2)];
-          const double ab = sqrt(cabs2(b));
+          const double ab2 = cabs2(b);
+          const double ad = fabs(a * dd);
           Rot r;
           r.c = 1.0; r.s = make_double2(0.0, 0.0); r.delta = 0.0;
-          const double sad = sqrt(fabs(a * dd));
-          if (ab > tol * sad && ab > 0.1 * tol * tr && ab > 0.0) {
-            my_ratio = fmax(my_ratio, sad > 0.0 ? ab / sad : 1.0);
-            const double th = (dd - a) / (2.0 * ab);
+          if (ab2 > tol * tol * ad && ab2 > floor2 && ab2 > 0.0) {
+            my_ratio = fmax(my_ratio, ad > 0.0 ? ab2 / ad : 1.0);
+            const double inv_ab = rsqrt(ab2);
+            const double th = 0.5 * (dd - a) * inv_ab;
             const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-            const double c = 1.0 / sqrt(1.0 + tt * tt);
-            const double sn = tt * c;
+            const double c = rsqrt(1.0 + tt * tt);
+            const double sn = tt * c * inv_ab;
             r.c = c;
-            r.s = make_double2(sn * b.x / ab, sn * b.y / ab);
-            r.delta = tt * ab;
+            r.s = make_double2(sn * b.x, sn * b.y);
+            r.delta = tt * (ab2 * inv_ab);
             any_rot = 1;
           }
           rot[threadIdx.x] = r;
@@ -267,8 +280,8 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
           const unsigned short pq = blk[idx];
           const int P = pq & 0xff, Q = pq >> 8;
           const Rot rP = rot[P];
-          int p, q;
-          pair_of(n2, s, P, &p, &q);
+          const int eP = pq_s[P];
+          const int p = eP & 0xffff, q = eP >> 16;
           if (P == Q) {
             if (rP.delta != 0.0) {
               double2 gpp = Gp[pidx(p, p, n2)], gqq = Gp[pidx(q, q, n2)];
@@ -282,8 +295,8 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
           }
           const Rot rQ = rot[Q];
           if (rP.delta == 0.0 && rQ.delta == 0.0) continue;
-          int pp, qq;
-          pair_of(n2, s, Q, &pp, &qq);
+          const int eQ = pq_s[Q];
+          const int pp = eQ & 0xffff, qq = eQ >> 16;
           const double2 g00 = gget(Gp, p, pp, n2), g01 = gget(Gp, p, qq, n2);
           const double2 g10 = gget(Gp, q, pp, n2), g11 = gget(Gp, q, qq, n2);
           // X = G_PQ J_Q,  J = [[c, s], [-conj(s), c]]
@@ -300,16 +313,19 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
           gset(Gp, q, qq, n2, cadd(cmul(sPc, x01), cscale(x11, rP.c)));
         }
         if (kVinLds) {
-          // V <- V J (columns p, q of every row)
-          for (int idx = threadIdx.x; idx < n2 * h; idx += blockDim.x) {
-            const int r = idx / h, P = idx - (idx / h) * h;
-            const Rot rP = rot[P];
-            if (rP.delta == 0.0) continue;
-            int p, q;
-            pair_of(n2, s, P, &p, &q);
-            const double2 vp = to_d2(V[r * n2 + p]), vq = to_d2(V[r * n2 + q]);
-            V[r * n2 + p] = from_d2<VT>(csub(cscale(vp, rP.c), cmul(cconj(rP.s), vq)));
-            V[r * n2 + q] = from_d2<VT>(cadd(cmul(rP.s, vp), cscale(vq, rP.c)));
+          // V <- V J (columns p, q of every row): thread owns pair vP on
+          // the rows vr0, vr0 + vgroups, ...
+          if (threadIdx.x < vgroups * h) {
+            const Rot rP = rot[vP];
+            if (rP.delta != 0.0) {
+              const int eP = pq_s[vP];
+              const int p = eP & 0xffff, q = eP >> 16;
+              for (int r = vr0; r < n2; r += vgroups) {
+                const double2 vp = to_d2(V[r * n2 + p]), vq = to_d2(V[r * n2 + q]);
+                V[r * n2 + p] = from_d2<VT>(csub(cscale(vp, rP.c), cmul(cconj(rP.s), vq)));
+                V[r * n2 + q] = from_d2<VT>(cadd(cmul(rP.s, vp), cscale(vq, rP.c)));
+              }
+            }
           }
         }
         ++step_count;
@@ -329,7 +345,7 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
         sweep_ratio = m;
       }
       __syncthreads();
-      if (any_rot == 0 || sweep_ratio < stop_ratio) break;
+      if (any_rot == 0 || sweep_ratio < stop_ratio2) break;
       __syncthreads();
     }
   }
@@ -471,13 +487,36 @@ __global__ void __launch_bounds__(1024) k_jacobi_vectors(EighDesc d) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
     if (ncol > 0) {
+      // lane owns pairs P = lane + 64 j; the log entries of the next
+      // (earlier) step are loaded while this step's rotations run
+      constexpr int NPL = NMAX / 128;
+      double nc[NPL], ns0[NPL], ns1[NPL];
+      bool nok[NPL];
+      // (unconditional loads from a clamped, valid entry, so that the wait
+      // for them can sit in the next step)
+      auto fetch = [&](int st) {
+#pragma unroll
+        for (int j = 0; j < NPL; ++j) {
+          const int P = lane + 64 * j;
+          nok[j] = P < h && st >= 0;
+          const double* e = log + ((long long)(st < 0 ? 0 : st) * h + (P < h ? P : h - 1)) * 3;
+          nc[j] = e[0]; ns0[j] = e[1]; ns1[j] = e[2];
+        }
+      };
+      fetch(steps - 1);
       int s = (steps - 1) % (n2 - 1);
       for (int st = steps - 1; st >= 0; --st) {
-        for (int P = lane; P < h; P += 64) {
-          const double* e = log + ((long long)st * h + P) * 3;
-          const double c = e[0];
-          const double2 sv = make_double2(e[1], e[2]);
-          if (!(c == 1.0 && sv.x == 0.0 && sv.y == 0.0)) {
+        double cc_[NPL], s0_[NPL], s1_[NPL];
+        bool ok_[NPL];
+#pragma unroll
+        for (int j = 0; j < NPL; ++j) { cc_[j] = nc[j]; s0_[j] = ns0[j]; s1_[j] = ns1[j]; ok_[j] = nok[j]; }
+        fetch(st - 1);
+#pragma unroll
+        for (int j = 0; j < NPL; ++j) {
+          const int P = lane + 64 * j;
+          const double c = cc_[j];
+          const double2 sv = make_double2(s0_[j], s1_[j]);
+          if (ok_[j] && !(c == 1.0 && sv.x == 0.0 && sv.y == 0.0)) {
             int p, q;
             pair_of(n2, s, P, &p, &q);
             for (int cc = 0; cc < ncol; ++cc) {
@@ -764,10 +803,10 @@ hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st) {
   const int n2 = nsub + (nsub & 1);
   const size_t gbytes = (size_t)n2 * (n2 + 1) / 2 * sizeof(double2);
   const long long nprob = (long long)batch * nb;
-  // one wavefront per matrix pays off once there are enough matrices to give
-  // every SIMD of the chip a few of them; otherwise the workgroup kernel
-  // below spreads each matrix over 8 wavefronts
-  if (n2 <= 32 && nprob >= 4096) {
+  // one wavefront per matrix: always for n <= 16, and up to 32 once there
+  // are enough matrices to give every SIMD of the chip a few of them;
+  // otherwise the workgroup kernel below spreads each matrix over 8 wavefronts
+  if (n2 <= 16 || (n2 <= 32 && nprob >= 4096)) {
     const unsigned grid = (unsigned)((nprob + 3) / 4);
     if (n2 <= 8) hipLaunchKernelGGL(k_jacobi_wave<8>, dim3(grid), dim3(256), 0, st, d, nprob);
     else if (n2 <= 16) hipLaunchKernelGGL(k_jacobi_wave<16>, dim3(grid), dim3(256), 0, st, d, nprob);
