@@ -60,7 +60,7 @@ template <typename S> __device__ inline void load_c(const S* p, long long off, d
 }
 
 template <typename SA, typename SB, typename SC, typename R, int WM, int WN, int KW>
-__global__ void __launch_bounds__(256) k_zgemm(GemmDesc d) {
+__global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
   static_assert(WM * WN * KW == 4, "four waves per workgroup");
   constexpr int TM = 32 * WM, TN = 32 * WN, TK = 16 * KW;
   constexpr int AE = TM * TK / 256, BE = TN * TK / 256;   // staged elements per thread
