@@ -51,8 +51,10 @@ def run_batched(args, circ):
     import torch
     from paper_2511_05719_amd import TTNEngine
     B = args.batch
+    free0, _ = torch.cuda.mem_get_info()
     eng = TTNEngine(circ.n_qubits, B, circ.leaf_of_qubit, chi_max=64, cutoff=1e-10, dtype="c64",
                     seed=args.seed)
+    free1, _ = torch.cuda.mem_get_info()
     ol = eng.upload(circ)
     for w in range(args.warmup):
         eng.run_circuit(ol, theta=theta_rows(circ, B, w * B), traj_offset=w * B, stats=False)
@@ -76,6 +78,7 @@ def run_batched(args, circ):
     fail = eng.decode(res.records, circ.data_rec, circ.code.checks)
     p_fail = float(fail.float().mean().item())
     eng.close()
+    st["engine_device_gib"] = (free0 - free1) / 2 ** 30
     return t1 - t0, prof, st, p_fail
 
 
@@ -178,7 +181,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--batch", type=int, default=2048)
     ap.add_argument("--rounds", type=int, default=5)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--plain-shots", type=int, default=4)
@@ -286,7 +289,8 @@ def main():
         "run_stats": {"p_fail": p_fail, "max_rank": st.get("max_rank"),
                       "mean_discarded_weight": st.get("discarded_weight", 0.0) / args.batch,
                       "hops_per_batch": st.get("hops"), "block_hops_per_batch": st.get("block_hops"),
-                      "launches_per_batch": st.get("launches")},
+                      "launches_per_batch": st.get("launches"),
+                      "engine_device_gib": st.get("engine_device_gib")},
     }
     print(json.dumps(out))
 

@@ -565,7 +565,7 @@ __global__ void __launch_bounds__(1024) k_jacobi_vectors(EighDesc d) {
 }
 
 // ---------------------------------------------------------------------------
-// Small problems (n <= 32): one wavefront per matrix, the full matrix and V
+// Small problems (n <= 16): one wavefront per matrix, the full matrix and V
 // in LDS, several matrices per workgroup.  Every step's 2 x 2 blocks (P, Q)
 // over all P, Q partition the matrix, so the lanes update disjoint entries;
 // a wavefront's LDS operations complete in order, so consecutive steps need
@@ -803,14 +803,13 @@ hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st) {
   const int n2 = nsub + (nsub & 1);
   const size_t gbytes = (size_t)n2 * (n2 + 1) / 2 * sizeof(double2);
   const long long nprob = (long long)batch * nb;
-  // one wavefront per matrix: always for n <= 16, and up to 32 once there
-  // are enough matrices to give every SIMD of the chip a few of them;
-  // otherwise the workgroup kernel below spreads each matrix over 8 wavefronts
-  if (n2 <= 16 || (n2 <= 32 && nprob >= 4096)) {
+  // one wavefront per matrix for n <= 16; above, the workgroup kernel below
+  // spreads each matrix over 8 wavefronts (faster per matrix from n = 24 on,
+  // at any batch)
+  if (n2 <= 16) {
     const unsigned grid = (unsigned)((nprob + 3) / 4);
     if (n2 <= 8) hipLaunchKernelGGL(k_jacobi_wave<8>, dim3(grid), dim3(256), 0, st, d, nprob);
-    else if (n2 <= 16) hipLaunchKernelGGL(k_jacobi_wave<16>, dim3(grid), dim3(256), 0, st, d, nprob);
-    else hipLaunchKernelGGL(k_jacobi_wave<32>, dim3(grid), dim3(256), 0, st, d, nprob);
+    else hipLaunchKernelGGL(k_jacobi_wave<16>, dim3(grid), dim3(256), 0, st, d, nprob);
     return hipGetLastError();
   }
   const dim3 grid((unsigned)nprob);

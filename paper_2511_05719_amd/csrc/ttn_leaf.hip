@@ -259,60 +259,70 @@ hipError_t launch_leaf_ops(const LeafBatch& b, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
+// One row per grid row (blockIdx.y, striding by gridDim.y); per-row element
+// indices fit 32 bits (a node holds at most 2^31 entries per row).
 template <typename S>
-__global__ void __launch_bounds__(256) k_extend(ExtendDesc d, long long total) {
-  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= total) return;
+__global__ void __launch_bounds__(256) k_extend(ExtendDesc d, int batch, int per) {
+  const int rr = blockIdx.x * blockDim.x + threadIdx.x;
+  if (rr >= per) return;
   int D[3] = {d.d0, d.d1, d.d2};
   int E[3] = {d.d0, d.d1, d.d2};
   E[d.leg_in] *= 2;
   if (d.leg_out >= 0) E[d.leg_out] *= 2;
-  const long long per = (long long)E[0] * E[1] * E[2];
-  const long long t = gid / per;
-  const long long rr = gid % per;
-  long long r = rr;
   int idx[3];
-  idx[2] = (int)(r % E[2]); r /= E[2];
-  idx[1] = (int)(r % E[1]);
-  idx[0] = (int)(r / E[1]);
-  const S* src = (const S*)d.src + t * d.src_stride;
-  S* dst = (S*)d.dst + t * d.dst_stride;
-  double2 v = make_double2(0.0, 0.0);
+  idx[2] = rr % E[2];
+  const int r1 = rr / E[2];
+  idx[1] = r1 % E[1];
+  idx[0] = r1 / E[1];
+  // the source entry (and, for mode 1, the block and physical row) is the
+  // same for every trajectory
+  int src_off = -1, src_off2 = -1, k = 0, row = 0;
   if (d.mode == 0) {
     const int kin = idx[d.leg_in] / D[d.leg_in];
     const int kout = idx[d.leg_out] / D[d.leg_out];
     if (kin == kout) {
       int j[3] = {idx[0], idx[1], idx[2]};
-      j[d.leg_in] %= D[d.leg_in];
-      j[d.leg_out] %= D[d.leg_out];
-      v = to_d2(src[((long long)j[0] * D[1] + j[1]) * D[2] + j[2]]);
+      j[d.leg_in] -= kin * D[d.leg_in];
+      j[d.leg_out] -= kout * D[d.leg_out];
+      src_off = (j[0] * D[1] + j[1]) * D[2] + j[2];
     }
   } else {
     // doubled leg_in = (k, u); block k = bmat[k] applied on physical leg ctrl_leg
     // (the projector at the start of a controlled gate, or B_k at its end)
-    const int k = idx[d.leg_in] / D[d.leg_in];
+    k = idx[d.leg_in] / D[d.leg_in];
     int j[3] = {idx[0], idx[1], idx[2]};
-    j[d.leg_in] %= D[d.leg_in];
-    const int row = j[d.ctrl_leg];
-    for (int c = 0; c < 2; ++c) {
-      int jj[3] = {j[0], j[1], j[2]};
-      jj[d.ctrl_leg] = c;
-      const double2 bm = make_double2(d.bmat[k][row][c][0], d.bmat[k][row][c][1]);
-      v = cadd(v, cmul(bm, to_d2(src[((long long)jj[0] * D[1] + jj[1]) * D[2] + jj[2]])));
-    }
+    j[d.leg_in] -= k * D[d.leg_in];
+    row = j[d.ctrl_leg];
+    j[d.ctrl_leg] = 0;
+    src_off = (j[0] * D[1] + j[1]) * D[2] + j[2];
+    j[d.ctrl_leg] = 1;
+    src_off2 = (j[0] * D[1] + j[1]) * D[2] + j[2];
   }
-  dst[rr] = from_d2<S>(v);
+  for (long long t = blockIdx.y; t < batch; t += gridDim.y) {
+    const S* src = (const S*)d.src + t * d.src_stride;
+    S* dst = (S*)d.dst + t * d.dst_stride;
+    double2 v = make_double2(0.0, 0.0);
+    if (d.mode == 0) {
+      if (src_off >= 0) v = to_d2(src[src_off]);
+    } else {
+      const double2 b0 = make_double2(d.bmat[k][row][0][0], d.bmat[k][row][0][1]);
+      const double2 b1 = make_double2(d.bmat[k][row][1][0], d.bmat[k][row][1][1]);
+      v = cadd(cmul(b0, to_d2(src[src_off])), cmul(b1, to_d2(src[src_off2])));
+    }
+    dst[rr] = from_d2<S>(v);
+  }
 }
 
 hipError_t launch_extend(const ExtendDesc& d, int batch, hipStream_t st) {
   int E[3] = {d.d0, d.d1, d.d2};
   E[d.leg_in] *= 2;
   if (d.leg_out >= 0) E[d.leg_out] *= 2;
-  const long long total = (long long)batch * E[0] * E[1] * E[2];
-  if (total <= 0) return hipSuccess;
-  dim3 grid((unsigned)((total + 255) / 256));
-  if (d.c128) hipLaunchKernelGGL(k_extend<double2>, grid, dim3(256), 0, st, d, total);
-  else hipLaunchKernelGGL(k_extend<float2>, grid, dim3(256), 0, st, d, total);
+  const long long per = (long long)E[0] * E[1] * E[2];
+  if (per <= 0 || batch <= 0) return hipSuccess;
+  if (per >= (1ll << 31)) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((per + 255) / 256), (unsigned)std::min(batch, 65535));
+  if (d.c128) hipLaunchKernelGGL(k_extend<double2>, grid, dim3(256), 0, st, d, batch, (int)per);
+  else hipLaunchKernelGGL(k_extend<float2>, grid, dim3(256), 0, st, d, batch, (int)per);
   return hipGetLastError();
 }
 

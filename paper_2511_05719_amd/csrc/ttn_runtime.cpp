@@ -123,6 +123,7 @@ struct ttn_ctx {
   int* nk_host = nullptr;                   // [4] pinned host copy
   // stats
   int64_t hops = 0, launches = 0, block_hops = 0;
+  int last_kb[2] = {0, 0};     // batch-max kept counts of the two blocks of the last block move
   ttn_ctx* adj = nullptr;      // twin context holding the adjoint state (created on first use)
   double gemm_flops = 0.0, gram_flops = 0.0;
   std::string err;
@@ -415,11 +416,38 @@ static ttn_status leg_apply(ttn_ctx* ctx, int node, int src_buf, std::array<int,
 // output has too few tiles to occupy the chip, K is split over up to
 // ctx->gslices workgroups per tile, each writing its partial product to its
 // own slice of G (the eigensolver sums the slices); *nsplit returns the count.
+// With a controlled gate's index on two legs of the node (the outgoing leg
+// `leg`, split in halves, and the incoming leg in_leg, whose block b spans
+// rows [b kin0, b kin0 + kin[b]) after the previous block move), the node is
+// zero unless both legs are in the same block, so block b of the Gram
+// matrix needs only the incoming rows of block b: K runs over
+// kh = max(kin) incoming rows, from 0 for block 0 and from d[in_leg] - kh
+// for block 1 (both ranges cover their block and stay inside the leg).
 static ttn_status gram(ttn_ctx* ctx, int node, int src_buf, std::array<int, 3> d, int leg, int blocks,
-                       int* nsplit) {
+                       int* nsplit, int in_leg = -1, const int* kin = nullptr) {
   GemmDesc g = gram_desc(ctx->bufs[src_buf].p, d, leg, ctx->G);
   ext_gram(ctx, g, node, leg, blocks > 1);
   if (blocks > 1) gram_split(g);
+  // (skipped when the split does not describe the leg, e.g. after a move in
+  // which every row lost its norm)
+  if (blocks > 1 && in_leg >= 0 && in_leg != leg && kin && kin[0] >= 0 && kin[1] >= 0 &&
+      kin[0] + kin[1] == d[in_leg] && std::max(kin[0], kin[1]) >= 1) {
+    const int din = d[in_leg];
+    const int kh = std::max(kin[0], kin[1]);
+    const bool outer = in_leg < 3 - leg - in_leg;      // K = (lower leg, higher leg) of the other two
+    const long long s_in = outer ? g.sAl1 : g.sAl2;   // A and B share the node's strides
+    const long long shift = (long long)(din - kh) * s_in;
+    g.sAg += shift;
+    g.sBg += shift;
+    if (outer) {
+      g.K = kh * g.Kin;
+      g.eKo = 0;
+    } else {
+      g.K = (g.K / g.Kin) * kh;
+      g.Kin = kh;
+      g.eKi = 0;
+    }
+  }
   const long long wgs = (long long)ctx->B * std::max(g.G2, 1) * zgemm_tiles(g);
   int ks = (int)std::min<long long>((kGramTargetWgs + wgs - 1) / wgs, ctx->gslices);
   ks = std::max(1, std::min(ks, g.K / 256));
@@ -459,7 +487,8 @@ static ttn_status read_kept(ttn_ctx* ctx, int kb[2]) {
   return TTN_OK;
 }
 
-static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int new_pad, int blocks = 1) {
+static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int new_pad, int blocks = 1,
+                      int in_leg = -1, const int* kin = nullptr) {
   const int lx = leg_toward(x, y), ly = leg_toward(y, x);
   const int e = bond_node(x, y);
   std::array<int, 3> dx = ctx->dims[x], dy = ctx->dims[y];
@@ -469,7 +498,7 @@ static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int ne
     return fail(ctx, TTN_EINVAL, "internal: bond dimension exceeds workspace");
   if (blocks > 1 && ((n & 1) || (new_pad & 1))) return fail(ctx, TTN_EINVAL, "internal: odd block size");
   int gsplit = 1;
-  TTN_TRY(gram(ctx, x, ctx->node_buf[x], dx, lx, blocks, &gsplit));
+  TTN_TRY(gram(ctx, x, ctx->node_buf[x], dx, lx, blocks, &gsplit, in_leg, kin));
   EighDesc ed{};
   ed.G = ctx->G; ed.n = n; ed.new_pad = new_pad; ed.cap = cap; ed.cutoff = cutoff;
   ed.gsplit = gsplit; ed.gslice = gslice_elems(ctx);
@@ -497,6 +526,8 @@ static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int ne
   if (kb[0] < 0 || kb[1] < 0 || kb[0] + kb[1] > new_pad || (blocks > 1 && std::max(kb[0], kb[1]) > new_pad / 2))
     return fail(ctx, TTN_EDEVICE, "internal: kept count out of range");
   int newd = blocks > 1 ? kb[0] + kb[1] : kb[0];
+  ctx->last_kb[0] = kb[0];
+  ctx->last_kb[1] = blocks > 1 ? kb[1] : 0;
   if (newd == 0) {             // every row lost its norm (flagged): keep one zero column
     newd = 1;
     kb[0] = 1;
@@ -637,6 +668,8 @@ static ttn_status controlled_gate(ttn_ctx* ctx, int qs, const double P[2][2][2][
     ctx->ext_ok[ns] = 0;
     if (ctx->prof) TTN_CHECK_HIP(launch_ledger_double(ctx->adim, ctx->L, ns, 2, -1, ctx->B, ctx->st));
   }
+  bool prev_block = false;      // the last forward move was a block move (kin: its kept counts)
+  int kin[2] = {0, 0};
   for (int i = 0; i < m; ++i) {
     const int x = path[i], y = path[i + 1];
     const int ly = leg_toward(y, x);
@@ -678,11 +711,17 @@ static ttn_status controlled_gate(ttn_ctx* ctx, int qs, const double P[2][2][2][
     const int qnear = (y == x / 2) ? ctx->nq_below[x] : ctx->N - ctx->nq_below[y];
     const long long near_dim = qnear >= 30 ? (1ll << 30) : (1ll << qnear);
     if (n >= kBlockMin) {
-      // the Gram matrix is block diagonal in k: two independent halves
-      TTN_TRY(hop(ctx, x, y, ctx->cutoff, n / 2, n, 2));
+      // the Gram matrix is block diagonal in k: two independent halves;
+      // after a block move into x, x's incoming leg is block structured too
+      const int in_leg = prev_block ? leg_toward(x, path[i - 1]) : -1;
+      TTN_TRY(hop(ctx, x, y, ctx->cutoff, n / 2, n, 2, in_leg, kin));
+      prev_block = true;
+      kin[0] = ctx->last_kb[0];
+      kin[1] = ctx->last_kb[1];
     } else {
       const int pad = (int)std::min<long long>(n, near_dim);
       TTN_TRY(hop(ctx, x, y, ctx->cutoff, pad, pad));
+      prev_block = false;
     }
   }
   for (int i = m; i > 0; --i) TTN_TRY(hop_truncating(ctx, path[i], path[i - 1]));

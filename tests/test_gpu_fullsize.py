@@ -102,3 +102,39 @@ def test_d7_chi128_runs():
     assert np.all(np.isfinite(lp)) and np.all(lp <= 1e-9)
     assert set(np.unique(res.records.cpu().numpy()).tolist()) <= {0, 1}
     eng.close()
+
+
+def test_bench_configuration_statistics_do_not_depend_on_the_batch():
+    # the benchmark's own workload and launch configuration: d=5, 5 rounds,
+    # SRX on the 8-point theta grid, default layout, chi_max = 64, cutoff
+    # 1e-10, complex64, 2048 trajectories.  chi = 64 truncates heavily here
+    # (the circuit's exact bond dimension is 2048) and many cuts fall inside
+    # clusters of equal Schmidt values, where which vectors are kept is decided
+    # by rounding: single trajectories are then not reproducible across batch
+    # sizes (tile shapes and solver variants follow the batch), in complex128
+    # too.  What must hold at any size: every row normalised (no flags), log P
+    # finite and <= 0, ranks within chi_max, records bits, and the batch's
+    # statistics the same as those of an independent batch of 256 other
+    # trajectories (mean log P, mean discarded weight, fraction of 1s among
+    # the records) within 5 standard errors
+    from paper_2511_05719_amd import TTNEngine
+    circ = build_circuit(5, 5, "srx")
+    out = {}
+    for rows, off in ((2048, 4096), (256, 65536)):
+        th = _theta_rows(circ, rows)
+        eng = TTNEngine(circ.n_qubits, rows, circ.leaf_of_qubit, chi_max=64, cutoff=1e-10, dtype="c64", seed=2)
+        res = eng.run_circuit(eng.upload(circ), theta=th, gamma=0.0, traj_offset=off)
+        st = res.stats
+        rec, lp = res.records.cpu().numpy(), res.logp.cpu().numpy()
+        eng.close()
+        assert st["flagged_rows"] == 0 and st["max_rank"] <= 64
+        assert np.all(np.isfinite(lp)) and np.all(lp <= 1e-9)
+        assert set(np.unique(rec).tolist()) <= {0, 1}
+        assert 0.0 <= st["discarded_weight"] / rows < 100.0
+        out[rows] = (lp, rec.mean(axis=1), st["discarded_weight"] / rows)
+    (la, fa, da), (lb, fb, db) = out[2048], out[256]
+    se = np.sqrt(la.var() / len(la) + lb.var() / len(lb))
+    assert abs(la.mean() - lb.mean()) < 5 * se, (la.mean(), lb.mean(), se)
+    se = np.sqrt(fa.var() / len(fa) + fb.var() / len(fb))
+    assert abs(fa.mean() - fb.mean()) < 5 * se, (fa.mean(), fb.mean(), se)
+    assert abs(da - db) < 0.2 * max(da, db)
