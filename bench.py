@@ -176,6 +176,27 @@ def cpu_oracle(circ, seed):
     return rate, (t2 - t0)
 
 
+# HBM traffic of one contraction launch at this workload and B=2048 (rocprofv3
+# FETCH_SIZE / WRITE_SIZE passes scaled by a 256 MiB copy, see
+# profiles/ttn_contract_d5_chi64_b2048_hbm_traffic.txt), valid for the GEMM
+# source it was measured on: reported only while that source is unchanged
+CONTRACT_TRAFFIC = {"batch": 2048, "bytes_per_launch": 1.2969e9,
+                    "gemm_sha256": "d03e3db73b3bb3a63e7dd63edc5b0f87fff7c9ac9fac1f27bf4e77e4c88f46de",
+                    "profile": "profiles/ttn_contract_d5_chi64_b2048_hbm_traffic.txt"}
+
+
+def contract_traffic(batch):
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2511_05719_amd", "csrc", "ttn_gemm.hip")
+    try:
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if h != CONTRACT_TRAFFIC["gemm_sha256"] or batch != CONTRACT_TRAFFIC["batch"]:
+        return None
+    return CONTRACT_TRAFFIC["bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,10 +257,14 @@ def main():
     d = prof[dom]
     bound, peak = bound_of[dom]
     achieved = d["alg_flops"] / max(d["ms"] / 1e3, 1e-12)
+    traffic = contract_traffic(args.batch) if dom == "contract" else None
     roof = {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": None, "kernel_class": dom, "launches": d["launches"],
+            "frac": achieved / peak, "traffic": traffic, "kernel_class": dom, "launches": d["launches"],
             "avg_ms": d["ms"] / max(d["launches"], 1), "share_of_gpu_time": d["ms"] / total_ms,
             "per_unit": per_unit["eigh" if dom.startswith("eigh") else dom]}
+    if traffic is not None:
+        roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 PMC, " + CONTRACT_TRAFFIC["profile"] + ")"
+        roof["traffic_rate_tbs"] = traffic / (roof["avg_ms"] / 1e3) / 1e12
 
     plain = None
     if not args.no_plain:
