@@ -56,10 +56,14 @@ def run_batched(args, circ):
                     seed=args.seed)
     free1, _ = torch.cuda.mem_get_info()
     ol = eng.upload(circ)
+    # GEMM tile shapes measured during the warm-up (the timed steps reuse
+    # the choices and measure nothing)
+    eng.autotune(not args.no_autotune and args.warmup > 0)
     for w in range(args.warmup):
         eng.run_circuit(ol, theta=theta_rows(circ, B, w * B), traj_offset=w * B, stats=False)
         torch.cuda.synchronize()
         log(f"warmup step {w} done")
+    tuned = eng.autotune(False)
     params = [theta_rows(circ, B, (args.warmup + k) * B) for k in range(args.steps)]
     params_dev = [torch.as_tensor(p, device="cuda") for p in params]
     eng.profile(True)
@@ -79,6 +83,7 @@ def run_batched(args, circ):
     p_fail = float(fail.float().mean().item())
     eng.close()
     st["engine_device_gib"] = (free0 - free1) / 2 ** 30
+    st["autotune"] = {"shapes_measured": tuned[0], "differs_from_fixed_rule": tuned[1]}
     return t1 - t0, prof, st, p_fail
 
 
@@ -108,8 +113,10 @@ def run_optimized(args):
     B = args.batch
     eng = TTNEngine(circ.n_qubits, B, circ.leaf_of_qubit, chi_max=64, cutoff=1e-10, dtype="c64", seed=args.seed)
     ol = eng.upload(circ)
+    eng.autotune(not args.no_autotune)
     eng.run_circuit(ol, theta=theta_rows(circ, B, 0), traj_offset=0, stats=False)
     torch.cuda.synchronize()
+    eng.autotune(False)
     steps = 2
     t0 = time.perf_counter()
     for k in range(steps):
@@ -209,6 +216,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the clustered-layout and gradient legs")
+    ap.add_argument("--no-autotune", action="store_true", help="fixed-rule GEMM tile shapes (no measuring "
+                    "in the warm-up)")
     ap.add_argument("--grad-records", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -315,7 +324,8 @@ def main():
                       "mean_discarded_weight": st.get("discarded_weight", 0.0) / args.batch,
                       "hops_per_batch": st.get("hops"), "block_hops_per_batch": st.get("block_hops"),
                       "launches_per_batch": st.get("launches"),
-                      "engine_device_gib": st.get("engine_device_gib")},
+                      "engine_device_gib": st.get("engine_device_gib"),
+                      "gemm_tile_autotune": st.get("autotune")},
     }
     print(json.dumps(out))
 

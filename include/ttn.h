@@ -293,6 +293,23 @@ enum {
 ttn_status ttn_profile_enable(ttn_ctx* ctx, int32_t on);
 ttn_status ttn_profile_read(ttn_ctx* ctx, int32_t cls, double* ms, int64_t* launches, double* alg_flops);
 
+/* Tile-shape tuner for the batched contractions and Gram matrices (no
+ * passage of the paper: launch tuning of this library).  Every such launch
+ * runs in one of four output-tile shapes (64x64, 128x32, 32x128, 32x32 with
+ * the K range split over the wavefronts); by default a fixed rule on the
+ * output dimensions picks it.  With on = 1, a launch whose shape (kind,
+ * M, N, K, inner/outer K split, batch sizes, split-K, operand layouts) has
+ * not been measured yet first runs once in every tile shape on its own
+ * operands, timed with events on the context's stream (the stream is
+ * synchronised: tuning stalls the host), and the fastest is kept for that
+ * shape; results do not depend on the choice beyond floating-point
+ * summation order.  on = 0 stops measuring new shapes but keeps using the
+ * measured ones; on = -1 forgets them and returns to the fixed rule.
+ * shapes / changed (may be null) receive the number of shapes measured and
+ * how many of them differ from the fixed rule.  Errors: TTN_EINVAL for
+ * other values of on. */
+ttn_status ttn_autotune(ttn_ctx* ctx, int32_t on, int64_t* shapes, int64_t* changed);
+
 /* Library build identification (no GPU needed). */
 const char* ttn_version(void);
 

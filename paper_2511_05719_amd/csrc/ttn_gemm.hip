@@ -267,9 +267,10 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
       }
 }
 
-// Output tile shape chosen for a problem: 64 x 64 in general, 128 x 32 or
-// 32 x 128 when one side is at most 32, 32 x 32 with the K chunk split over
-// the four waves when both are.
+// Output tile shape of a problem by the fixed rule: 64 x 64 in general,
+// 128 x 32 or 32 x 128 when one side is at most 32, 32 x 32 with the K chunk
+// split over the four waves when both are (the runtime's tuner may pick
+// another of the four by measurement).
 enum TileCfg { TILE_64x64 = 0, TILE_128x32 = 1, TILE_32x128 = 2, TILE_32x32 = 3 };
 static int tile_cfg(int M, int N) {
   if (M <= 32 && N <= 32) return TILE_32x32;
@@ -285,6 +286,8 @@ static void tile_dims(int cfg, int* tm, int* tn) {
     default: *tm = 64; *tn = 64; return;
   }
 }
+
+int zgemm_rule_cfg(const GemmDesc& d) { return tile_cfg(d.M, d.N); }
 
 long long zgemm_tiles(const GemmDesc& d) {
   int tm, tn;
@@ -303,7 +306,7 @@ hipError_t launch_cfg(GemmDesc d, int batch, hipStream_t st) {
 }
 
 template <typename SA, typename SB, typename SC, typename R>
-hipError_t launch_zgemm_t(GemmDesc d, int batch, hipStream_t st) {
+hipError_t launch_zgemm_t(GemmDesc d, int batch, hipStream_t st, int cfg) {
   if (d.M <= 0 || d.N <= 0 || batch <= 0) return hipSuccess;
   if (d.K <= 0) return hipErrorInvalidValue;
   if (d.Kin <= 0) d.Kin = d.K;
@@ -312,7 +315,8 @@ hipError_t launch_zgemm_t(GemmDesc d, int batch, hipStream_t st) {
   if (d.H < 1 || d.ksplit > 64) return hipErrorInvalidValue;
   if (d.ext && (d.K % d.Kin != 0 || d.ext_stride < 1)) return hipErrorInvalidValue;
   if (d.ext && (d.eM < 0 || d.eN < 0 || d.eH < 0 || d.eKo < 0 || d.eKi < 0) && !d.knew) return hipErrorInvalidValue;
-  switch (tile_cfg(d.M, d.N)) {
+  if (cfg < 0 || cfg >= kZgemmCfgs) cfg = tile_cfg(d.M, d.N);
+  switch (cfg) {
     case TILE_128x32: return launch_cfg<SA, SB, SC, R, 4, 1, 1>(d, batch, st);
     case TILE_32x128: return launch_cfg<SA, SB, SC, R, 1, 4, 1>(d, batch, st);
     case TILE_32x32: return launch_cfg<SA, SB, SC, R, 1, 1, 4>(d, batch, st);
@@ -320,12 +324,12 @@ hipError_t launch_zgemm_t(GemmDesc d, int batch, hipStream_t st) {
   }
 }
 
-hipError_t launch_zgemm(const GemmDesc& d, int batch, int kind, hipStream_t st) {
+hipError_t launch_zgemm(const GemmDesc& d, int batch, int kind, hipStream_t st, int cfg) {
   switch (kind) {
-    case GEMM_C64:        return launch_zgemm_t<float2, float2, float2, float>(d, batch, st);
-    case GEMM_C128:       return launch_zgemm_t<double2, double2, double2, double>(d, batch, st);
-    case GEMM_GRAM_C64:   return launch_zgemm_t<float2, float2, double2, double>(d, batch, st);
-    case GEMM_GRAM_C128:  return launch_zgemm_t<double2, double2, double2, double>(d, batch, st);
+    case GEMM_C64:        return launch_zgemm_t<float2, float2, float2, float>(d, batch, st, cfg);
+    case GEMM_C128:       return launch_zgemm_t<double2, double2, double2, double>(d, batch, st, cfg);
+    case GEMM_GRAM_C64:   return launch_zgemm_t<float2, float2, double2, double>(d, batch, st, cfg);
+    case GEMM_GRAM_C128:  return launch_zgemm_t<double2, double2, double2, double>(d, batch, st, cfg);
     default: return hipErrorInvalidValue;
   }
 }

@@ -41,8 +41,12 @@ struct GemmDesc {
   int eKo, eKi;             // outer (l / Kin) and inner (l % Kin) parts of K
 };
 
-hipError_t launch_zgemm(const GemmDesc& d, int batch, int kind, hipStream_t st);
-// output tiles per (t, g, h) of the tile shape the launcher picks for d
+// cfg: one of the kZgemmCfgs tile shapes (64x64, 128x32, 32x128, 32x32 with
+// the K chunk split over the waves), or -1 for the fixed rule
+constexpr int kZgemmCfgs = 4;
+hipError_t launch_zgemm(const GemmDesc& d, int batch, int kind, hipStream_t st, int cfg = -1);
+// the fixed rule's tile shape for d, and its output tiles per (t, g, h)
+int zgemm_rule_cfg(const GemmDesc& d);
 long long zgemm_tiles(const GemmDesc& d);
 
 // ---------------------------------------------------------------- EIGH ----

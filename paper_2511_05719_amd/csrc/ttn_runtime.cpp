@@ -28,6 +28,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -124,6 +125,11 @@ struct ttn_ctx {
   // stats
   int64_t hops = 0, launches = 0, block_hops = 0;
   int last_kb[2] = {0, 0};     // batch-max kept counts of the two blocks of the last block move
+  // GEMM tile-shape tuner: per launch shape, the measured fastest tile shape
+  int tune_on = 0;
+  std::map<std::array<long long, 14>, int> tune;
+  int64_t tuned_shapes = 0, tuned_changed = 0;
+  hipEvent_t tune_ev[2] = {nullptr, nullptr};
   ttn_ctx* adj = nullptr;      // twin context holding the adjoint state (created on first use)
   double gemm_flops = 0.0, gram_flops = 0.0;
   std::string err;
@@ -365,6 +371,43 @@ static inline void* offset_ptr(const void* p, long long elems, size_t es) {
   return (void*)((const char*)p + elems * (long long)es);
 }
 
+// One batched GEMM launch of the hot path with its tile shape: the tuned
+// one for this launch shape if the tuner has measured it; with tuning on, a
+// shape not seen before is first run once in each of the four tile shapes on
+// its own operands (every shape computes the same product, overwriting C),
+// timed with events on the context's stream, and the fastest is kept.
+static ttn_status run_gemm(ttn_ctx* ctx, const GemmDesc& g, int kind) {
+  const std::array<long long, 14> key = {kind, g.M, g.N, g.K, g.Kin, g.H, std::max(g.G2, 1), std::max(g.ksplit, 1),
+                                         g.a_m_fast, g.b_n_fast, g.conjA, g.conjB, g.ext != nullptr, ctx->B};
+  auto it = ctx->tune.find(key);
+  int cfg = it != ctx->tune.end() ? it->second : -1;
+  if (cfg < 0 && ctx->tune_on) {
+    if (!ctx->tune_ev[0]) {
+      TTN_CHECK_HIP(hipEventCreate(&ctx->tune_ev[0]));
+      TTN_CHECK_HIP(hipEventCreate(&ctx->tune_ev[1]));
+    }
+    float best_ms = 0.0f;
+    for (int c = 0; c < kZgemmCfgs; ++c) {
+      TTN_CHECK_HIP(launch_zgemm(g, ctx->B, kind, ctx->st, c));          // warm
+      TTN_CHECK_HIP(hipEventRecord(ctx->tune_ev[0], ctx->st));
+      TTN_CHECK_HIP(launch_zgemm(g, ctx->B, kind, ctx->st, c));
+      TTN_CHECK_HIP(hipEventRecord(ctx->tune_ev[1], ctx->st));
+      TTN_CHECK_HIP(hipEventSynchronize(ctx->tune_ev[1]));
+      float ms = 0.0f;
+      TTN_CHECK_HIP(hipEventElapsedTime(&ms, ctx->tune_ev[0], ctx->tune_ev[1]));
+      if (c == 0 || ms < best_ms) {
+        best_ms = ms;
+        cfg = c;
+      }
+    }
+    ctx->tune[key] = cfg;
+    ++ctx->tuned_shapes;
+    if (cfg != zgemm_rule_cfg(g)) ++ctx->tuned_changed;
+  }
+  TTN_CHECK_HIP(launch_zgemm(g, ctx->B, kind, ctx->st, cfg));
+  return TTN_OK;
+}
+
 // T' = W applied on leg `leg` of the node in src_buf, written to dst_buf with
 // that leg of dimension newd.  W is [rows][wrows][n].  blocks = 2: W is block
 // diagonal with diagonal blocks [wrows/2][n/2]; block b contributes kb[b]
@@ -407,7 +450,7 @@ static ttn_status leg_apply(ttn_ctx* ctx, int node, int src_buf, std::array<int,
     ctx->gemm_flops += 8.0 * (double)g.M * g.N * g.K * g.H * ctx->B;
     ++ctx->launches;
     ProfScope ps(ctx, CLS_GEMM);
-    TTN_CHECK_HIP(launch_zgemm(g, ctx->B, ctx->c128 ? GEMM_C128 : GEMM_C64, ctx->st));
+    TTN_TRY(run_gemm(ctx, g, ctx->c128 ? GEMM_C128 : GEMM_C64));
   }
   return TTN_OK;
 }
@@ -459,7 +502,7 @@ static ttn_status gram(ttn_ctx* ctx, int node, int src_buf, std::array<int, 3> d
   ctx->gram_flops += 8.0 * (double)g.M * g.N * g.K * std::max(g.G2, 1) * ctx->B;
   ++ctx->launches;
   ProfScope ps(ctx, CLS_GRAM);
-  TTN_CHECK_HIP(launch_zgemm(g, ctx->B, ctx->c128 ? GEMM_GRAM_C128 : GEMM_GRAM_C64, ctx->st));
+  TTN_TRY(run_gemm(ctx, g, ctx->c128 ? GEMM_GRAM_C128 : GEMM_GRAM_C64));
   return TTN_OK;
 }
 
@@ -1056,6 +1099,8 @@ ttn_status ttn_destroy(ttn_ctx* ctx) {
   hipStreamSynchronize(ctx->st);
   if (ctx->adj) ttn_destroy(ctx->adj);
   for (auto& b : ctx->bufs) hipFree(b.p);
+  for (hipEvent_t e : ctx->tune_ev)
+    if (e) hipEventDestroy(e);
   for (int c = 0; c < TTN_NCLASS; ++c)
     for (auto& e : ctx->prof_ev[c]) {
       hipEventDestroy(e.first);
@@ -1852,6 +1897,22 @@ ttn_status ttn_bond_dims(ttn_ctx* ctx, int32_t row, int32_t* dims) {
   dims[0] = 0;
   dims[1] = 1;
   for (int e = 2; e < ctx->L; ++e) dims[e] = r[e];
+  return TTN_OK;
+}
+
+ttn_status ttn_autotune(ttn_ctx* ctx, int32_t on, int64_t* shapes, int64_t* changed) {
+  if (!ctx) return TTN_EINVAL;
+  if (on < -1 || on > 1) return fail(ctx, TTN_EINVAL, "on must be -1, 0 or 1");
+  if (on == -1) {
+    ctx->tune.clear();
+    ctx->tuned_shapes = 0;
+    ctx->tuned_changed = 0;
+    ctx->tune_on = 0;
+  } else {
+    ctx->tune_on = on;
+  }
+  if (shapes) *shapes = ctx->tuned_shapes;
+  if (changed) *changed = ctx->tuned_changed;
   return TTN_OK;
 }
 

@@ -231,6 +231,15 @@ class TTNEngine:
     def profile(self, on: bool = True):
         check(lib().ttn_profile_enable(self._ctx, 1 if on else 0), self._ctx)
 
+    def autotune(self, on) -> tuple:
+        """Tile-shape tuning of the GEMM launches: True measures new shapes,
+        False keeps the measured choices, None forgets them.  Returns
+        (shapes measured, shapes whose choice differs from the fixed rule)."""
+        shapes, changed = C.c_int64(0), C.c_int64(0)
+        mode = -1 if on is None else (1 if on else 0)
+        check(lib().ttn_autotune(self._ctx, mode, C.byref(shapes), C.byref(changed)), self._ctx)
+        return shapes.value, changed.value
+
     def profile_read(self) -> dict:
         out = {}
         for name, cls in _abi.CLASSES.items():

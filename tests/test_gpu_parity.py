@@ -257,3 +257,35 @@ def test_chi128_random_circuit_amplitudes(dtype):
         amp = eng.statevector(r)
         assert np.abs(amp - full[r]).max() < tol, (r, np.abs(amp - full[r]).max())
     eng.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_autotuned_tile_shapes_keep_parity(dtype):
+    # d=3, 3 rounds, SRX + AD at per-row parameters, untruncated: with the
+    # tile-shape tuner measuring every new GEMM shape (run 1), then reusing
+    # its choices without measuring (run 2), records and Kraus branches equal
+    # the oracle's and log P agrees; forgetting the choices returns to the
+    # fixed rule
+    circ = build_circuit(3, 3, "srx+ad")
+    rows = 32
+    g = np.random.default_rng(11)
+    th = g.uniform(0.02, 0.3, (rows, circ.n_loc))
+    ga = g.uniform(1e-3, 2e-2, (rows, circ.n_loc))
+    ref = sv.run(circ, th, ga, 4, np.arange(rows))
+    eng = _engine(circ, rows, dtype=dtype, seed=4)
+    ol = eng.upload(circ)
+    tol = 1e-9 if dtype == "c128" else 2e-4
+    for on in (True, False):
+        eng.autotune(on)
+        res = eng.run_circuit(ol, theta=th, gamma=ga)
+        got, gbr, glp = res.records.cpu().numpy(), res.branches.cpu().numpy(), res.logp.cpu().numpy()
+        same = np.all(got == ref.records, axis=1) & np.all(gbr == ref.branches, axis=1)
+        if dtype == "c128":
+            assert same.all()
+        else:
+            assert same.mean() >= 0.9
+        assert np.abs(glp[same] - ref.logp[same]).max() < tol
+    shapes, changed = eng.autotune(False)
+    assert shapes > 0 and 0 <= changed <= shapes
+    assert eng.autotune(None) == (0, 0)
+    eng.close()
