@@ -110,6 +110,8 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
     Kt = max(ko, 0) * max(ki, 0);
     if (h >= ht || m0 >= Mt || n0 >= Nt) Kt = 0;
   }
+  if (d.band && (m0 >= d.bM1 || m0 + TM <= d.bM0 || n0 >= d.bN1 || n0 + TN <= d.bN0 || h < d.bH0 || h >= d.bH1))
+    Kt = 0;
   // K slice of this split (an empty slice still writes its zero partials)
   const int nchunks = (Kt + TK - 1) / TK;
   const int per = (nchunks + d.ksplit - 1) / d.ksplit;

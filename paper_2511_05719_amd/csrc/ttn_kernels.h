@@ -39,6 +39,11 @@ struct GemmDesc {
   int eM, eN, eH;           // M <= extent(eM) * mM, N <= extent(eN) * mN, H <= extent(eH)
   int mM, mN;
   int eKo, eKi;             // outer (l / Kin) and inner (l % Kin) parts of K
+  // Bands (optional, band = 1): only rows [bM0, bM1), columns [bN0, bN1) and
+  // inner batches [bH0, bH1) can be non-zero; output tiles wholly outside
+  // are written as zeros without K work (a block-structured leg of the node)
+  int band;
+  int bM0, bM1, bN0, bN1, bH0, bH1;
 };
 
 // cfg: one of the kZgemmCfgs tile shapes (64x64, 128x32, 32x128, 32x32 with

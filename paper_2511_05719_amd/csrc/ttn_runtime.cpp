@@ -412,8 +412,32 @@ static ttn_status run_gemm(ttn_ctx* ctx, const GemmDesc& g, int kind) {
 // that leg of dimension newd.  W is [rows][wrows][n].  blocks = 2: W is block
 // diagonal with diagonal blocks [wrows/2][n/2]; block b contributes kb[b]
 // rows, placed at new indices [kb[0] * b, kb[0] * b + kb[b]) (newd = kb[0] + kb[1]).
+// A leg of a node that carries a controlled gate's block index alongside
+// the contracted leg: the node is zero unless both are in the same block,
+// and block b of that leg spans [lo[b], hi[b]).
+struct Partner {
+  int leg = -1;
+  int lo[2] = {0, 0};
+  int hi[2] = {0, 0};
+};
+
+// The band of the GEMM's flattened rest dimension that block b of a partner
+// leg maps to (nothing when the partner leg is the inner, faster part of a
+// flattened dimension: its band would be strided).
+static void set_band(GemmDesc& g, std::array<int, 3> d, int leg, const Partner& pt, int b) {
+  const int lo = pt.lo[b], hi = pt.hi[b];
+  g.bM0 = 0; g.bM1 = 1 << 30; g.bN0 = 0; g.bN1 = 1 << 30; g.bH0 = 0; g.bH1 = 1 << 30;
+  g.band = 1;
+  if (leg == 0 && pt.leg == 1) { g.bN0 = lo * d[2]; g.bN1 = hi * d[2]; }
+  else if (leg == 2 && pt.leg == 0) { g.bM0 = lo * d[1]; g.bM1 = hi * d[1]; }
+  else if (leg == 1 && pt.leg == 0) { g.bH0 = lo; g.bH1 = hi; }
+  else if (leg == 1 && pt.leg == 2) { g.bN0 = lo; g.bN1 = hi; }
+  else g.band = 0;
+}
+
 static ttn_status leg_apply(ttn_ctx* ctx, int node, int src_buf, std::array<int, 3> d, int leg, const void* W,
-                            int wrows, int newd, int dst_buf, int blocks = 1, const int* kb = nullptr) {
+                            int wrows, int newd, int dst_buf, int blocks = 1, const int* kb = nullptr,
+                            const Partner* pt = nullptr) {
   const int n = d[leg];
   const bool wA = (leg != 2);
   const long long capT = buf_elems(ctx, src_buf), capW = ws_elems(ctx), capC = buf_elems(ctx, dst_buf);
@@ -444,6 +468,7 @@ static ttn_status leg_apply(ttn_ctx* ctx, int node, int src_buf, std::array<int,
       if (wA) { g.A = offset_ptr(g.A, oW, ctx->es); g.B = offset_ptr(g.B, oT, ctx->es); }
       else { g.A = offset_ptr(g.A, oT, ctx->es); g.B = offset_ptr(g.B, oW, ctx->es); }
       g.C = offset_ptr(g.C, oC, ctx->es);
+      if (pt && pt->leg >= 0 && pt->leg != leg) set_band(g, d, leg, *pt, b);
     }
     if (!gemm_fits(g, ctx->B, wA ? capW - oW : capT - oT, wA ? capT - oT : capW - oW, capC - oC))
       return fail(ctx, TTN_EINVAL, "internal: contraction exceeds its buffers");
@@ -531,7 +556,8 @@ static ttn_status read_kept(ttn_ctx* ctx, int kb[2]) {
 }
 
 static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int new_pad, int blocks = 1,
-                      int in_leg = -1, const int* kin = nullptr) {
+                      int in_leg = -1, const int* kin = nullptr, const Partner* px = nullptr,
+                      const Partner* py = nullptr) {
   const int lx = leg_toward(x, y), ly = leg_toward(y, x);
   const int e = bond_node(x, y);
   std::array<int, 3> dx = ctx->dims[x], dy = ctx->dims[y];
@@ -577,11 +603,11 @@ static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int ne
   }
   const int bx = acquire(ctx, ctx->node_cls[x]);
   if (bx < 0) return fail(ctx, TTN_EINVAL, "internal: pool exhausted");
-  TTN_TRY(leg_apply(ctx, x, ctx->node_buf[x], dx, lx, ctx->Wi, new_pad, newd, bx, blocks, kb));
+  TTN_TRY(leg_apply(ctx, x, ctx->node_buf[x], dx, lx, ctx->Wi, new_pad, newd, bx, blocks, kb, px));
   adopt(ctx, x, bx);
   const int by = acquire(ctx, ctx->node_cls[y]);
   if (by < 0) return fail(ctx, TTN_EINVAL, "internal: pool exhausted");
-  TTN_TRY(leg_apply(ctx, y, ctx->node_buf[y], dy, ly, ctx->Wa, new_pad, newd, by, blocks, kb));
+  TTN_TRY(leg_apply(ctx, y, ctx->node_buf[y], dy, ly, ctx->Wa, new_pad, newd, by, blocks, kb, py));
   adopt(ctx, y, by);
   // the bond's new per-row extents: the kept counts (a block move leaves
   // them untrusted until the truncating sweep re-factors the bond)
@@ -757,7 +783,21 @@ static ttn_status controlled_gate(ttn_ctx* ctx, int qs, const double P[2][2][2][
       // the Gram matrix is block diagonal in k: two independent halves;
       // after a block move into x, x's incoming leg is block structured too
       const int in_leg = prev_block ? leg_toward(x, path[i - 1]) : -1;
-      TTN_TRY(hop(ctx, x, y, ctx->cutoff, n / 2, n, 2, in_leg, kin));
+      // the legs that carry the index next to the moving bond: x's incoming
+      // leg (blocks of the previous move) and y's outgoing leg (halves)
+      Partner px, py;
+      if (in_leg >= 0 && kin[0] + kin[1] == ctx->dims[x][in_leg]) {
+        px.leg = in_leg;
+        px.lo[0] = 0; px.hi[0] = kin[0];
+        px.lo[1] = kin[0]; px.hi[1] = kin[0] + kin[1];
+      }
+      if (y != ne) {
+        py.leg = leg_toward(y, path[i + 2]);
+        const int half = ctx->dims[y][py.leg] / 2;
+        py.lo[0] = 0; py.hi[0] = half;
+        py.lo[1] = half; py.hi[1] = 2 * half;
+      }
+      TTN_TRY(hop(ctx, x, y, ctx->cutoff, n / 2, n, 2, in_leg, kin, &px, &py));
       prev_block = true;
       kin[0] = ctx->last_kb[0];
       kin[1] = ctx->last_kb[1];
