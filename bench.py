@@ -246,9 +246,12 @@ def main():
                 "two actual leg dimensions; per diagonal block in block-diagonal moves)",
         "contract": "8 k n r real flops per factor product (k kept, n actual bond dimension, r = product "
                     "of the other two actual leg dimensions)",
+        "move": "8 (r^2 (3n - 2r) / 3 + r^3 / 3) real flops per exact centre move (pivoted Cholesky of "
+                "rank r and the inverse of its triangle, n = problem size)",
     }
     bound_of = {"contract": ("mfma", PEAK["fp32_mfma"]), "gram": ("mfma", PEAK["fp64_mfma"]),
-                "eigh_small": ("alu", PEAK["fp64_valu"]), "eigh_large": ("alu", PEAK["fp64_valu"])}
+                "eigh_small": ("alu", PEAK["fp64_valu"]), "eigh_large": ("alu", PEAK["fp64_valu"]),
+                "move": ("alu", PEAK["fp64_valu"])}
     total_ms = max(sum(v["ms"] for v in prof.values()), 1e-9)
     classes = {}
     for k, (bound, peak) in bound_of.items():

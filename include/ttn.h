@@ -262,6 +262,13 @@ ttn_status ttn_test_gram(ttn_ctx* ctx, int32_t rows, const int32_t* dims3, int32
 ttn_status ttn_test_eigh(ttn_ctx* ctx, int32_t rows, int32_t n, int32_t new_pad, int32_t cap, double cutoff,
                          const double* G, int64_t g_elems, void* W_iso, void* W_abs, int64_t w_elems,
                          int32_t* rank, int32_t* sweeps, int32_t blocks);
+/* ttn_test_move: the factors of an exact centre move by pivoted Cholesky
+ * (the QR route of complex64 contexts): same arguments and outputs as
+ * ttn_test_eigh (without sweeps), n <= 64 per diagonal block; the rank is
+ * the number of pivots above cutoff x trace, at most cap. */
+ttn_status ttn_test_move(ttn_ctx* ctx, int32_t rows, int32_t n, int32_t new_pad, int32_t cap, double cutoff,
+                         const double* G, int64_t g_elems, void* W_iso, void* W_abs, int64_t w_elems,
+                         int32_t* rank, int32_t blocks);
 
 /* Profiling.  While enabled, every kernel launch of the context is
  * bracketed by HIP events on its stream, grouped by kernel class, and the
@@ -274,7 +281,11 @@ ttn_status ttn_test_eigh(ttn_ctx* ctx, int32_t rows, int32_t n, int32_t new_pad,
  *                 two actual leg dimensions), per diagonal block when the
  *                 move is block diagonal;
  *   contraction   8 k n r real flops for each of the two factor products
- *                 (k = kept values).
+ *                 (k = kept values);
+ *   exact move    8 (r^2 (3n - 2r) / 3 + r^3 / 3) real flops for a pivoted
+ *                 Cholesky factorisation of rank r and the inverse of its
+ *                 r x r triangle (n = the problem size after dropping zero
+ *                 rows).
  * The Gram and contraction ledgers track the actual leg dimensions from the
  * last state reset (ttn_init_product, or the start of a run) on: enable
  * profiling before it.  Enabling resets the counters.  ttn_profile_read
@@ -288,7 +299,8 @@ enum {
   TTN_CLASS_LEAF = 4,         /* bottom-node gates, measurements, jumps     */
   TTN_CLASS_EXTEND = 5,       /* controlled-gate index extensions           */
   TTN_CLASS_OTHER = 6,
-  TTN_NCLASS = 7
+  TTN_CLASS_MOVE = 7,         /* pivoted-Cholesky exact centre moves        */
+  TTN_NCLASS = 8
 };
 ttn_status ttn_profile_enable(ttn_ctx* ctx, int32_t on);
 ttn_status ttn_profile_read(ttn_ctx* ctx, int32_t cls, double* ms, int64_t* launches, double* alg_flops);

@@ -37,7 +37,8 @@ constexpr int kThreadsLarge = 1024;   // n > 64: G alone fills the LDS, one work
 int eigh_max_sweeps() { return kMaxSweeps; }
 
 __device__ inline int pidx(int i, int j, int n) {   // packed upper triangle, i <= j
-  return i * (2 * n - i + 1) / 2 + (j - i);
+  // (both factors are below 2^24: the full-rate 24-bit multiply)
+  return (int)((unsigned)__umul24((unsigned)i, (unsigned)(2 * n - i + 1)) >> 1) + (j - i);
 }
 // entry (i, j) of the Hermitian matrix from its packed upper triangle, and
 // its store; branch-free (lanes of one wave take both triangles at once)
@@ -781,6 +782,214 @@ __global__ void __launch_bounds__(256) k_jacobi_wave(EighDesc d, long long nprob
       else { ((float2*)d.W_iso)[o2] = make_float2(0, 0); ((float2*)d.W_abs)[o2] = make_float2(0, 0); }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Exact centre moves by a pivoted Cholesky factorisation of the Gram matrix
+// (the QR factorisation M P = Q R of the node reshaped with the bond as its
+// column, computed through G = M^H M = P R^H R P^T): rank revealing (the
+// pivoting stops once the largest remaining diagonal entry falls to
+// cutoff x trace), no truncation otherwise.  The factors are
+//   W_iso = P_kept R11^-1   (x <- x W_iso = Q, an isometry)
+//   W_abs = R P^T           (y absorbs R)
+// in the same [new_pad][n] row layout as the eigensolver's, rows >= rank
+// zero.  For moves that keep every value above the cutoff (the forward
+// moves of a controlled gate, plain moves of the centre); truncation to chi
+// stays with the eigensolver.  One workgroup of 256 threads per problem
+// (a row, or one diagonal block of a row), n <= 64 after the compaction.
+template <int NMAX>
+__global__ void __launch_bounds__(256) k_pchol(EighDesc d) {
+  static_assert(NMAX == 64, "one lane per column");
+  constexpr int LD = NMAX + 1;
+  // A: the residual; after step k row order[k] holds row k of R on the
+  // columns pivoted at step k or later, and (after the inverse) X = R11^-1
+  // on the columns pivoted before: X[c][a] (c < a) at A[order[a]][order[c]]
+  __shared__ double2 A[NMAX * LD];
+  __shared__ int cidx[NMAX], inv[NMAX], wcount[4];
+  __shared__ int pos[NMAX], order[NMAX];
+  __shared__ double red[256];
+  __shared__ double dmax_s;
+  __shared__ int piv_s;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long pid = blockIdx.x;
+  const Problem pb = problem_of(d, pid);
+  const long long t = pb.t;
+  const double2* G = d.G + t * (long long)d.n * d.n;
+  const int n = compact_rows<4>(d, G, pb, cidx, inv, wcount);
+  for (int i = wave; i < n; i += 4)
+    if (lane < n) A[i * LD + lane] = gram_at(d, G, (long long)(pb.off + cidx[i]) * d.n + pb.off + cidx[lane]);
+  if (threadIdx.x < NMAX) pos[threadIdx.x] = -1;
+  // trace of the whole matrix (both blocks), and of this problem
+  double part = 0.0, own = 0.0;
+  for (int i = threadIdx.x; i < d.n; i += blockDim.x) part += gram_at(d, G, (long long)i * d.n + i).x;
+  if (threadIdx.x < n) own = gram_at(d, G, (long long)(pb.off + cidx[threadIdx.x]) * d.n + pb.off + cidx[threadIdx.x]).x;
+  red[threadIdx.x] = part;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double tr = red[0];
+  __syncthreads();
+  red[threadIdx.x] = own;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double mine = red[0];
+  const bool finite = isfinite(tr) && tr > 0.0;
+  const double tot = d.blocks > 1 ? tr : mine;
+  const double tol = d.cutoff * tot;
+  const int lim = min(min(d.cap, pb.pad), n);
+  int k = 0;
+  if (finite) {
+    for (; k < lim; ++k) {
+      // pivot: the largest remaining diagonal entry (ties: lowest index)
+      if (wave == 0) {
+        double v = (lane < n && pos[lane] < 0) ? A[lane * LD + lane].x : -1.0;
+        int vi = lane;
+        for (int o = 32; o > 0; o >>= 1) {
+          const double ov = __shfl_xor(v, o);
+          const int oi = __shfl_xor(vi, o);
+          if (ov > v || (ov == v && oi < vi)) { v = ov; vi = oi; }
+        }
+        if (lane == 0) { dmax_s = v; piv_s = vi; }
+      }
+      __syncthreads();
+      const double dm = dmax_s;
+      const int p = piv_s;
+      if (!(dm > tol) || !isfinite(dm)) break;          // (uniform: shared values)
+      // rank-one update of the residual with the unscaled pivot row:
+      // A_ij -= conj(A_pi) A_pj / A_pp  (rows by wave, columns by lane)
+      const double idm = 1.0 / dm;
+      const bool colj = lane < n && lane != p && pos[lane] < 0;
+      const double2 apj = colj ? cscale(A[p * LD + lane], idm) : make_double2(0.0, 0.0);
+      for (int i = wave; i < n; i += 4) {
+        if (i == p || pos[i] >= 0) continue;            // (uniform per wave)
+        const double2 api = cconj(A[p * LD + i]);
+        if (colj) A[i * LD + lane] = csub(A[i * LD + lane], cmul(api, apj));
+      }
+      __syncthreads();
+      // row k of R = row p scaled by 1 / sqrt(A_pp); the pivot leaves the
+      // residual
+      if (wave == 0) {
+        const double rkk = sqrt(dm);
+        if (colj) A[p * LD + lane] = cscale(A[p * LD + lane], 1.0 / rkk);
+        if (lane == 0) {
+          A[p * LD + p] = make_double2(rkk, 0.0);
+          pos[p] = k;
+          order[k] = p;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const int r = k;
+  // R11^-1 by columns: 4 neighbouring lanes per column b (b < r), each
+  // summing a quarter of every dot product; X[a][b] for a = b - 1 .. 0 goes
+  // to A[order[b]][order[a]] (X[b][b] = 1 / R[b][b] is not stored)
+  {
+    const int b = threadIdx.x >> 2, sub = threadIdx.x & 3;
+    const bool act = b < r;
+    const int bb = act ? b : 0;                       // the 4 lanes of a column iterate alike
+    const int rowb = act ? order[b] : 0;
+    for (int a = bb - 1; a >= 0; --a) {
+      double2 s = make_double2(0.0, 0.0);
+      if (act) {
+        const int rowa = order[a];
+        for (int c = a + 1 + sub; c <= b; c += 4) {
+          const double2 xcb = (c == b) ? make_double2(1.0 / A[rowb * LD + rowb].x, 0.0) : A[rowb * LD + order[c]];
+          s = cadd(s, cmul(A[rowa * LD + order[c]], xcb));
+        }
+      }
+      s.x += __shfl_xor(s.x, 1); s.y += __shfl_xor(s.y, 1);
+      s.x += __shfl_xor(s.x, 2); s.y += __shfl_xor(s.y, 2);
+      if (act && sub == 0) A[rowb * LD + order[a]] = cscale(s, -1.0 / A[order[a] * LD + order[a]].x);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+  // kept weight, normalisation, counts
+  double resid = 0.0;
+  if (threadIdx.x < n && pos[threadIdx.x] < 0) resid = fmax(A[threadIdx.x * LD + threadIdx.x].x, 0.0);
+  red[threadIdx.x] = resid;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double kept = fmax(mine - red[0], 0.0);
+  double scale;
+  int kk = r;
+  if (d.blocks > 1) {
+    scale = finite ? 1.0 / sqrt(tr) : 0.0;
+  } else if (!(kept > 0.0) || !isfinite(kept) || r == 0) {
+    kk = 0;
+    scale = 0.0;
+  } else {
+    scale = 1.0 / sqrt(kept);
+  }
+  if (threadIdx.x == 0) {
+    if (d.blocks > 1) {
+      if (!finite && d.flags) atomicOr(d.flags + t, 1);
+      if (d.disc_acc && tot > 0.0) atomicAdd(d.disc_acc + t, (mine - kept) / tot);
+    } else {
+      if (kk == 0 && d.flags) d.flags[t] |= 1;
+      if (d.disc_acc && tot > 0.0) d.disc_acc[t] += (tot - kept) / tot;
+      if (d.rank_out) d.rank_out[t * d.rank_stride] = kk;
+      if (d.rank_max) d.rank_max[t * d.rank_stride] = max(d.rank_max[t * d.rank_stride], kk);
+    }
+    if (d.flops_acc) {
+      // algorithmic work: complex Cholesky r^2 (3n - 2r) / 3 + triangular
+      // inverse r^3 / 3 multiply-adds, 8 real flops each
+      const double f = 8.0 * ((double)r * r * (3.0 * n - 2.0 * r) / 3.0 + (double)r * r * r / 3.0);
+      if (d.blocks > 1) atomicAdd(d.flops_acc + t, f);
+      else d.flops_acc[t] += f;
+    }
+    if (d.nk_out) {
+      d.nk_out[t * 4 + 2 * pb.k] = r;
+      d.nk_out[t * 4 + 2 * pb.k + 1] = kk;
+      if (d.blocks <= 1) { d.nk_out[t * 4 + 2] = 0; d.nk_out[t * 4 + 3] = 0; }
+    }
+    if (d.sweeps_out) d.sweeps_out[t] = 0;
+  }
+  // factors: own block rows pad_off + a, columns off + i; zeros in the other
+  // block's columns
+  const long long base = t * (long long)d.new_pad * d.n;
+  const int nr = pb.n;
+  for (int idx = threadIdx.x; idx < pb.pad * nr; idx += blockDim.x) {
+    const int a = idx / nr, i = idx - (idx / nr) * nr;
+    double2 wi = make_double2(0.0, 0.0), wa = make_double2(0.0, 0.0);
+    const int c = inv[i];
+    if (a < kk && c >= 0) {
+      const int pc = pos[c];
+      const int ra = order[a];
+      // R[a][c]: row a of R holds the columns pivoted at step a or later
+      if (pc < 0 || pc >= a) wa = cscale(A[ra * LD + c], scale);
+      // (P R11^-1)[c][a] = X[pos c][a] for a kept pivot c (X upper triangular)
+      if (pc == a) wi = make_double2(1.0 / A[ra * LD + ra].x, 0.0);
+      else if (pc >= 0 && pc < a) wi = A[ra * LD + c];
+    }
+    const long long o = base + (long long)(pb.pad_off + a) * d.n + pb.off + i;
+    if (d.out_c128) { ((double2*)d.W_iso)[o] = wi; ((double2*)d.W_abs)[o] = wa; }
+    else { ((float2*)d.W_iso)[o] = from_d2<float2>(wi); ((float2*)d.W_abs)[o] = from_d2<float2>(wa); }
+    if (d.blocks > 1) {
+      const long long o2 = base + (long long)(pb.pad_off + a) * d.n + (1 - pb.k) * pb.n + i;
+      if (d.out_c128) { ((double2*)d.W_iso)[o2] = make_double2(0, 0); ((double2*)d.W_abs)[o2] = make_double2(0, 0); }
+      else { ((float2*)d.W_iso)[o2] = make_float2(0, 0); ((float2*)d.W_abs)[o2] = make_float2(0, 0); }
+    }
+  }
+}
+
+hipError_t launch_pchol(const EighDesc& d, int batch, hipStream_t st) {
+  if (batch <= 0) return hipSuccess;
+  const int nb = d.blocks > 1 ? 2 : 1;
+  if (d.n < 1 || d.new_pad < 1 || (nb == 2 && ((d.n & 1) || (d.new_pad & 1))) || d.n / nb > 64)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pchol<64>, dim3((unsigned)((long long)batch * nb)), dim3(256), 0, st, d);
+  return hipGetLastError();
 }
 
 static bool g_attr_done = false;

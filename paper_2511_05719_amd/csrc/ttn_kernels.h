@@ -94,6 +94,10 @@ struct EighDesc {
   double2* gpk;         // problems of size > 128: packed G in device memory, [batch][256 * 257 / 2]
 };
 hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st);
+// Exact (non-truncating) centre-move factors by pivoted Cholesky of G, same
+// outputs as launch_eigh (rank = pivots above cutoff x trace, at most cap);
+// problems of size <= 64 (per block)
+hipError_t launch_pchol(const EighDesc& d, int batch, hipStream_t st);
 int eigh_max_sweeps();
 
 // ----------------------------------------------------------- LEAF OPS ----

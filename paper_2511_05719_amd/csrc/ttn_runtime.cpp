@@ -41,7 +41,7 @@ using namespace ttn;
 enum {
   CLS_GEMM = TTN_CLASS_CONTRACT, CLS_GRAM = TTN_CLASS_GRAM, CLS_EIGH_SMALL = TTN_CLASS_EIGH_SMALL,
   CLS_EIGH_LARGE = TTN_CLASS_EIGH_LARGE, CLS_LEAF = TTN_CLASS_LEAF, CLS_EXTEND = TTN_CLASS_EXTEND,
-  CLS_OTHER = TTN_CLASS_OTHER
+  CLS_OTHER = TTN_CLASS_OTHER, CLS_MOVE = TTN_CLASS_MOVE
 };
 
 namespace {
@@ -117,7 +117,7 @@ struct ttn_ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[TTN_NCLASS];
   size_t prof_used[TTN_NCLASS] = {0};
   double* ledger[TTN_NCLASS] = {nullptr};   // device [B] algorithmic flops per class (or null)
-  double* ledger_mem = nullptr;             // [4][B]: eigh small, eigh large, Gram, contraction
+  double* ledger_mem = nullptr;             // [5][B]: eigh small, eigh large, Gram, contraction, move
   int* adim = nullptr;                      // [B][L][3] actual leg dimensions (profiling)
   int* nk = nullptr;                        // [B][4] eigensolver counts of the last move
   int* nk_max = nullptr;                    // [4] their maxima over rows (device)
@@ -555,9 +555,12 @@ static ttn_status read_kept(ttn_ctx* ctx, int kb[2]) {
   return TTN_OK;
 }
 
+// exact: the move keeps every value above the cutoff (the cap cannot bind);
+// complex64 contexts then factor by pivoted Cholesky (QR) instead of the
+// eigensolver when the problem fits it (n <= 64 per block).
 static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int new_pad, int blocks = 1,
                       int in_leg = -1, const int* kin = nullptr, const Partner* px = nullptr,
-                      const Partner* py = nullptr) {
+                      const Partner* py = nullptr, bool exact = false) {
   const int lx = leg_toward(x, y), ly = leg_toward(y, x);
   const int e = bond_node(x, y);
   std::array<int, 3> dx = ctx->dims[x], dy = ctx->dims[y];
@@ -577,7 +580,8 @@ static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int ne
   ed.rank_max = blocks > 1 ? nullptr : ctx->rank_max + e;
   ed.rank_stride = ctx->L;
   const bool large = (n / blocks + ((n / blocks) & 1)) > 64;
-  ed.flops_acc = ctx->ledger[large ? CLS_EIGH_LARGE : CLS_EIGH_SMALL];
+  const bool qr = exact && !ctx->c128 && !large && (blocks > 1 || n <= cap);
+  ed.flops_acc = ctx->ledger[qr ? CLS_MOVE : large ? CLS_EIGH_LARGE : CLS_EIGH_SMALL];
   ed.disc_acc = ctx->disc_acc; ed.flags = ctx->flags; ed.degen_acc = ctx->degen_acc;
   eigh_ws(ctx, ed);
   ed.nk_out = ctx->nk;
@@ -585,8 +589,12 @@ static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int ne
   // entries below 1e-12 of the diagonal change nothing they hold
   ed.tol = ctx->c128 ? 1e-15 : 1e-10;
   ed.early_stop = ctx->c128 ? 0 : 1;
-  ctx->launches += large ? 2 : 1;
-  {
+  if (qr) {
+    ++ctx->launches;
+    ProfScope ps(ctx, CLS_MOVE);
+    TTN_CHECK_HIP(launch_pchol(ed, ctx->B, ctx->st));
+  } else {
+    ctx->launches += large ? 2 : 1;
     ProfScope ps(ctx, large ? CLS_EIGH_LARGE : CLS_EIGH_SMALL);
     TTN_CHECK_HIP(launch_eigh(ed, ctx->B, ctx->st));
   }
@@ -634,11 +642,13 @@ static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int ne
   return TTN_OK;
 }
 
-static ttn_status hop_truncating(ttn_ctx* ctx, int x, int y) {
+// plain moves of the centre (exact: no gate has widened the bond) and the
+// truncating sweep after a controlled gate
+static ttn_status hop_truncating(ttn_ctx* ctx, int x, int y, bool exact = false) {
   const int e = bond_node(x, y);
   const int n = ctx->dims[x][leg_toward(x, y)];
   const int cap = bond_cap(ctx, e);
-  return hop(ctx, x, y, ctx->cutoff, cap, std::min(n, cap));
+  return hop(ctx, x, y, ctx->cutoff, cap, std::min(n, cap), 1, -1, nullptr, nullptr, nullptr, exact);
 }
 
 static ttn_status flush_leaf(ttn_ctx* ctx);
@@ -647,7 +657,7 @@ static ttn_status move_centre(ttn_ctx* ctx, int target) {
   if (ctx->centre == target) return TTN_OK;
   TTN_TRY(flush_leaf(ctx));
   std::vector<int> p = tree_path(ctx->centre, target);
-  for (size_t i = 0; i + 1 < p.size(); ++i) TTN_TRY(hop_truncating(ctx, p[i], p[i + 1]));
+  for (size_t i = 0; i + 1 < p.size(); ++i) TTN_TRY(hop_truncating(ctx, p[i], p[i + 1], true));
   return TTN_OK;
 }
 
@@ -797,13 +807,13 @@ static ttn_status controlled_gate(ttn_ctx* ctx, int qs, const double P[2][2][2][
         py.lo[0] = 0; py.hi[0] = half;
         py.lo[1] = half; py.hi[1] = 2 * half;
       }
-      TTN_TRY(hop(ctx, x, y, ctx->cutoff, n / 2, n, 2, in_leg, kin, &px, &py));
+      TTN_TRY(hop(ctx, x, y, ctx->cutoff, n / 2, n, 2, in_leg, kin, &px, &py, true));
       prev_block = true;
       kin[0] = ctx->last_kb[0];
       kin[1] = ctx->last_kb[1];
     } else {
       const int pad = (int)std::min<long long>(n, near_dim);
-      TTN_TRY(hop(ctx, x, y, ctx->cutoff, pad, pad));
+      TTN_TRY(hop(ctx, x, y, ctx->cutoff, pad, pad, 1, -1, nullptr, nullptr, nullptr, true));
       prev_block = false;
     }
   }
@@ -1112,7 +1122,7 @@ ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {
   ok &= hipMalloc((void**)&ctx->rank_table, Bz * L * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->ext, Bz * L * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->rank_max, Bz * L * sizeof(int)) == hipSuccess;
-  ok &= hipMalloc((void**)&ctx->ledger_mem, 4 * Bz * sizeof(double)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->ledger_mem, 5 * Bz * sizeof(double)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->adim, Bz * L * 3 * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->nk, Bz * 4 * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->nk_max, 4 * sizeof(int)) == hipSuccess;
@@ -1122,7 +1132,8 @@ ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {
     ctx->ledger[CLS_EIGH_LARGE] = ctx->ledger_mem + Bz;
     ctx->ledger[CLS_GRAM] = ctx->ledger_mem + 2 * Bz;
     ctx->ledger[CLS_GEMM] = ctx->ledger_mem + 3 * Bz;
-    ok &= launch_fill_f64(ctx->ledger_mem, 0.0, 4ll * ctx->B, ctx->st) == hipSuccess;
+    ctx->ledger[CLS_MOVE] = ctx->ledger_mem + 4 * Bz;
+    ok &= launch_fill_f64(ctx->ledger_mem, 0.0, 5ll * ctx->B, ctx->st) == hipSuccess;
   }
   ok &= hipMalloc((void**)&ctx->disc_acc, Bz * sizeof(double)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->flags, Bz * sizeof(int)) == hipSuccess;
@@ -1961,7 +1972,7 @@ ttn_status ttn_profile_enable(ttn_ctx* ctx, int32_t on) {
   TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
   ctx->prof = on != 0;
   for (int c = 0; c < TTN_NCLASS; ++c) ctx->prof_used[c] = 0;
-  TTN_CHECK_HIP(launch_fill_f64(ctx->ledger_mem, 0.0, 4ll * ctx->B, ctx->st));
+  TTN_CHECK_HIP(launch_fill_f64(ctx->ledger_mem, 0.0, 5ll * ctx->B, ctx->st));
   return TTN_OK;
 }
 
@@ -2007,6 +2018,26 @@ ttn_status ttn_test_leg_apply(ttn_ctx* ctx, int32_t rows, const int32_t* dims3, 
   if (!gemm_fits(g, rows, wA ? w_elems : t_elems, wA ? t_elems : w_elems, out_elems))
     return fail(ctx, TTN_EINVAL, "buffers too small for the contraction");
   TTN_CHECK_HIP(launch_zgemm(g, rows, ctx->c128 ? GEMM_C128 : GEMM_C64, ctx->st));
+  TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
+  return TTN_OK;
+}
+
+ttn_status ttn_test_move(ttn_ctx* ctx, int32_t rows, int32_t n, int32_t new_pad, int32_t cap, double cutoff,
+                         const double* G, int64_t g_elems, void* W_iso, void* W_abs, int64_t w_elems,
+                         int32_t* rank, int32_t blocks) {
+  if (!ctx) return TTN_EINVAL;
+  if (rows < 1 || rows > ctx->B || n < 1 || n / blocks > 64 || new_pad < 1 || new_pad > ctx->nmax || cap < 1 ||
+      !G || !W_iso || !W_abs || (blocks != 1 && blocks != 2) || (blocks == 1 && !rank) ||
+      (blocks == 2 && ((n & 1) || (new_pad & 1))))
+    return fail(ctx, TTN_EINVAL, "bad arguments (rows <= batch, n <= 64 per block, new_pad <= workspace)");
+  if (g_elems < (int64_t)rows * n * n || w_elems < (int64_t)rows * new_pad * n)
+    return fail(ctx, TTN_EINVAL, "buffers too small for the factorisation");
+  EighDesc ed{};
+  ed.G = (const double2*)G; ed.n = n; ed.new_pad = new_pad; ed.cap = cap; ed.cutoff = cutoff;
+  ed.W_iso = W_iso; ed.W_abs = W_abs; ed.out_c128 = ctx->c128;
+  ed.blocks = blocks;
+  ed.rank_out = blocks == 1 ? rank : nullptr; ed.rank_stride = 1;
+  TTN_CHECK_HIP(launch_pchol(ed, rows, ctx->st));
   TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
   return TTN_OK;
 }

@@ -227,6 +227,76 @@ def test_eigh_zero_rows_are_compacted(dtype, n, blocks):
     eng.close()
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,rank,blocks", [(1, 1, 1), (5, 3, 1), (16, 16, 1), (40, 17, 1), (64, 64, 1), (64, 30, 1),
+                                           (32, 9, 2), (128, 50, 2)])
+def test_exact_move_factors(dtype, n, rank, blocks):
+    # pivoted Cholesky centre move: x W_iso^T must be an isometry and, since
+    # nothing above the cutoff is dropped, (x W_iso^T) W_abs must rebuild the
+    # node (normalised by the kept weight, or by the whole trace for blocks);
+    # the rank is the numerical rank; dead rows (zero Gram diagonal)
+    # scattered in
+    from paper_2511_05719_amd._abi import lib, check
+    g = np.random.default_rng(n * 31 + rank + blocks)
+    rows, K = 4, 3 * n + 4
+    h = n // blocks
+    M = np.zeros((rows, K, n), complex)
+    for t in range(rows):
+        for b in range(blocks):
+            cols = np.arange(b * h, (b + 1) * h)
+            dead = g.random(h) < (0.25 if t % 2 else 0.0)
+            live = cols[~dead]
+            if len(live) == 0:
+                continue
+            r = min(rank // blocks if blocks > 1 else rank, len(live))
+            A = (g.normal(size=(K, r)) + 1j * g.normal(size=(K, r))) @ \
+                (g.normal(size=(r, len(live))) + 1j * g.normal(size=(r, len(live))))
+            A *= (10.0 ** (-np.arange(len(live)) / 32.0))[None, :]
+            M[t][:, live] = A
+        if np.linalg.norm(M[t]) > 0:
+            M[t] /= np.linalg.norm(M[t])
+    G = np.zeros((rows, n, n), complex)
+    for b in range(blocks):
+        sl = slice(b * h, (b + 1) * h)
+        G[:, sl, sl] = np.einsum("tki,tkj->tij", M[:, :, sl].conj(), M[:, :, sl])
+    eng = _engine(dtype, chi=64)
+    Gd = torch.view_as_real(torch.as_tensor(G)).contiguous().cuda()
+    wdt = torch.float64 if dtype == "c128" else torch.float32
+    Wi = torch.full((rows, n, n, 2), 7.0, dtype=wdt, device="cuda")
+    Wa = torch.full((rows, n, n, 2), 7.0, dtype=wdt, device="cuda")
+    rk = torch.full((rows,), -1, dtype=torch.int32, device="cuda")
+    cutoff = 1e-12
+    check(lib().ttn_test_move(eng._ctx, rows, n, n, h, cutoff, Gd.data_ptr(), rows * n * n, Wi.data_ptr(),
+                              Wa.data_ptr(), rows * n * n, rk.data_ptr() if blocks == 1 else None, blocks), eng._ctx)
+    Wi, Wa, rk = _host_complex(Wi), _host_complex(Wa), rk.cpu().numpy()
+    tol = 1e-9 if dtype == "c128" else 3e-5
+    for t in range(rows):
+        for b in range(blocks):
+            sl = slice(b * h, (b + 1) * h)
+            Mb = M[t][:, sl]
+            s = np.linalg.svd(Mb, compute_uv=False) if np.any(Mb) else np.zeros(1)
+            r_num = int((s ** 2 > 1e-9 * np.sum(s ** 2)).sum()) if np.any(s) else 0
+            wi, wa = Wi[t, sl, sl], Wa[t, sl, sl]
+            k = int(np.sum(np.linalg.norm(wa, axis=1) > 0))
+            assert k >= r_num and k <= min(h, Mb.shape[0])
+            if blocks == 1:
+                assert rk[t] == k
+            assert np.all(wi[k:] == 0) and np.all(wa[k:] == 0)
+            if blocks == 2:
+                other = slice((1 - b) * h, (2 - b) * h)
+                assert np.all(Wi[t, sl, other] == 0) and np.all(Wa[t, sl, other] == 0)
+            if k == 0:
+                continue
+            Q = Mb @ wi[:k].T
+            if blocks == 1:
+                target = Mb
+            else:
+                target = Mb / np.linalg.norm(M[t])
+            assert np.abs(Q.conj().T @ Q - np.eye(k)).max() < tol * 10
+            assert np.abs(Q @ wa[:k] - target).max() < tol
+    eng.close()
+
+
 def test_eigh_truncation_cap():
     from paper_2511_05719_amd._abi import lib, check
     g = np.random.default_rng(3)
