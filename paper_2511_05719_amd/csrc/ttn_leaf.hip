@@ -259,12 +259,12 @@ hipError_t launch_leaf_ops(const LeafBatch& b, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// One row per grid row (blockIdx.y, striding by gridDim.y); per-row element
-// indices fit 32 bits (a node holds at most 2^31 entries per row).
+// Each thread owns two consecutive entries of a row (their source offsets
+// are the same for every trajectory) and writes them for the rows
+// blockIdx.y, blockIdx.y + gridDim.y, ... as one 2-element store; per-row
+// element indices fit 32 bits (a node holds at most 2^31 entries per row).
 template <typename S>
-__global__ void __launch_bounds__(256) k_extend(ExtendDesc d, int batch, int per) {
-  const int rr = blockIdx.x * blockDim.x + threadIdx.x;
-  if (rr >= per) return;
+__device__ inline void extend_source(const ExtendDesc& d, int rr, int* src_off, int* src_off2, int* k, int* row) {
   int D[3] = {d.d0, d.d1, d.d2};
   int E[3] = {d.d0, d.d1, d.d2};
   E[d.leg_in] *= 2;
@@ -274,9 +274,7 @@ __global__ void __launch_bounds__(256) k_extend(ExtendDesc d, int batch, int per
   const int r1 = rr / E[2];
   idx[1] = r1 % E[1];
   idx[0] = r1 / E[1];
-  // the source entry (and, for mode 1, the block and physical row) is the
-  // same for every trajectory
-  int src_off = -1, src_off2 = -1, k = 0, row = 0;
+  *src_off = -1; *src_off2 = -1; *k = 0; *row = 0;
   if (d.mode == 0) {
     const int kin = idx[d.leg_in] / D[d.leg_in];
     const int kout = idx[d.leg_out] / D[d.leg_out];
@@ -284,32 +282,49 @@ __global__ void __launch_bounds__(256) k_extend(ExtendDesc d, int batch, int per
       int j[3] = {idx[0], idx[1], idx[2]};
       j[d.leg_in] -= kin * D[d.leg_in];
       j[d.leg_out] -= kout * D[d.leg_out];
-      src_off = (j[0] * D[1] + j[1]) * D[2] + j[2];
+      *src_off = (j[0] * D[1] + j[1]) * D[2] + j[2];
     }
   } else {
     // doubled leg_in = (k, u); block k = bmat[k] applied on physical leg ctrl_leg
     // (the projector at the start of a controlled gate, or B_k at its end)
-    k = idx[d.leg_in] / D[d.leg_in];
+    *k = idx[d.leg_in] / D[d.leg_in];
     int j[3] = {idx[0], idx[1], idx[2]};
-    j[d.leg_in] -= k * D[d.leg_in];
-    row = j[d.ctrl_leg];
+    j[d.leg_in] -= *k * D[d.leg_in];
+    *row = j[d.ctrl_leg];
     j[d.ctrl_leg] = 0;
-    src_off = (j[0] * D[1] + j[1]) * D[2] + j[2];
+    *src_off = (j[0] * D[1] + j[1]) * D[2] + j[2];
     j[d.ctrl_leg] = 1;
-    src_off2 = (j[0] * D[1] + j[1]) * D[2] + j[2];
+    *src_off2 = (j[0] * D[1] + j[1]) * D[2] + j[2];
   }
+}
+
+template <typename S>
+__device__ inline double2 extend_value(const ExtendDesc& d, const S* src, int so, int so2, int k, int row) {
+  if (d.mode == 0) return so >= 0 ? to_d2(src[so]) : make_double2(0.0, 0.0);
+  const double2 b0 = make_double2(d.bmat[k][row][0][0], d.bmat[k][row][0][1]);
+  const double2 b1 = make_double2(d.bmat[k][row][1][0], d.bmat[k][row][1][1]);
+  return cadd(cmul(b0, to_d2(src[so])), cmul(b1, to_d2(src[so2])));
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_extend(ExtendDesc d, int batch, int per) {
+  const int r0 = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
+  if (r0 >= per) return;
+  const bool two = r0 + 1 < per;
+  int a0, a1, ka, rowa, b0, b1, kb, rowb;
+  extend_source<S>(d, r0, &a0, &a1, &ka, &rowa);
+  if (two) extend_source<S>(d, r0 + 1, &b0, &b1, &kb, &rowb);
   for (long long t = blockIdx.y; t < batch; t += gridDim.y) {
     const S* src = (const S*)d.src + t * d.src_stride;
     S* dst = (S*)d.dst + t * d.dst_stride;
-    double2 v = make_double2(0.0, 0.0);
-    if (d.mode == 0) {
-      if (src_off >= 0) v = to_d2(src[src_off]);
+    const S va = from_d2<S>(extend_value<S>(d, src, a0, a1, ka, rowa));
+    if (two) {
+      const S vb = from_d2<S>(extend_value<S>(d, src, b0, b1, kb, rowb));
+      dst[r0] = va;
+      dst[r0 + 1] = vb;
     } else {
-      const double2 b0 = make_double2(d.bmat[k][row][0][0], d.bmat[k][row][0][1]);
-      const double2 b1 = make_double2(d.bmat[k][row][1][0], d.bmat[k][row][1][1]);
-      v = cadd(cmul(b0, to_d2(src[src_off])), cmul(b1, to_d2(src[src_off2])));
+      dst[r0] = va;
     }
-    dst[rr] = from_d2<S>(v);
   }
 }
 
@@ -320,7 +335,11 @@ hipError_t launch_extend(const ExtendDesc& d, int batch, hipStream_t st) {
   const long long per = (long long)E[0] * E[1] * E[2];
   if (per <= 0 || batch <= 0) return hipSuccess;
   if (per >= (1ll << 31)) return hipErrorInvalidValue;
-  dim3 grid((unsigned)((per + 255) / 256), (unsigned)std::min(batch, 65535));
+  // rows per workgroup: enough workgroups to fill the chip several times
+  const long long pairs = (per + 1) / 2;
+  const long long xblocks = (pairs + 255) / 256;
+  const int ry = (int)std::max<long long>(1, std::min<long long>(batch, std::max<long long>(1, 65536 / xblocks)));
+  dim3 grid((unsigned)xblocks, (unsigned)std::min(ry, 65535));
   if (d.c128) hipLaunchKernelGGL(k_extend<double2>, grid, dim3(256), 0, st, d, batch, (int)per);
   else hipLaunchKernelGGL(k_extend<float2>, grid, dim3(256), 0, st, d, batch, (int)per);
   return hipGetLastError();
