@@ -128,55 +128,79 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
     }
   const int li = lane & 15, lk = lane >> 4;
 
+  // Per-thread staging coordinates, fixed over the K loop: the in-row offset
+  // of each staged element's row (column) of A (B), -1 beyond the row's
+  // extent, its k within the chunk and its LDS slot.  In-row offsets and
+  // strides fit 24 bits x 24 bits products below 2^31 (checked by the
+  // launcher), so the K loop runs on 32-bit full-rate integer arithmetic.
+  int a_ro[AE], a_kk[AE], a_ls[AE], b_co[BE], b_kk[BE], b_ls[BE];
+#pragma unroll
+  for (int r = 0; r < AE; ++r) {
+    const int e = tid + 256 * r;
+    const int mm = d.a_m_fast ? e % TM : e / TK;
+    const int kk = d.a_m_fast ? e / TM : e % TK;
+    const int gm = m0 + mm;
+    a_ro[r] = gm < Mt ? __umul24((unsigned)gm, (unsigned)d.sAi) : -1;
+    a_kk[r] = kk;
+    a_ls[r] = kk * (TM + PADL) + mm;
+  }
+#pragma unroll
+  for (int r = 0; r < BE; ++r) {
+    const int e = tid + 256 * r;
+    const int nn = d.b_n_fast ? e % TN : e / TK;
+    const int kk = d.b_n_fast ? e / TN : e % TK;
+    const int gn = n0 + nn;
+    b_co[r] = gn < Nt ? __umul24((unsigned)gn, (unsigned)d.sBj) : -1;
+    b_kk[r] = kk;
+    b_ls[r] = kk * (TN + PADL) + nn;
+  }
+  // the K index l splits into (l / Kin, l % Kin); within one leg (Kin >= K
+  // range) the quotient is 0; otherwise a float reciprocal and one
+  // correction step give the exact quotient (l < 2^22)
+  const bool kflat = Kin >= kend;
+  const float kinv = 1.0f / (float)Kin;
+  const unsigned sA1 = (unsigned)d.sAl1, sA2 = (unsigned)d.sAl2, sB1 = (unsigned)d.sBl1, sB2 = (unsigned)d.sBl2;
+  auto kpart = [&](int gk, unsigned s1, unsigned s2) -> int {
+    if (kflat) return __umul24((unsigned)gk, s2);
+    int q = (int)((float)gk * kinv);
+    if (q * Kin > gk) --q;
+    else if ((q + 1) * Kin <= gk) ++q;
+    return __umul24((unsigned)q, s1) + __umul24((unsigned)(gk - q * Kin), s2);
+  };
+
   R ra_re[AE], ra_im[AE], rb_re[BE], rb_im[BE];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < AE; ++r) {
-      const int e = tid + 256 * r;
-      const int mm = d.a_m_fast ? e % TM : e / TK;
-      const int kk = d.a_m_fast ? e / TM : e % TK;
-      const int gm = m0 + mm, gk = k0 + kk;
+      const int gk = k0 + a_kk[r];
       double re = 0.0, im = 0.0;
-      if (gm < Mt && gk < kend) {
-        const long long off = (long long)gm * d.sAi + (long long)(gk / Kin) * d.sAl1 +
-                              (long long)(gk % Kin) * d.sAl2;
-        load_c(A, off, re, im);
-      }
+      if (a_ro[r] >= 0 && gk < kend) load_c(A, (long long)(a_ro[r] + kpart(gk, sA1, sA2)), re, im);
       ra_re[r] = (R)re;
       ra_im[r] = (R)im * sgnA;
     }
 #pragma unroll
     for (int r = 0; r < BE; ++r) {
-      const int e = tid + 256 * r;
-      const int nn = d.b_n_fast ? e % TN : e / TK;
-      const int kk = d.b_n_fast ? e / TN : e % TK;
-      const int gn = n0 + nn, gk = k0 + kk;
+      const int gk = k0 + b_kk[r];
       double re = 0.0, im = 0.0;
-      if (gn < Nt && gk < kend) {
-        const long long off = (long long)(gk / Kin) * d.sBl1 + (long long)(gk % Kin) * d.sBl2 +
-                              (long long)gn * d.sBj;
-        load_c(B, off, re, im);
-      }
+      if (b_co[r] >= 0 && gk < kend) load_c(B, (long long)(b_co[r] + kpart(gk, sB1, sB2)), re, im);
       rb_re[r] = (R)re;
       rb_im[r] = (R)im * sgnB;
     }
   };
+  R* As0 = &As[0][0][0];
+  R* As1 = &As[1][0][0];
+  R* Bs0 = &Bs[0][0][0];
+  R* Bs1 = &Bs[1][0][0];
   auto stage = [&]() {
 #pragma unroll
     for (int r = 0; r < AE; ++r) {
-      const int e = tid + 256 * r;
-      const int mm = d.a_m_fast ? e % TM : e / TK;
-      const int kk = d.a_m_fast ? e / TM : e % TK;
-      As[0][kk][mm] = ra_re[r];
-      As[1][kk][mm] = ra_im[r];
+      As0[a_ls[r]] = ra_re[r];
+      As1[a_ls[r]] = ra_im[r];
     }
 #pragma unroll
     for (int r = 0; r < BE; ++r) {
-      const int e = tid + 256 * r;
-      const int nn = d.b_n_fast ? e % TN : e / TK;
-      const int kk = d.b_n_fast ? e / TN : e % TK;
-      Bs[0][kk][nn] = rb_re[r];
-      Bs[1][kk][nn] = rb_im[r];
+      Bs0[b_ls[r]] = rb_re[r];
+      Bs1[b_ls[r]] = rb_im[r];
     }
   };
 
@@ -316,6 +340,18 @@ hipError_t launch_zgemm_t(GemmDesc d, int batch, hipStream_t st, int cfg) {
   if (d.ksplit < 1) d.ksplit = 1;
   if (d.H < 1 || d.ksplit > 64) return hipErrorInvalidValue;
   if (d.ext && (d.K % d.Kin != 0 || d.ext_stride < 1)) return hipErrorInvalidValue;
+  {
+    // the kernel's in-row offsets: 24-bit factors, sums below 2^31
+    const long long lim24 = 1ll << 24;
+    const long long kq = (d.K - 1) / d.Kin, kr = (d.K >= d.Kin) ? d.Kin - 1 : d.K - 1;
+    const long long sA[4] = {d.sAi, d.sAl1, d.sAl2, 0}, sB[4] = {d.sBj, d.sBl1, d.sBl2, 0};
+    for (int i = 0; i < 3; ++i)
+      if (sA[i] < 0 || sA[i] >= lim24 || sB[i] < 0 || sB[i] >= lim24) return hipErrorInvalidValue;
+    if (d.M >= lim24 || d.N >= lim24 || d.K >= (1 << 22)) return hipErrorInvalidValue;
+    const long long ea = (long long)(d.M - 1) * d.sAi + kq * d.sAl1 + kr * d.sAl2;
+    const long long eb = (long long)(d.N - 1) * d.sBj + kq * d.sBl1 + kr * d.sBl2;
+    if (ea >= (1ll << 31) || eb >= (1ll << 31)) return hipErrorInvalidValue;
+  }
   if (d.ext && (d.eM < 0 || d.eN < 0 || d.eH < 0 || d.eKo < 0 || d.eKi < 0) && !d.knew) return hipErrorInvalidValue;
   if (cfg < 0 || cfg >= kZgemmCfgs) cfg = tile_cfg(d.M, d.N);
   switch (cfg) {
