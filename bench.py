@@ -183,25 +183,52 @@ def cpu_oracle(circ, seed):
     return rate, (t2 - t0)
 
 
-# HBM traffic of one contraction launch at this workload and B=2048 (rocprofv3
-# FETCH_SIZE / WRITE_SIZE passes scaled by a 256 MiB copy, see
-# profiles/ttn_contract_d5_chi64_b2048_hbm_traffic.txt), valid for the GEMM
-# source it was measured on: reported only while that source is unchanged
-CONTRACT_TRAFFIC = {"batch": 2048, "bytes_per_launch": 1.2969e9,
-                    "gemm_sha256": "d03e3db73b3bb3a63e7dd63edc5b0f87fff7c9ac9fac1f27bf4e77e4c88f46de",
-                    "profile": "profiles/ttn_contract_d5_chi64_b2048_hbm_traffic.txt"}
+# HBM traffic of one launch of a kernel class at this workload and B=2048
+# (rocprofv3 FETCH_SIZE / WRITE_SIZE passes, each scaled by what the counter
+# reads for a 256 MiB device copy, see the profile named), valid for the
+# source file it was measured on: reported only while that file is unchanged
+TRAFFIC = {
+    "profile": "profiles/ttn_d5_chi64_b2048_hbm_traffic.txt",
+    "batch": 2048,
+    "classes": {
+        # k_zgemm<float2, float2, float2, ...>, all tile shapes
+        "contract": {"bytes_per_launch": 1.1782e9, "source": "ttn_gemm.hip",
+                     "sha256": "df0e24b983f08d00be0362e823a71c7ab335629e54e886fbf60a46ef502d37b8"},
+        # k_zgemm<float2, float2, double2, ...>, all tile shapes
+        "gram": {"bytes_per_launch": 0.5132e9, "source": "ttn_gemm.hip",
+                 "sha256": "df0e24b983f08d00be0362e823a71c7ab335629e54e886fbf60a46ef502d37b8"},
+        # k_jacobi<false, ...> + k_jacobi_vectors<128>, one pair per launch
+        "eigh_large": {"bytes_per_launch": 7.3133e9, "source": "ttn_eigh.hip",
+                       "sha256": "3592c1d94d3abfc6d580551cc612532540637a53777788857f7d96abdc55c9bf"},
+    },
+}
 
 
-def contract_traffic(batch):
+def class_traffic(cls, batch):
     import hashlib
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2511_05719_amd", "csrc", "ttn_gemm.hip")
+    ent = TRAFFIC["classes"].get(cls)
+    if ent is None or batch != TRAFFIC["batch"]:
+        return None
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2511_05719_amd", "csrc", ent["source"])
     try:
         h = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except OSError:
         return None
-    if h != CONTRACT_TRAFFIC["gemm_sha256"] or batch != CONTRACT_TRAFFIC["batch"]:
-        return None
-    return CONTRACT_TRAFFIC["bytes_per_launch"]
+    return ent["bytes_per_launch"] if h == ent["sha256"] else None
+
+
+def copy_calibration():
+    """Three device copies of 256 MiB: the reference dispatch that scales the
+    FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    n = 256 * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("copied 3 x 256 MiB", flush=True)
 
 
 def main():
@@ -219,7 +246,12 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="fixed-rule GEMM tile shapes (no measuring "
                     "in the warm-up)")
     ap.add_argument("--grad-records", type=int, default=64)
+    ap.add_argument("--copy-calibration", action="store_true", help="only run the 256 MiB copy that "
+                    "calibrates the HBM byte counters, then exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (trajectories shard "
               "across GPUs by id ranges, see DESIGN.md)", file=sys.stderr)
@@ -269,13 +301,13 @@ def main():
     d = prof[dom]
     bound, peak = bound_of[dom]
     achieved = d["alg_flops"] / max(d["ms"] / 1e3, 1e-12)
-    traffic = contract_traffic(args.batch) if dom == "contract" else None
+    traffic = class_traffic(dom, args.batch)
     roof = {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
             "frac": achieved / peak, "traffic": traffic, "kernel_class": dom, "launches": d["launches"],
             "avg_ms": d["ms"] / max(d["launches"], 1), "share_of_gpu_time": d["ms"] / total_ms,
             "per_unit": per_unit["eigh" if dom.startswith("eigh") else dom]}
     if traffic is not None:
-        roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 PMC, " + CONTRACT_TRAFFIC["profile"] + ")"
+        roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 PMC, " + TRAFFIC["profile"] + ")"
         roof["traffic_rate_tbs"] = traffic / (roof["avg_ms"] / 1e3) / 1e12
 
     plain = None

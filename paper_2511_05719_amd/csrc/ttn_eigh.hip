@@ -40,17 +40,6 @@ __device__ inline int pidx(int i, int j, int n) {   // packed upper triangle, i 
   // (both factors are below 2^24: the full-rate 24-bit multiply)
   return (int)((unsigned)__umul24((unsigned)i, (unsigned)(2 * n - i + 1)) >> 1) + (j - i);
 }
-// entry (i, j) of the Hermitian matrix from its packed upper triangle, and
-// its store; branch-free (lanes of one wave take both triangles at once)
-__device__ inline double2 gget(const double2* Gp, int i, int j, int n) {
-  double2 v = Gp[pidx(min(i, j), max(i, j), n)];
-  v.y = (i <= j) ? v.y : -v.y;
-  return v;
-}
-__device__ inline void gset(double2* Gp, int i, int j, int n, double2 v) {
-  v.y = (i <= j) ? v.y : -v.y;
-  Gp[pidx(min(i, j), max(i, j), n)] = v;
-}
 // circle-method pairing for step s of an even size n (no integer division)
 __device__ inline void pair_of(int n, int s, int j, int* p, int* q) {
   int a, b;
@@ -64,6 +53,28 @@ __device__ inline void pair_of(int n, int s, int j, int* p, int* q) {
 }
 
 struct Rot { double c; double2 s; double delta; };
+// a rotation in tangent form, J = c [[1, t], [-conj(t), 1]] (s = c t), so
+// that the two-sided block update needs two fused multiply-adds per real
+// component and one scaling by c_P c_Q at the end
+struct RotT { double2 t; double c; double delta; };
+
+__device__ inline double2 c_sub_mul_conj(double2 a, double2 b, double2 t) {   // a - b conj(t)
+  return make_double2(fma(-b.x, t.x, fma(-b.y, t.y, a.x)), fma(-b.y, t.x, fma(b.x, t.y, a.y)));
+}
+__device__ inline double2 c_add_mul(double2 a, double2 b, double2 t) {        // a + b t
+  return make_double2(fma(b.x, t.x, fma(-b.y, t.y, a.x)), fma(b.x, t.y, fma(b.y, t.x, a.y)));
+}
+__device__ inline double2 c_sub_mul(double2 a, double2 b, double2 t) {        // a - b t
+  return make_double2(fma(-b.x, t.x, fma(b.y, t.y, a.x)), fma(-b.x, t.y, fma(-b.y, t.x, a.y)));
+}
+__device__ inline double2 c_add_mul_conj(double2 a, double2 b, double2 t) {   // a + b conj(t)
+  return make_double2(fma(b.x, t.x, fma(b.y, t.y, a.x)), fma(b.y, t.x, fma(-b.x, t.y, a.y)));
+}
+// the imaginary part with its sign bit flipped by m (0 or the sign bit)
+__device__ inline double2 conj_if(double2 v, unsigned long long m) {
+  v.y = __longlong_as_double(__double_as_longlong(v.y) ^ (long long)m);
+  return v;
+}
 
 // entry o of one row's Gram matrix: the sum of its partial products when the
 // Gram launch split its K range
@@ -186,13 +197,16 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
   const int n2 = n + (n & 1);          // even size, a zero dummy index if odd
   const int h = n2 / 2;
   const int npk = n2 * (n2 + 1) / 2;
-  const int nblk = h * (h + 1) / 2;
+  const int nblk = h * (h - 1) / 2;
   constexpr bool kGlobalG = NMAX > 128;
   double2* Gp = kGlobalG ? d.gpk + pid * (long long)(NMAX * (NMAX + 1) / 2) : smem;   // packed G
   VT* V = reinterpret_cast<VT*>(smem + npk);           // [n2][n2] if kVinLds
-  __shared__ Rot rot[NMAX / 2];
+  __shared__ RotT rot[NMAX / 2];
   __shared__ int pq_s[NMAX / 2];                                    // this step's pairs, p | q << 16
-  __shared__ unsigned short blk[(NMAX / 2) * (NMAX / 2 + 1) / 2];   // (P, Q) of the upper 2x2 blocks
+  // this step's pairs in bytes: {16 p, 16 q, 16 rowbase(p), 16 rowbase(q)};
+  // entry (i, j), i <= j, of the packed triangle is element rowbase(i) + j
+  __shared__ int4 pinfo[NMAX / 2];
+  __shared__ unsigned short blk[(NMAX / 2) * (NMAX / 2 - 1) / 2];   // (P, Q), P < Q: off-diagonal 2x2 blocks
   __shared__ double lam[NMAX];
   __shared__ int order_s[NMAX];
   __shared__ double red[NT];
@@ -210,8 +224,8 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
   }
   for (int idx = threadIdx.x; idx < nblk; idx += blockDim.x) {
     int P = 0, rem = idx;
-    while (rem >= h - P) { rem -= h - P; ++P; }
-    blk[idx] = (unsigned short)(P | ((P + rem) << 8));
+    while (rem >= h - 1 - P) { rem -= h - 1 - P; ++P; }
+    blk[idx] = (unsigned short)(P | ((P + 1 + rem) << 8));
   }
   if (kVinLds)
     for (int idx = threadIdx.x; idx < n2 * n2; idx += blockDim.x)
@@ -242,7 +256,7 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
       if (threadIdx.x == 0) any_rot = 0;
       __syncthreads();
-      double my_ratio = 0.0;     // rotation threads: largest rotated squared ratio this sweep
+      double my_ratio = 0.0;     // rotation threads: 1 once they rotated a pair at or above the stop ratio
       for (int s = 0; s < n2 - 1; ++s) {
         // -- rotation parameters of the n2/2 pairs (the tests on squares,
         //    one reciprocal square root for |b| and one for c: the serial
@@ -251,80 +265,85 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
           int p, q;
           pair_of(n2, s, threadIdx.x, &p, &q);
           pq_s[threadIdx.x] = p | (q << 16);
-          const double a = Gp[pidx(p, p, n2)].x, dd = Gp[pidx(q, q, n2)].x;
-          const double2 b = Gp[pidx(p, q, n2)];
+          const int rbp = pidx(p, p, n2) - p, rbq = pidx(q, q, n2) - q;
+          pinfo[threadIdx.x] = make_int4(16 * p, 16 * q, 16 * rbp, 16 * rbq);
+          const double a = Gp[rbp + p].x, dd = Gp[rbq + q].x;
+          const double2 b = Gp[rbp + q];
           const double ab2 = cabs2(b);
           const double ad = fabs(a * dd);
-          Rot r;
-          r.c = 1.0; r.s = make_double2(0.0, 0.0); r.delta = 0.0;
+          RotT r;
+          r.c = 1.0; r.t = make_double2(0.0, 0.0); r.delta = 0.0;
           if (ab2 > tol * tol * ad && ab2 > floor2 && ab2 > 0.0) {
-            my_ratio = fmax(my_ratio, ad > 0.0 ? ab2 / ad : 1.0);
+            if (ab2 >= stop_ratio2 * ad) my_ratio = 1.0;
             const double inv_ab = rsqrt(ab2);
             const double th = 0.5 * (dd - a) * inv_ab;
             const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-            const double c = rsqrt(1.0 + tt * tt);
-            const double sn = tt * c * inv_ab;
-            r.c = c;
-            r.s = make_double2(sn * b.x, sn * b.y);
+            const double tn = tt * inv_ab;
+            r.c = rsqrt(1.0 + tt * tt);
+            r.t = make_double2(tn * b.x, tn * b.y);
             r.delta = tt * (ab2 * inv_ab);
             any_rot = 1;
+            // the pair's own 2x2 diagonal block (no other block of this
+            // step touches these three entries)
+            Gp[rbp + p] = make_double2(a - r.delta, 0.0);
+            Gp[rbq + q] = make_double2(dd + r.delta, 0.0);
+            Gp[rbp + q] = make_double2(0.0, 0.0);
           }
           rot[threadIdx.x] = r;
           if (!kVinLds && log) {
             double* e = log + ((long long)step_count * h + threadIdx.x) * 3;
-            e[0] = r.c; e[1] = r.s.x; e[2] = r.s.y;
+            e[0] = r.c; e[1] = r.c * r.t.x; e[2] = r.c * r.t.y;
           }
         }
         __syncthreads();
-        // -- G <- J^H G J, block by block --
+        // -- G <- J^H G J on the off-diagonal blocks --
+        const char* Gb = reinterpret_cast<const char*>(Gp);
         for (int idx = threadIdx.x; idx < nblk; idx += blockDim.x) {
           const unsigned short pq = blk[idx];
           const int P = pq & 0xff, Q = pq >> 8;
-          const Rot rP = rot[P];
-          const int eP = pq_s[P];
-          const int p = eP & 0xffff, q = eP >> 16;
-          if (P == Q) {
-            if (rP.delta != 0.0) {
-              double2 gpp = Gp[pidx(p, p, n2)], gqq = Gp[pidx(q, q, n2)];
-              gpp.x -= rP.delta; gpp.y = 0.0;
-              gqq.x += rP.delta; gqq.y = 0.0;
-              Gp[pidx(p, p, n2)] = gpp;
-              Gp[pidx(q, q, n2)] = gqq;
-              Gp[pidx(p, q, n2)] = make_double2(0.0, 0.0);
-            }
-            continue;
-          }
-          const Rot rQ = rot[Q];
+          const RotT rP = rot[P], rQ = rot[Q];
           if (rP.delta == 0.0 && rQ.delta == 0.0) continue;
-          const int eQ = pq_s[Q];
-          const int pp = eQ & 0xffff, qq = eQ >> 16;
-          const double2 g00 = gget(Gp, p, pp, n2), g01 = gget(Gp, p, qq, n2);
-          const double2 g10 = gget(Gp, q, pp, n2), g11 = gget(Gp, q, qq, n2);
-          // X = G_PQ J_Q,  J = [[c, s], [-conj(s), c]]
-          const double2 sQc = cconj(rQ.s);
-          const double2 x00 = csub(cscale(g00, rQ.c), cmul(g01, sQc));
-          const double2 x01 = cadd(cmul(g00, rQ.s), cscale(g01, rQ.c));
-          const double2 x10 = csub(cscale(g10, rQ.c), cmul(g11, sQc));
-          const double2 x11 = cadd(cmul(g10, rQ.s), cscale(g11, rQ.c));
-          // Y = J_P^H X,  J^H = [[c, -s], [conj(s), c]]
-          const double2 sPc = cconj(rP.s);
-          gset(Gp, p, pp, n2, csub(cscale(x00, rP.c), cmul(rP.s, x10)));
-          gset(Gp, p, qq, n2, csub(cscale(x01, rP.c), cmul(rP.s, x11)));
-          gset(Gp, q, pp, n2, cadd(cmul(sPc, x00), cscale(x10, rP.c)));
-          gset(Gp, q, qq, n2, cadd(cmul(sPc, x01), cscale(x11, rP.c)));
+          const int4 eP = pinfo[P], eQ = pinfo[Q];
+          // entry (i, j) of the block: byte offset of its upper-triangle
+          // slot, and the sign mask that conjugates a lower-triangle entry
+          const bool u00 = eP.x <= eQ.x, u01 = eP.x <= eQ.y, u10 = eP.y <= eQ.x, u11 = eP.y <= eQ.y;
+          const int o00 = u00 ? eP.z + eQ.x : eQ.z + eP.x;
+          const int o01 = u01 ? eP.z + eQ.y : eQ.w + eP.x;
+          const int o10 = u10 ? eP.w + eQ.x : eQ.z + eP.y;
+          const int o11 = u11 ? eP.w + eQ.y : eQ.w + eP.y;
+          constexpr unsigned long long kSign = 0x8000000000000000ull;
+          const unsigned long long m00 = u00 ? 0ull : kSign, m01 = u01 ? 0ull : kSign;
+          const unsigned long long m10 = u10 ? 0ull : kSign, m11 = u11 ? 0ull : kSign;
+          const double2 g00 = conj_if(*reinterpret_cast<const double2*>(Gb + o00), m00);
+          const double2 g01 = conj_if(*reinterpret_cast<const double2*>(Gb + o01), m01);
+          const double2 g10 = conj_if(*reinterpret_cast<const double2*>(Gb + o10), m10);
+          const double2 g11 = conj_if(*reinterpret_cast<const double2*>(Gb + o11), m11);
+          // X = G_PQ [[1, tQ], [-conj(tQ), 1]]
+          const double2 x00 = c_sub_mul_conj(g00, g01, rQ.t), x01 = c_add_mul(g01, g00, rQ.t);
+          const double2 x10 = c_sub_mul_conj(g10, g11, rQ.t), x11 = c_add_mul(g11, g10, rQ.t);
+          // Y = cP cQ [[1, -tP], [conj(tP), 1]] X
+          const double cc = rP.c * rQ.c;
+          const double2 y00 = cscale(c_sub_mul(x00, x10, rP.t), cc), y01 = cscale(c_sub_mul(x01, x11, rP.t), cc);
+          const double2 y10 = cscale(c_add_mul_conj(x10, x00, rP.t), cc);
+          const double2 y11 = cscale(c_add_mul_conj(x11, x01, rP.t), cc);
+          char* Gw = reinterpret_cast<char*>(Gp);
+          *reinterpret_cast<double2*>(Gw + o00) = conj_if(y00, m00);
+          *reinterpret_cast<double2*>(Gw + o01) = conj_if(y01, m01);
+          *reinterpret_cast<double2*>(Gw + o10) = conj_if(y10, m10);
+          *reinterpret_cast<double2*>(Gw + o11) = conj_if(y11, m11);
         }
         if (kVinLds) {
           // V <- V J (columns p, q of every row): thread owns pair vP on
           // the rows vr0, vr0 + vgroups, ...
           if (threadIdx.x < vgroups * h) {
-            const Rot rP = rot[vP];
+            const RotT rP = rot[vP];
             if (rP.delta != 0.0) {
               const int eP = pq_s[vP];
               const int p = eP & 0xffff, q = eP >> 16;
               for (int r = vr0; r < n2; r += vgroups) {
                 const double2 vp = to_d2(V[r * n2 + p]), vq = to_d2(V[r * n2 + q]);
-                V[r * n2 + p] = from_d2<VT>(csub(cscale(vp, rP.c), cmul(cconj(rP.s), vq)));
-                V[r * n2 + q] = from_d2<VT>(cadd(cmul(rP.s, vp), cscale(vq, rP.c)));
+                V[r * n2 + p] = from_d2<VT>(cscale(c_sub_mul_conj(vp, vq, rP.t), rP.c));
+                V[r * n2 + q] = from_d2<VT>(cscale(c_add_mul(vq, vp, rP.t), rP.c));
               }
             }
           }
@@ -346,7 +365,7 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
         sweep_ratio = m;
       }
       __syncthreads();
-      if (any_rot == 0 || sweep_ratio < stop_ratio2) break;
+      if (any_rot == 0 || sweep_ratio == 0.0) break;
       __syncthreads();
     }
   }
