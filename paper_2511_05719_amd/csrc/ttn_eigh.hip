@@ -25,6 +25,8 @@
 // own workgroup; cutoff and normalisation refer to the trace of the whole
 // matrix, and each workgroup writes its own diagonal block of the factors
 // (and zeros in its rows of the other block).
+#include <vector>
+
 #include "ttn_device.h"
 #include "ttn_kernels.h"
 
@@ -40,6 +42,20 @@ __device__ inline int pidx(int i, int j, int n) {   // packed upper triangle, i 
   // (both factors are below 2^24: the full-rate 24-bit multiply)
   return (int)((unsigned)__umul24((unsigned)i, (unsigned)(2 * n - i + 1)) >> 1) + (j - i);
 }
+// Problems above 64 whose compacted even size n2 is at least 7/8 of the next
+// power of two are solved by coset-grouped sweeps on the padded matrix; the
+// others by circle-ordered sweeps on n2 (padding would cost more than the
+// grouping saves).
+__device__ inline int padded_pow2(int n) {
+  int N = 4;
+  while (N < n) N <<= 1;
+  return N;
+}
+__device__ inline bool coset_order(int n) {
+  const int n2 = n + (n & 1);
+  return n2 > 64 && 8 * n2 >= 7 * padded_pow2(n2);
+}
+
 // circle-method pairing for step s of an even size n (no integer division)
 __device__ inline void pair_of(int n, int s, int j, int* p, int* q) {
   int a, b;
@@ -194,6 +210,7 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
   __shared__ int inv[NMAX];
   __shared__ int wcount[NT / 64];
   const int n = compact_rows<NT / 64>(d, G, pb, cidx, inv, wcount);   // compacted size
+  if (!kVinLds && coset_order(n)) return;        // solved by k_jacobi_coset
   const int n2 = n + (n & 1);          // even size, a zero dummy index if odd
   const int h = n2 / 2;
   const int npk = n2 * (n2 + 1) / 2;
@@ -460,13 +477,458 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
   }
 }
 
-// Kept eigenvectors of a problem of size > 64 from the rotation log.
-// V = J_1 J_2 ... J_S, so column c of V is J_1 (J_2 (... (J_S e_c))): the log
-// is replayed in reverse on the unit vectors of the kept columns only.
-// Columns are independent, so each wavefront owns a few of them in LDS and
-// runs through the log with no workgroup barrier; lane j applies the
-// rotations of pairs j and j + 64 of every step (disjoint index pairs).
-// One workgroup per problem (a row, or one diagonal block of a row).
+// ---------------------------------------------------------------------------
+// Problems above 64: coset-grouped sweeps.
+//
+// The compacted matrix is padded with zero rows to N = 2^k (zero rows never
+// rotate).  A sweep is the N - 1 matchings M_d = {(i, i ^ d) : i < i ^ d},
+// d = 1 .. N - 1, which together visit every pair once, taken in groups of
+// up to three from one subgroup H = {0, a, b, a ^ b} of (Z_2)^k: {a, b,
+// a ^ b}, {a, b} or {a}.  Every matching of a group maps each coset {r, r ^ a,
+// r ^ b, r ^ a ^ b} of H onto itself, so the group's rotations act inside
+// 4 x 4 blocks: one thread per coset computes them on its diagonal block in
+// registers (one rotation after another, as cyclic Jacobi does), and then
+// every off-diagonal block (Q, R) gets U_Q^H G_QR U_R with one read and one
+// write of G per group instead of one per matching.
+// ---------------------------------------------------------------------------
+constexpr int kPlanMaxK = 8;                  // N <= 256
+struct SweepPlan {
+  int ngroups[kPlanMaxK + 1];
+  unsigned grp[kPlanMaxK + 1][256];           // a | b << 8 | m << 16 (m matchings: a, b, a ^ b)
+  unsigned char dseq[kPlanMaxK + 1][256];     // the matchings of one sweep in order
+};
+__constant__ SweepPlan c_plan;
+
+__device__ inline int hibit(int x) { return 31 - __clz(x); }
+// x with a zero bit inserted at position b
+__device__ inline int insert_zero(int x, int b) { return ((x >> b) << (b + 1)) | (x & ((1 << b) - 1)); }
+// pair index of (i, i ^ d), i < i ^ d, within matching d: i without bit hibit(d)
+__device__ inline int pair_index(int i, int hb) { return ((i >> (hb + 1)) << hb) | (i & ((1 << hb) - 1)); }
+
+// rotation of the pair (p, q), p < q, with g_pp = a, g_qq = dd, g_pq = b
+// (the tests of the circle-ordered solver).  With w = dd - a and
+// D = |w| + sqrt(w^2 + 4 |b|^2): t = 2 sign(w) b / D (the smaller-angle
+// root), delta = 2 sign(w) |b|^2 / D, and c = (1 + |t|^2)^-1/2;
+// one square root, one reciprocal (refined twice by Newton's iteration, D
+// >= |w| > 0) and one reciprocal square root.  ic = 1 / c.
+__device__ __forceinline__ RotT jacobi_rot(double a, double dd, double2 b, double tol, double floor2,
+                                  double stop_ratio2, bool* rotated, bool* big, double* ic) {
+  RotT r;
+  r.c = 1.0; r.t = make_double2(0.0, 0.0); r.delta = 0.0;
+  *ic = 1.0;
+  const double ab2 = cabs2(b);
+  const double ad = fabs(a * dd);
+  *rotated = false; *big = false;
+  if (ab2 > tol * tol * ad && ab2 > floor2 && ab2 > 0.0) {
+    *big = ab2 >= stop_ratio2 * ad;
+    const double w = dd - a;
+    const double D = fabs(w) + sqrt(fma(w, w, 4.0 * ab2));
+    double y = __builtin_amdgcn_rcp(D);
+    y = fma(y, fma(-D, y, 1.0), y);
+    y = fma(y, fma(-D, y, 1.0), y);
+    const double g = (w >= 0.0 ? 2.0 : -2.0) * y;
+    r.t = make_double2(g * b.x, g * b.y);
+    r.delta = g * ab2;
+    const double x = fma(4.0 * ab2, y * y, 1.0);     // 1 + |t|^2
+    r.c = rsqrt(x);
+    *ic = x * r.c;
+    *rotated = true;
+  }
+  return r;
+}
+
+// slots of the two pairs of matching J of a coset (r, r ^ a, r ^ b, r ^ a ^ b):
+// a: (0, 1), (2, 3); b: (0, 2), (1, 3); a ^ b: (0, 3), (1, 2)
+template <int J> struct CosetPairs {
+  static constexpr int s00 = 0, s01 = J == 0 ? 1 : (J == 1 ? 2 : 3);
+  static constexpr int s10 = J == 0 ? 2 : 1, s11 = J == 2 ? 2 : 3;
+};
+template <int S> __device__ inline int comp(const int4& v) {
+  return S == 0 ? v.x : (S == 1 ? v.y : (S == 2 ? v.z : v.w));
+}
+
+struct RotCtl { double tol, floor2, stop_ratio2; };
+
+// The rotation of one pair of a coset's diagonal block (entries a = B_00,
+// dd = B_11, b = B_01 in slot order, slot indices i0, i1), computed in slot
+// order: the same rotation as in index order, relabelled (t -> -conj(t),
+// delta -> -delta when the first slot holds the larger index).  Its log entry
+// is written in index order.
+__device__ __forceinline__ RotT coset_rot(double a, double dd, double2 b, int i0, int i1, int hb,
+                                          const RotCtl& rc, double* e, bool* rotated, bool* big, double* ic) {
+  bool bg;
+  const RotT r = jacobi_rot(a, dd, b, rc.tol, rc.floor2, rc.stop_ratio2, rotated, &bg, ic);
+  *big |= bg;
+  e += (long long)pair_index(min(i0, i1), hb) * 3;
+  const double tx = i0 < i1 ? r.t.x : -r.t.x;
+  e[0] = r.c; e[1] = r.c * tx; e[2] = r.c * r.t.y;
+  return r;
+}
+
+// Coefficients of one rotation for the off-diagonal blocks.  Rows (and
+// columns) of a coset carry pending scales sigma (products of the c's of the
+// group's earlier rotations), so a rotation of slots (S0, S1) becomes
+// X0 <- X0 - alpha X1, X1 <- X1 + beta X0 with alpha = t sigma1 / sigma0,
+// beta = conj(t) sigma0 / sigma1 (and the conjugate coefficients on the
+// column side), and the scales multiply by c; every entry is scaled once,
+// after the group.
+struct RotAB { double2 alpha, beta; };
+
+// Matching J of a group on a coset's diagonal block B (members v), worked by
+// two lanes that both hold B: lane ln computes the rotation of pair ln (its
+// log entry and off-diagonal coefficients), the lanes swap them, and both
+// rotate the cross block between the pairs from both sides, set each pair's
+// own 2 x 2 block to its exact diagonal form and advance the pending scales
+// sig (and their inverses isig).  Returns whether a pair rotated.
+template <int J>
+__device__ __forceinline__ bool coset_matching(double2 (&B)[4][4], double (&sig)[4], double (&isig)[4],
+                                               const int4& v, int dm, int ln, const RotCtl& rc, double* log_step,
+                                               RotAB (&rec)[2], bool* big) {
+  using S = CosetPairs<J>;
+  constexpr int a0 = S::s00, a1 = S::s01, b0 = S::s10, b1 = S::s11;
+  const bool hi = ln != 0;
+  bool rot;
+  double ic;
+  const RotT r = coset_rot(hi ? B[b0][b0].x : B[a0][a0].x, hi ? B[b1][b1].x : B[a1][a1].x,
+                           hi ? B[b0][b1] : B[a0][a1], hi ? comp<b0>(v) : comp<a0>(v),
+                           hi ? comp<b1>(v) : comp<a1>(v), hibit(dm), rc, log_step, &rot, big, &ic);
+  {
+    const double s0 = hi ? sig[b0] : sig[a0], s1 = hi ? sig[b1] : sig[a1];
+    const double is0 = hi ? isig[b0] : isig[a0], is1 = hi ? isig[b1] : isig[a1];
+    RotAB ab;
+    ab.alpha = cscale(r.t, s1 * is0);
+    ab.beta = cscale(cconj(r.t), s0 * is1);
+    rec[ln] = ab;
+  }
+  RotT ro;
+  ro.t = make_double2(__shfl_xor(r.t.x, 1), __shfl_xor(r.t.y, 1));
+  ro.c = __shfl_xor(r.c, 1);
+  ro.delta = __shfl_xor(r.delta, 1);
+  const double ico = __shfl_xor(ic, 1);
+  const bool roto = __shfl_xor((int)rot, 1) != 0;
+  const RotT r0 = hi ? ro : r, r1 = hi ? r : ro;
+  const bool rot0 = hi ? roto : rot, rot1 = hi ? rot : roto;
+  const double ic0 = hi ? ico : ic, ic1 = hi ? ic : ico;
+  sig[a0] *= r0.c; sig[a1] *= r0.c; sig[b0] *= r1.c; sig[b1] *= r1.c;
+  isig[a0] *= ic0; isig[a1] *= ic0; isig[b0] *= ic1; isig[b1] *= ic1;
+  if (!rot0 && !rot1) return false;
+  // cross block C = B[{a0, a1}][{b0, b1}] <- J0^H C J1
+  double2 c00 = B[a0][b0], c01 = B[a0][b1], c10 = B[a1][b0], c11 = B[a1][b1];
+  {
+    const double2 x00 = c_sub_mul(c00, c10, r0.t), x10 = c_add_mul_conj(c10, c00, r0.t);
+    const double2 x01 = c_sub_mul(c01, c11, r0.t), x11 = c_add_mul_conj(c11, c01, r0.t);
+    const double cc = r0.c * r1.c;
+    c00 = cscale(c_sub_mul_conj(x00, x01, r1.t), cc);
+    c01 = cscale(c_add_mul(x01, x00, r1.t), cc);
+    c10 = cscale(c_sub_mul_conj(x10, x11, r1.t), cc);
+    c11 = cscale(c_add_mul(x11, x10, r1.t), cc);
+  }
+  B[a0][b0] = c00; B[a0][b1] = c01; B[a1][b0] = c10; B[a1][b1] = c11;
+  B[b0][a0] = cconj(c00); B[b1][a0] = cconj(c01); B[b0][a1] = cconj(c10); B[b1][a1] = cconj(c11);
+  if (rot0) {
+    B[a0][a0].x -= r0.delta; B[a1][a1].x += r0.delta;
+    B[a0][a1] = make_double2(0.0, 0.0); B[a1][a0] = make_double2(0.0, 0.0);
+  }
+  if (rot1) {
+    B[b0][b0].x -= r1.delta; B[b1][b1].x += r1.delta;
+    B[b0][b1] = make_double2(0.0, 0.0); B[b1][b0] = make_double2(0.0, 0.0);
+  }
+  return true;
+}
+
+// matching J on an off-diagonal block: rows by coset Q's coefficients (from
+// the left), columns by coset R's (from the right, conjugated)
+template <int S0, int S1>
+__device__ __forceinline__ void ab_rows(double2 (&X)[4][4], const RotAB& r) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const double2 x0 = X[S0][u], x1 = X[S1][u];
+    X[S0][u] = c_sub_mul(x0, x1, r.alpha);
+    X[S1][u] = c_add_mul(x1, x0, r.beta);
+  }
+}
+template <int S0, int S1>
+__device__ __forceinline__ void ab_cols(double2 (&X)[4][4], const RotAB& r) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const double2 x0 = X[s][S0], x1 = X[s][S1];
+    X[s][S0] = c_sub_mul_conj(x0, x1, r.alpha);
+    X[s][S1] = c_add_mul_conj(x1, x0, r.beta);
+  }
+}
+template <int J>
+__device__ __forceinline__ void coset_block(double2 (&X)[4][4], const RotAB (&a)[2], const RotAB (&b)[2]) {
+  using S = CosetPairs<J>;
+  ab_rows<S::s00, S::s01>(X, a[0]);
+  ab_rows<S::s10, S::s11>(X, a[1]);
+  ab_cols<S::s00, S::s01>(X, b[0]);
+  ab_cols<S::s10, S::s11>(X, b[1]);
+}
+
+// byte offset of entry (i, j) (byte indices 16 i, 16 j; packed row bases
+// rbi, rbj in bytes) and the mask that conjugates a lower-triangle entry
+__device__ inline int coset_off(int i16, int rbi, int j16, int rbj) { return i16 < j16 ? rbi + j16 : rbj + i16; }
+__device__ inline unsigned long long coset_msk(int i16, int j16) {
+  return i16 < j16 ? 0ull : 0x8000000000000000ull;
+}
+
+constexpr int kThreadsCoset = 512;
+template <int NMAX>
+__global__ void __launch_bounds__(kThreadsCoset) k_jacobi_coset(EighDesc d) {
+  constexpr int NT = kThreadsCoset;
+  constexpr int NQ = NMAX / 4;
+  extern __shared__ double2 smem[];
+  const long long pid = blockIdx.x;
+  const Problem pb = problem_of(d, pid);
+  const long long t = pb.t;
+  const double2* G = d.G + t * (long long)d.n * d.n;
+  __shared__ int cidx[NMAX];
+  __shared__ int inv[NMAX];
+  __shared__ int wcount[NT / 64];
+  const int n = compact_rows<NT / 64>(d, G, pb, cidx, inv, wcount);
+  if (!coset_order(n)) return;              // solved by the circle-ordered k_jacobi
+  int kk = 2;
+  while ((1 << kk) < n) ++kk;
+  const int N = 1 << kk;
+  const int npk = N * (N + 1) / 2;
+  const int nq = N / 4;
+  const int nblk = nq * (nq - 1) / 2;
+  constexpr bool kGlobalG = NMAX > 128;
+  double2* Gp = kGlobalG ? d.gpk + pid * (long long)(NMAX * (NMAX + 1) / 2) : smem;
+  __shared__ RotAB rq[NQ][3][2];            // this group's off-diagonal coefficients: coset, matching, pair
+  __shared__ double4 qsig[NQ];              // the cosets' scales after the group
+  __shared__ int4 qm[NQ];                   // coset members r, r ^ a, r ^ b, r ^ a ^ b, in bytes (16 i)
+  __shared__ int4 qrb[NQ];                  // their packed row bases, in bytes
+  __shared__ int qact[NQ];                  // the coset rotated in this group
+  __shared__ unsigned short blk[NQ * (NQ - 1) / 2];
+  __shared__ double lam[NMAX];
+  __shared__ int order_s[NMAX];
+  __shared__ double wsum[NT / 64];
+  __shared__ int any_big;
+  __shared__ int any_rot;
+  __shared__ double trace_s;
+
+  for (int idx = threadIdx.x; idx < npk; idx += NT) {
+    int i = 0, rem = idx;
+    while (rem >= N - i) { rem -= N - i; ++i; }
+    const int j = i + rem;
+    Gp[idx] = (i < n && j < n) ? gram_at(d, G, (long long)(pb.off + cidx[i]) * d.n + pb.off + cidx[j])
+                               : make_double2(0.0, 0.0);
+  }
+  for (int idx = threadIdx.x; idx < nblk; idx += NT) {
+    int Q = 0, rem = idx;
+    while (rem >= nq - 1 - Q) { rem -= nq - 1 - Q; ++Q; }
+    blk[idx] = (unsigned short)(Q | ((Q + 1 + rem) << 8));
+  }
+  // trace of the whole matrix (both blocks in block-diagonal mode)
+  {
+    double part = 0.0;
+    for (int i = threadIdx.x; i < d.n; i += NT) part += gram_at(d, G, (long long)i * d.n + i).x;
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int w = 0; w < NT / 64; ++w) s += wsum[w];
+      trace_s = s;
+    }
+    __syncthreads();
+  }
+  const double tr = trace_s;
+  const bool finite = isfinite(tr) && tr > 0.0;
+
+  int step_count = 0, sweeps_done = 0;
+  double* log = d.rot_log + pid * d.log_stride;
+  const int hN = N / 2;
+  const double tol = d.tol > 0.0 ? d.tol : 1e-15;
+  const double stop_ratio = d.early_stop ? 0.25 * sqrt(tol) : 0.0;
+  const double stop_ratio2 = stop_ratio * stop_ratio;
+  const double floor2 = (0.1 * tol * tr) * (0.1 * tol * tr);
+  const int ngroups = c_plan.ngroups[kk];
+  const char* Gb = reinterpret_cast<const char*>(Gp);
+  char* Gw = reinterpret_cast<char*>(Gp);
+  constexpr unsigned long long kSign = 0x8000000000000000ull;
+  if (n >= 2 && finite) {
+    for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+      if (threadIdx.x == 0) { any_rot = 0; any_big = 0; }
+      __syncthreads();
+      bool my_big = false;       // coset lanes: rotated a pair at or above the stop ratio this sweep
+      for (int g = 0; g < ngroups; ++g) {
+        const unsigned gi = c_plan.grp[kk][g];
+        const int ga = gi & 0xff, gbv = (gi >> 8) & 0xff, m = (int)(gi >> 16);
+        // -- each coset's diagonal block: the group's rotations one matching
+        //    after another, in registers --
+        //    (two lanes per coset, lane ln working pair ln of each matching)
+        if (threadIdx.x < 2 * nq) {
+          const int Q = threadIdx.x >> 1, ln = threadIdx.x & 1;
+          int e1 = ga, e2 = gbv;
+          if (hibit(e2) == hibit(e1)) e2 ^= e1;
+          const int h1 = hibit(e1), h2 = hibit(e2);
+          const int lo = min(h1, h2), hi = max(h1, h2);
+          const int r0 = insert_zero(insert_zero(Q, lo), hi);
+          const int4 v = make_int4(r0, r0 ^ ga, r0 ^ gbv, r0 ^ ga ^ gbv);
+          const int4 v16 = make_int4(16 * v.x, 16 * v.y, 16 * v.z, 16 * v.w);
+          const int4 rb16 = make_int4(16 * (pidx(v.x, v.x, N) - v.x), 16 * (pidx(v.y, v.y, N) - v.y),
+                                      16 * (pidx(v.z, v.z, N) - v.z), 16 * (pidx(v.w, v.w, N) - v.w));
+          double2 B[4][4];
+#define COSET_LD(S, U, CS, CU)                                                                       \
+  B[S][U] = conj_if(*reinterpret_cast<const double2*>(Gb + coset_off(v16.CS, rb16.CS, v16.CU, rb16.CU)), \
+                    coset_msk(v16.CS, v16.CU));                                                        \
+  B[U][S] = cconj(B[S][U]);
+          B[0][0] = make_double2(reinterpret_cast<const double2*>(Gb + rb16.x + v16.x)->x, 0.0);
+          B[1][1] = make_double2(reinterpret_cast<const double2*>(Gb + rb16.y + v16.y)->x, 0.0);
+          B[2][2] = make_double2(reinterpret_cast<const double2*>(Gb + rb16.z + v16.z)->x, 0.0);
+          B[3][3] = make_double2(reinterpret_cast<const double2*>(Gb + rb16.w + v16.w)->x, 0.0);
+          COSET_LD(0, 1, x, y) COSET_LD(0, 2, x, z) COSET_LD(0, 3, x, w)
+          COSET_LD(1, 2, y, z) COSET_LD(1, 3, y, w) COSET_LD(2, 3, z, w)
+#undef COSET_LD
+          const RotCtl rc{tol, floor2, stop_ratio2};
+          double* lg = log + (long long)step_count * hN * 3;
+          double sig[4] = {1.0, 1.0, 1.0, 1.0}, isig[4] = {1.0, 1.0, 1.0, 1.0};
+          bool act = coset_matching<0>(B, sig, isig, v, ga, ln, rc, lg, rq[Q][0], &my_big);
+          if (m > 1) act |= coset_matching<1>(B, sig, isig, v, gbv, ln, rc, lg + hN * 3, rq[Q][1], &my_big);
+          if (m > 2)
+            act |= coset_matching<2>(B, sig, isig, v, ga ^ gbv, ln, rc, lg + 2 * hN * 3, rq[Q][2], &my_big);
+          if (act) {
+            any_rot = 1;
+            // (both lanes hold the same block; each stores half of it)
+#define COSET_ST(S, U, CS, CU)                                                                       \
+  *reinterpret_cast<double2*>(Gw + coset_off(v16.CS, rb16.CS, v16.CU, rb16.CU)) =                       \
+      conj_if(B[S][U], coset_msk(v16.CS, v16.CU));
+            if (ln == 0) {
+              *reinterpret_cast<double2*>(Gw + rb16.x + v16.x) = B[0][0];
+              *reinterpret_cast<double2*>(Gw + rb16.y + v16.y) = B[1][1];
+              COSET_ST(0, 1, x, y) COSET_ST(0, 2, x, z) COSET_ST(0, 3, x, w)
+            } else {
+              *reinterpret_cast<double2*>(Gw + rb16.z + v16.z) = B[2][2];
+              *reinterpret_cast<double2*>(Gw + rb16.w + v16.w) = B[3][3];
+              COSET_ST(1, 2, y, z) COSET_ST(1, 3, y, w) COSET_ST(2, 3, z, w)
+            }
+#undef COSET_ST
+          }
+          if (ln == 0) {
+            qsig[Q] = make_double4(sig[0], sig[1], sig[2], sig[3]);
+            qact[Q] = act;
+            qm[Q] = v16;
+            qrb[Q] = rb16;
+          }
+        }
+        __syncthreads();
+        // -- off-diagonal blocks: G_QR <- U_Q^H G_QR U_R --
+        for (int idx = threadIdx.x; idx < nblk; idx += NT) {
+          const unsigned short qr = blk[idx];
+          const int Q = qr & 0xff, R = qr >> 8;
+          if (!qact[Q] && !qact[R]) continue;
+          const int4 mq = qm[Q], bq = qrb[Q], mr = qm[R], br = qrb[R];
+          double2 X[4][4];
+#define COSET_LD(S, U, CS, CU)                                                                       \
+  X[S][U] = conj_if(*reinterpret_cast<const double2*>(Gb + coset_off(mq.CS, bq.CS, mr.CU, br.CU)),     \
+                    coset_msk(mq.CS, mr.CU));
+#define COSET_ROW(S, CS) COSET_LD(S, 0, CS, x) COSET_LD(S, 1, CS, y) COSET_LD(S, 2, CS, z) COSET_LD(S, 3, CS, w)
+          COSET_ROW(0, x) COSET_ROW(1, y) COSET_ROW(2, z) COSET_ROW(3, w)
+#undef COSET_ROW
+#undef COSET_LD
+          coset_block<0>(X, rq[Q][0], rq[R][0]);
+          if (m > 1) coset_block<1>(X, rq[Q][1], rq[R][1]);
+          if (m > 2) coset_block<2>(X, rq[Q][2], rq[R][2]);
+          const double4 sq = qsig[Q], sr = qsig[R];
+#define COSET_ST(S, U, CS, CU)                                                                       \
+  *reinterpret_cast<double2*>(Gw + coset_off(mq.CS, bq.CS, mr.CU, br.CU)) =                             \
+      conj_if(cscale(X[S][U], sq.CS * sr.CU), coset_msk(mq.CS, mr.CU));
+#define COSET_ROW(S, CS) COSET_ST(S, 0, CS, x) COSET_ST(S, 1, CS, y) COSET_ST(S, 2, CS, z) COSET_ST(S, 3, CS, w)
+          COSET_ROW(0, x) COSET_ROW(1, y) COSET_ROW(2, z) COSET_ROW(3, w)
+#undef COSET_ROW
+#undef COSET_ST
+        }
+        step_count += m;
+        __syncthreads();
+      }
+      ++sweeps_done;
+      if (my_big) any_big = 1;
+      __syncthreads();
+      if (any_rot == 0 || any_big == 0) break;
+      __syncthreads();
+    }
+  }
+  // -- eigenvalues, descending order, truncation --
+  for (int i = threadIdx.x; i < n; i += NT) {
+    const double l = Gp[pidx(i, i, N)].x;
+    lam[i] = (isfinite(l) && l > 0.0) ? l : 0.0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += NT) {
+    int rk = 0;
+    const double li = lam[i];
+    for (int j = 0; j < n; ++j) rk += (lam[j] > li) || (lam[j] == li && j < i);
+    order_s[rk] = i;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mine = 0.0;
+    for (int i = 0; i < n; ++i) mine += lam[i];
+    const double tot = d.blocks > 1 ? tr : mine;
+    int k = 0;
+    double kept = 0.0;
+    const int lim = min(min(d.cap, pb.pad), n);
+    if (finite && tot > 0.0) {
+      while (k < lim && lam[order_s[k]] > d.cutoff * tot) { kept += lam[order_s[k]]; ++k; }
+    }
+    double scale = 0.0;
+    if (d.blocks > 1) {
+      scale = finite ? 1.0 / sqrt(tr) : 0.0;
+      if (!finite && d.flags) atomicOr(d.flags + t, 1);
+      if (d.disc_acc && tot > 0.0) atomicAdd(d.disc_acc + t, (mine - kept) / tot);
+    } else {
+      if (!(kept > 0.0) || !isfinite(kept)) {
+        k = 0;
+        if (d.flags) d.flags[t] |= 1;
+      } else {
+        scale = 1.0 / sqrt(kept);
+      }
+      if (d.disc_acc && tot > 0.0) d.disc_acc[t] += (tot - kept) / tot;
+      if (d.degen_acc && k > 0 && k < n) {
+        const double lk1 = lam[order_s[k - 1]], lk = lam[order_s[k]];
+        if (lk > d.cutoff * tot && lk1 - lk <= 1e-6 * lk1) d.degen_acc[t] += 1;
+      }
+      if (d.rank_out) d.rank_out[t * d.rank_stride] = k;
+      if (d.rank_max) d.rank_max[t * d.rank_stride] = max(d.rank_max[t * d.rank_stride], k);
+    }
+    if (d.flops_acc || d.nk_out) {
+      // algorithmic work of an n x n complex Hermitian eigen-decomposition
+      // with vectors: 36 n^3 real flops, n = the number of non-zero
+      // eigenvalues (the actual bond dimension)
+      int na = 0;
+      for (int i = 0; i < n; ++i) na += lam[i] > 1e-15 * tot;
+      const double f = 36.0 * (double)na * na * na;
+      if (d.flops_acc) {
+        if (d.blocks > 1) atomicAdd(d.flops_acc + t, f);
+        else d.flops_acc[t] += f;
+      }
+      if (d.nk_out) {
+        d.nk_out[t * 4 + 2 * pb.k] = na;
+        d.nk_out[t * 4 + 2 * pb.k + 1] = k;
+        if (d.blocks <= 1) { d.nk_out[t * 4 + 2] = 0; d.nk_out[t * 4 + 3] = 0; }
+      }
+    }
+    if (d.sweeps_out) d.sweeps_out[t] = sweeps_done;
+    d.kept[pid] = k;
+    d.scale_abs[pid] = scale;
+    d.nsteps[pid] = step_count;
+  }
+  for (int a = threadIdx.x; a < n; a += NT) {
+    d.order[pid * pb.n + a] = order_s[a];
+    d.lam_sorted[pid * pb.n + a] = lam[order_s[a]];
+  }
+}
+
+// Kept eigenvectors of a problem of size > 64 from the rotation log of its
+// solver (coset-grouped or circle-ordered).  V = J_1 J_2 ... J_S, so column c of V is
+// J_1 (J_2 (... (J_S e_c))): the log is replayed in reverse on the unit
+// vectors of the kept columns only.  Columns are independent, so each
+// wavefront owns a few of them in LDS and runs through the log with no
+// workgroup barrier; lane j applies the rotations of pairs j and j + 64 of
+// every matching (disjoint index pairs).  One workgroup per problem (a row,
+// or one diagonal block of a row).
 constexpr int kVecCols = 4;     // columns per wave and pass
 template <int NMAX>
 __global__ void __launch_bounds__(1024) k_jacobi_vectors(EighDesc d) {
@@ -482,8 +944,11 @@ __global__ void __launch_bounds__(1024) k_jacobi_vectors(EighDesc d) {
   __shared__ int inv[NMAX];
   __shared__ int wcount[W];
   const int n = compact_rows<W>(d, d.G + t * (long long)d.n * d.n, pb, cidx, inv, wcount);
-  const int n2 = n + (n & 1);
-  const int h = n2 / 2;
+  const bool cos = coset_order(n);
+  int kk = 2;
+  while ((1 << kk) < n) ++kk;
+  const int N = cos ? 1 << kk : n + (n & 1);   // the solver's size
+  const int h = N / 2;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;   // launched with W waves
   const int k = d.kept[pid];
   for (int a = threadIdx.x; a < n; a += W * 64) {
@@ -501,7 +966,7 @@ __global__ void __launch_bounds__(1024) k_jacobi_vectors(EighDesc d) {
     for (int cc = 0; cc < kVecCols; ++cc) {
       const int a = base + wave + cc * W;
       if (a < k) ncol = cc + 1;
-      for (int i = lane; i < n2; i += 64)
+      for (int i = lane; i < N; i += 64)
         X[wave][cc][i] = make_double2((a < k && i == order_s[a]) ? 1.0 : 0.0, 0.0);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -524,13 +989,14 @@ __global__ void __launch_bounds__(1024) k_jacobi_vectors(EighDesc d) {
         }
       };
       fetch(steps - 1);
-      int s = (steps - 1) % (n2 - 1);
+      int s = (steps - 1) % (N - 1);            // position in the sweep
       for (int st = steps - 1; st >= 0; --st) {
         double cc_[NPL], s0_[NPL], s1_[NPL];
         bool ok_[NPL];
 #pragma unroll
         for (int j = 0; j < NPL; ++j) { cc_[j] = nc[j]; s0_[j] = ns0[j]; s1_[j] = ns1[j]; ok_[j] = nok[j]; }
         fetch(st - 1);
+        const int dm = cos ? c_plan.dseq[kk][s] : 1, hb = hibit(dm);
 #pragma unroll
         for (int j = 0; j < NPL; ++j) {
           const int P = lane + 64 * j;
@@ -538,7 +1004,8 @@ __global__ void __launch_bounds__(1024) k_jacobi_vectors(EighDesc d) {
           const double2 sv = make_double2(s0_[j], s1_[j]);
           if (ok_[j] && !(c == 1.0 && sv.x == 0.0 && sv.y == 0.0)) {
             int p, q;
-            pair_of(n2, s, P, &p, &q);
+            if (cos) { p = insert_zero(P, hb); q = p ^ dm; }
+            else pair_of(N, s, P, &p, &q);
             for (int cc = 0; cc < ncol; ++cc) {
               const double2 xp = X[wave][cc][p], xq = X[wave][cc][q];
               X[wave][cc][p] = cadd(cscale(xp, c), cmul(sv, xq));
@@ -549,7 +1016,7 @@ __global__ void __launch_bounds__(1024) k_jacobi_vectors(EighDesc d) {
         // the next (earlier) step touches entries other lanes just wrote
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        s = (s == 0) ? n2 - 2 : s - 1;
+        s = (s == 0) ? N - 2 : s - 1;
       }
     }
     __syncthreads();
@@ -1013,6 +1480,81 @@ hipError_t launch_pchol(const EighDesc& d, int batch, hipStream_t st) {
 
 static bool g_attr_done = false;
 
+// Sweep plans of the coset-grouped solver for N = 2^k, k = 2 .. 8: groups
+// {a, b, a ^ b} (two-dimensional subspaces of (Z_2)^k, pairwise meeting only
+// in 0), then the left-over matchings two at a time ({a, b}), and at most one
+// alone ({a}, with any b != a fixing the cosets).  The triples are chosen
+// greedily over a few fixed pseudo-random orders, keeping the plan with the
+// fewest groups (a plan covers every d = 1 .. N - 1 exactly once).
+static SweepPlan make_sweep_plans() {
+  SweepPlan plan{};
+  unsigned long long lcg = 0x2545F4914F6CDD1DULL;
+  auto next = [&]() { lcg = lcg * 6364136223846793005ULL + 1442695040888963407ULL; return (unsigned)(lcg >> 33); };
+  for (int k = 2; k <= kPlanMaxK; ++k) {
+    const int N = 1 << k;
+    std::vector<unsigned> best;
+    for (int attempt = 0; attempt < 48; ++attempt) {
+      std::vector<int> ord;
+      for (int x = 1; x < N; ++x) ord.push_back(x);
+      if (attempt > 0)
+        for (int i = (int)ord.size() - 1; i > 0; --i) std::swap(ord[i], ord[next() % (unsigned)(i + 1)]);
+      std::vector<char> used(N, 0);
+      std::vector<unsigned> groups;
+      for (int a : ord) {
+        if (used[a]) continue;
+        for (int b : ord) {
+          if (b == a || used[b] || used[a ^ b]) continue;
+          used[a] = used[b] = used[a ^ b] = 1;
+          groups.push_back((unsigned)a | ((unsigned)b << 8) | (3u << 16));
+          break;
+        }
+      }
+      std::vector<int> rest;
+      for (int a : ord) if (!used[a]) rest.push_back(a);
+      size_t i = 0;
+      for (; i + 1 < rest.size(); i += 2) groups.push_back((unsigned)rest[i] | ((unsigned)rest[i + 1] << 8) | (2u << 16));
+      if (i < rest.size()) {
+        const int a = rest[i];
+        groups.push_back((unsigned)a | ((unsigned)(a == 1 ? 2 : 1) << 8) | (1u << 16));
+      }
+      if (best.empty() || groups.size() < best.size()) best = groups;
+    }
+    plan.ngroups[k] = (int)best.size();
+    int pos = 0;
+    for (size_t g = 0; g < best.size(); ++g) {
+      plan.grp[k][g] = best[g];
+      const int a = best[g] & 0xff, b = (best[g] >> 8) & 0xff, m = (int)(best[g] >> 16);
+      const int dd[3] = {a, b, a ^ b};
+      for (int j = 0; j < m; ++j) plan.dseq[k][pos++] = (unsigned char)dd[j];
+    }
+  }
+  return plan;
+}
+
+const SweepPlan& sweep_plans() {
+  static const SweepPlan plan = make_sweep_plans();
+  return plan;
+}
+
+// the plans in each device's constant memory (once per device)
+static hipError_t upload_plans() {
+  static bool done[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  if (done[dev]) return hipSuccess;
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c_plan), &sweep_plans(), sizeof(SweepPlan));
+  if (e == hipSuccess) done[dev] = true;
+  return e;
+}
+
+int eigh_padded_size(int n) {
+  int N = 4;
+  while (N < n) N <<= 1;
+  return N;
+}
+
 hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st) {
   if (batch <= 0) return hipSuccess;
   const int nb = d.blocks > 1 ? 2 : 1;
@@ -1025,6 +1567,8 @@ hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st) {
                         hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
     hipFuncSetAttribute((const void*)k_jacobi<false, kThreadsLarge, double2, 128>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
+    hipFuncSetAttribute((const void*)k_jacobi_coset<128>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        140 * 1024);
     g_attr_done = true;
   }
   const int nsub = d.n / nb;
@@ -1050,21 +1594,33 @@ hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st) {
                          gbytes + (size_t)n2 * n2 * sizeof(float2), st, d);
     return hipGetLastError();
   }
-  // problems above 64: rotation log, then the kept columns replayed from it
+  // problems above 64: coset-grouped sweeps on the matrix padded to a power
+  // of two, with a rotation log; then the kept columns replayed from it
   if (!d.rot_log || !d.order || !d.lam_sorted || !d.kept || !d.scale_abs || !d.nsteps)
     return hipErrorInvalidValue;
-  if ((long long)d.max_steps < (long long)kMaxSweeps * (n2 - 1) ||
-      d.log_stride < (long long)kMaxSweeps * (n2 - 1) * (n2 / 2) * 3)
+  const int N = eigh_padded_size(n2);
+  if ((long long)d.max_steps < (long long)kMaxSweeps * (N - 1) ||
+      d.log_stride < (long long)kMaxSweeps * (N - 1) * (N / 2) * 3)
     return hipErrorInvalidValue;
-  if (n2 <= 128) {
+  hipError_t pe = upload_plans();
+  if (pe != hipSuccess) return pe;
+  // (each solver returns at once on the other's problems)
+  if (N <= 128) {
+    const size_t nbytes = (size_t)N * (N + 1) / 2 * sizeof(double2);
     hipLaunchKernelGGL((k_jacobi<false, kThreadsLarge, double2, 128>), grid, dim3(kThreadsLarge), gbytes, st, d);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_jacobi_coset<128>, grid, dim3(kThreadsCoset), nbytes, st, d);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_jacobi_vectors<128>, grid, dim3(16 * 64), 0, st, d);
     return hipGetLastError();
   }
-  if (n2 > 256 || !d.gpk) return hipErrorInvalidValue;
+  if (N > 256 || !d.gpk) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_jacobi<false, kThreadsLarge, double2, 256>), grid, dim3(kThreadsLarge), 0, st, d);
+  hipError_t ec = hipGetLastError();
+  if (ec != hipSuccess) return ec;
+  hipLaunchKernelGGL(k_jacobi_coset<256>, grid, dim3(kThreadsCoset), 0, st, d);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_jacobi_vectors<256>, grid, dim3(8 * 64), 0, st, d);

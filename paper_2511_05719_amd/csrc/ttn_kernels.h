@@ -99,6 +99,9 @@ hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st);
 // problems of size <= 64 (per block)
 hipError_t launch_pchol(const EighDesc& d, int batch, hipStream_t st);
 int eigh_max_sweeps();
+// size that the solver pads a problem above 64 to (a power of two, >= 4):
+// its rotation log holds eigh_max_sweeps() * (N - 1) matchings of N / 2 pairs
+int eigh_padded_size(int n);
 
 // ----------------------------------------------------------- LEAF OPS ----
 // One op on one or both physical legs of a bottom node, for every trajectory.

@@ -1101,7 +1101,8 @@ ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {
   }
   const size_t Bz = (size_t)ctx->B;
   const int n2 = nmax;
-  ctx->max_steps = eigh_max_sweeps() * (n2 - 1);
+  const int nlog = eigh_padded_size(n2);      // the solver's padded size for problems above 64
+  ctx->max_steps = eigh_max_sweeps() * (nlog - 1);
   bool ok = true;
   ctx->gslices = (int)std::max<long long>(1, std::min<long long>(8, 2048 / ctx->B));
   ok &= hipMalloc((void**)&ctx->G, ctx->gslices * Bz * n2 * n2 * sizeof(double2)) == hipSuccess;
@@ -1109,7 +1110,7 @@ ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {
   ok &= hipMalloc(&ctx->Wa, Bz * n2 * n2 * ctx->es) == hipSuccess;
   // eigen-problems above 64 keep a rotation log: one per row, or one per
   // diagonal block when the blocks themselves exceed 64 (bonds above 128)
-  ctx->log_stride = (long long)ctx->max_steps * (n2 / 2) * 3;
+  ctx->log_stride = (long long)ctx->max_steps * (nlog / 2) * 3;
   const size_t log_problems = n2 > 128 ? 2 * Bz : Bz;
   if (n2 > 64) ok &= hipMalloc((void**)&ctx->rot_log, log_problems * ctx->log_stride * sizeof(double)) == hipSuccess;
   // (the solver strides the packed matrices by the size of a 256-wide one)
