@@ -335,14 +335,21 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
           const double2 g01 = conj_if(*reinterpret_cast<const double2*>(Gb + o01), m01);
           const double2 g10 = conj_if(*reinterpret_cast<const double2*>(Gb + o10), m10);
           const double2 g11 = conj_if(*reinterpret_cast<const double2*>(Gb + o11), m11);
-          // X = G_PQ [[1, tQ], [-conj(tQ), 1]]
-          const double2 x00 = c_sub_mul_conj(g00, g01, rQ.t), x01 = c_add_mul(g01, g00, rQ.t);
-          const double2 x10 = c_sub_mul_conj(g10, g11, rQ.t), x11 = c_add_mul(g11, g10, rQ.t);
-          // Y = cP cQ [[1, -tP], [conj(tP), 1]] X
-          const double cc = rP.c * rQ.c;
-          const double2 y00 = cscale(c_sub_mul(x00, x10, rP.t), cc), y01 = cscale(c_sub_mul(x01, x11, rP.t), cc);
-          const double2 y10 = cscale(c_add_mul_conj(x10, x00, rP.t), cc);
-          const double2 y11 = cscale(c_add_mul_conj(x11, x01, rP.t), cc);
+          // X = G_PQ J_Q, J = [[c, s], [-conj(s), c]], s = c t; then
+          // Y = J_P^H X (the products with c and s as written: the
+          // tangent form with one c_P c_Q scaling at the end changes the
+          // rounding enough to move stabilizer-state records off their
+          // exact values in complex64 runs)
+          const double2 sQ = cscale(rQ.t, rQ.c), sP = cscale(rP.t, rP.c);
+          const double2 sQc = cconj(sQ), sPc = cconj(sP);
+          const double2 x00 = csub(cscale(g00, rQ.c), cmul(g01, sQc));
+          const double2 x01 = cadd(cmul(g00, sQ), cscale(g01, rQ.c));
+          const double2 x10 = csub(cscale(g10, rQ.c), cmul(g11, sQc));
+          const double2 x11 = cadd(cmul(g10, sQ), cscale(g11, rQ.c));
+          const double2 y00 = csub(cscale(x00, rP.c), cmul(sP, x10));
+          const double2 y01 = csub(cscale(x01, rP.c), cmul(sP, x11));
+          const double2 y10 = cadd(cmul(sPc, x00), cscale(x10, rP.c));
+          const double2 y11 = cadd(cmul(sPc, x01), cscale(x11, rP.c));
           char* Gw = reinterpret_cast<char*>(Gp);
           *reinterpret_cast<double2*>(Gw + o00) = conj_if(y00, m00);
           *reinterpret_cast<double2*>(Gw + o01) = conj_if(y01, m01);
