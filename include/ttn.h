@@ -233,6 +233,16 @@ ttn_status ttn_uniforms(ttn_ctx* ctx, uint64_t traj_offset, int32_t rows, int32_
 /* Host-side evaluation of the same counter-based generator (no GPU needed). */
 double ttn_philox_uniform_host(uint64_t seed, uint64_t traj, uint64_t draw);
 
+/* Host-side sweep plan of the coset-ordered eigensolver for N = 2^k,
+ * k = 2 .. 8 (no GPU needed): a cyclic Jacobi sweep visits every pair of
+ * the N indices once (Sec. III.B's truncations solve G = V diag(s^2) V^H by
+ * such sweeps); this one is the matchings {(i, i ^ d)}, d = 1 .. N - 1,
+ * in groups.  groups[g] = a | b << 8 | m << 16: the group applies the m
+ * matchings a, b, a ^ b (first m of them), all inside the cosets of
+ * {0, a, b, a ^ b}.  Writes at most cap entries; returns the number of
+ * groups, or -1 for k outside 2 .. 8 or cap too small. */
+int32_t ttn_test_sweep_plan(int32_t k, uint32_t* groups, int32_t cap);
+
 /* [sync] Kernel-level test exports (not part of the simulation path; the
  * same kernels the engine launches).  Buffers are device memory of the
  * context's dtype (complex64 = 2 floats, complex128 = 2 doubles per

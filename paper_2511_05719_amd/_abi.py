@@ -19,6 +19,7 @@ SYMBOLS = ("ttn_create", "ttn_destroy", "ttn_last_error", "ttn_init_product", "t
            "ttn_compress",
            "ttn_to_statevector", "ttn_bond_dims", "ttn_uniforms", "ttn_philox_uniform_host",
            "ttn_version", "ttn_test_leg_apply", "ttn_test_gram", "ttn_test_eigh", "ttn_test_move",
+           "ttn_test_sweep_plan",
            "ttn_profile_enable", "ttn_profile_read", "ttn_autotune")
 CLASSES = {"contract": 0, "gram": 1, "eigh_small": 2, "eigh_large": 3, "leaf": 4, "extend": 5, "other": 6,
            "move": 7}
@@ -81,6 +82,7 @@ def lib() -> C.CDLL:
         "ttn_autotune": (i32, [vp, i32, C.POINTER(i64), C.POINTER(i64)]),
         "ttn_test_eigh": (i32, [vp, i32, i32, i32, i32, dbl, vp, i64, vp, vp, i64, vp, vp, i32]),
         "ttn_test_move": (i32, [vp, i32, i32, i32, i32, dbl, vp, i64, vp, vp, i64, vp, i32]),
+        "ttn_test_sweep_plan": (i32, [i32, C.POINTER(C.c_uint32), i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

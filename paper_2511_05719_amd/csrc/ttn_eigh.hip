@@ -1556,6 +1556,14 @@ static hipError_t upload_plans() {
   return e;
 }
 
+int eigh_sweep_plan(int k, unsigned* groups, int cap) {
+  if (k < 2 || k > kPlanMaxK || !groups) return -1;
+  const SweepPlan& plan = sweep_plans();
+  if (cap < plan.ngroups[k]) return -1;
+  for (int g = 0; g < plan.ngroups[k]; ++g) groups[g] = plan.grp[k][g];
+  return plan.ngroups[k];
+}
+
 int eigh_padded_size(int n) {
   int N = 4;
   while (N < n) N <<= 1;

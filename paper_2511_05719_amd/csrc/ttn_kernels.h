@@ -102,6 +102,9 @@ int eigh_max_sweeps();
 // size that the solver pads a problem above 64 to (a power of two, >= 4):
 // its rotation log holds eigh_max_sweeps() * (N - 1) matchings of N / 2 pairs
 int eigh_padded_size(int n);
+// the coset-ordered solver's sweep plan for N = 2^k (a | b << 8 | m << 16
+// per group): the number of groups, or -1 (k outside 2 .. 8, cap too small)
+int eigh_sweep_plan(int k, unsigned* groups, int cap);
 
 // ----------------------------------------------------------- LEAF OPS ----
 // One op on one or both physical legs of a bottom node, for every trajectory.

@@ -1012,6 +1012,10 @@ double ttn_philox_uniform_host(uint64_t seed, uint64_t traj, uint64_t draw) {
   return philox_uniform(seed, traj, draw);
 }
 
+int32_t ttn_test_sweep_plan(int32_t k, uint32_t* groups, int32_t cap) {
+  return eigh_sweep_plan(k, groups, cap);
+}
+
 const char* ttn_last_error(const ttn_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {

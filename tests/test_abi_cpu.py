@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     text = open(os.path.join(ROOT, "include", "ttn.h")).read()
-    return sorted(set(re.findall(r"^(?:ttn_status|double|const char\*)\s+(ttn_[a-z0-9_]+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^(?:ttn_status|double|int32_t|const char\*)\s+(ttn_[a-z0-9_]+)\s*\(", text, re.M)))
 
 
 def _lib():
