@@ -99,14 +99,15 @@ def test_gram_fp64(dtype, shape, leg, ksplit):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("n,rank", [(1, 1), (2, 2), (4, 3), (16, 16), (64, 40), (64, 64), (100, 100), (113, 90),
-                                    (120, 120), (128, 128), (128, 77), (200, 150), (240, 200), (256, 256),
-                                    (256, 90)])
+@pytest.mark.parametrize("n,rank", [(1, 1), (2, 2), (4, 3), (16, 16), (64, 40), (64, 64), (80, 80), (95, 70),
+                                    (100, 100), (113, 90), (120, 120), (121, 100), (128, 128), (128, 77),
+                                    (150, 120), (200, 150), (240, 200), (256, 256), (256, 90)])
 def test_eigh_centre_move_factors(dtype, n, rank):
     # n > 128: chi_max = 128 contexts, packed Gram matrix in device memory.
-    # Above 64 the circle-ordered solver takes n = 100 and 200; the coset-
-    # ordered one takes 113 (odd), 120 and 240 (padded to 128 / 256), 128
-    # and 256.
+    # Above 64, sizes below 3/4 of the next power of two take the circle-
+    # ordered solver (here n = 80, 95 (odd) and 150); the others the coset-
+    # ordered one, padded to 128 or 256 (n = 100, 113, 120, 121, 200, 240)
+    # or not (128, 256).
     from paper_2511_05719_amd._abi import lib, check
     g = np.random.default_rng(n * 1000 + rank)
     rows, m = 4, max(n, 8) * 3
