@@ -1622,25 +1622,43 @@ hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st) {
     return hipErrorInvalidValue;
   hipError_t pe = upload_plans();
   if (pe != hipSuccess) return pe;
-  // (each solver returns at once on the other's problems)
+  // (each solver returns at once on the other's problems; the circle-ordered
+  // launch, usually the thinner one, runs on the auxiliary stream beside the
+  // coset-ordered one so that neither waits for the other's tail)
+  if (N > 256 || (N > 128 && !d.gpk)) return hipErrorInvalidValue;
+  const bool fork = d.aux_stream && d.ev_fork && d.ev_join;
+  hipStream_t sc = st;
+  if (fork) {
+    hipError_t e = hipEventRecord(d.ev_fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(d.aux_stream, d.ev_fork, 0);
+    if (e != hipSuccess) return e;
+    sc = d.aux_stream;
+  }
+  if (N <= 128)
+    hipLaunchKernelGGL((k_jacobi<false, kThreadsLarge, double2, 128>), grid, dim3(kThreadsLarge), gbytes, sc, d);
+  else
+    hipLaunchKernelGGL((k_jacobi<false, kThreadsLarge, double2, 256>), grid, dim3(kThreadsLarge), 0, sc, d);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (fork) {
+    e = hipEventRecord(d.ev_join, sc);
+    if (e != hipSuccess) return e;
+  }
+  if (N <= 128)
+    hipLaunchKernelGGL(k_jacobi_coset<128>, grid, dim3(kThreadsCoset), (size_t)N * (N + 1) / 2 * sizeof(double2),
+                       st, d);
+  else
+    hipLaunchKernelGGL(k_jacobi_coset<256>, grid, dim3(kThreadsCoset), 0, st, d);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (fork) {
+    e = hipStreamWaitEvent(st, d.ev_join, 0);
+    if (e != hipSuccess) return e;
+  }
   if (N <= 128) {
-    const size_t nbytes = (size_t)N * (N + 1) / 2 * sizeof(double2);
-    hipLaunchKernelGGL((k_jacobi<false, kThreadsLarge, double2, 128>), grid, dim3(kThreadsLarge), gbytes, st, d);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_jacobi_coset<128>, grid, dim3(kThreadsCoset), nbytes, st, d);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_jacobi_vectors<128>, grid, dim3(16 * 64), 0, st, d);
     return hipGetLastError();
   }
-  if (N > 256 || !d.gpk) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_jacobi<false, kThreadsLarge, double2, 256>), grid, dim3(kThreadsLarge), 0, st, d);
-  hipError_t ec = hipGetLastError();
-  if (ec != hipSuccess) return ec;
-  hipLaunchKernelGGL(k_jacobi_coset<256>, grid, dim3(kThreadsCoset), 0, st, d);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_jacobi_vectors<256>, grid, dim3(8 * 64), 0, st, d);
   return hipGetLastError();
 }

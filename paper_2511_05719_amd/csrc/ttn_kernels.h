@@ -92,6 +92,11 @@ struct EighDesc {
   long long gslice;     // element stride between them
   long long log_stride; // doubles of rot_log per problem (problem = row, or (row, block))
   double2* gpk;         // problems of size > 128: packed G in device memory, [batch][256 * 257 / 2]
+  // problems above 64: the circle-ordered solver runs on aux_stream beside
+  // the coset-ordered one (fork after ev_fork on the caller's stream, joined
+  // through ev_join before the vector replay); all null: one stream
+  hipStream_t aux_stream;
+  hipEvent_t ev_fork, ev_join;
 };
 hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st);
 // Exact (non-truncating) centre-move factors by pivoted Cholesky of G, same

@@ -130,6 +130,10 @@ struct ttn_ctx {
   std::map<std::array<long long, 14>, int> tune;
   int64_t tuned_shapes = 0, tuned_changed = 0;
   hipEvent_t tune_ev[2] = {nullptr, nullptr};
+  // the eigensolver's auxiliary stream (default priority) and its fork/join
+  // events, created with the eigensolver workspace for bonds above 64
+  hipStream_t st_aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   ttn_ctx* adj = nullptr;      // twin context holding the adjoint state (created on first use)
   double gemm_flops = 0.0, gram_flops = 0.0;
   std::string err;
@@ -536,6 +540,7 @@ static void eigh_ws(const ttn_ctx* ctx, EighDesc& ed) {
   ed.rot_log = ctx->rot_log; ed.max_steps = ctx->max_steps; ed.log_stride = ctx->log_stride;
   ed.lam_sorted = ctx->lam_sorted; ed.order = ctx->order; ed.kept = ctx->kept;
   ed.scale_abs = ctx->scale_abs; ed.nsteps = ctx->nsteps; ed.gpk = ctx->gpk;
+  ed.aux_stream = ctx->st_aux; ed.ev_fork = ctx->ev_fork; ed.ev_join = ctx->ev_join;
 }
 
 // Move the isometry centre from x to its neighbour y (Sec. III.B: the
@@ -1116,7 +1121,12 @@ ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {
   // diagonal block when the blocks themselves exceed 64 (bonds above 128)
   ctx->log_stride = (long long)ctx->max_steps * (nlog / 2) * 3;
   const size_t log_problems = n2 > 128 ? 2 * Bz : Bz;
-  if (n2 > 64) ok &= hipMalloc((void**)&ctx->rot_log, log_problems * ctx->log_stride * sizeof(double)) == hipSuccess;
+  if (n2 > 64) {
+    ok &= hipMalloc((void**)&ctx->rot_log, log_problems * ctx->log_stride * sizeof(double)) == hipSuccess;
+    ok &= hipStreamCreateWithFlags(&ctx->st_aux, hipStreamNonBlocking) == hipSuccess;
+    ok &= hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) == hipSuccess;
+    ok &= hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) == hipSuccess;
+  }
   // (the solver strides the packed matrices by the size of a 256-wide one)
   if (n2 > 128) ok &= hipMalloc((void**)&ctx->gpk, Bz * (size_t)(256 * 257 / 2) * sizeof(double2)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->lam_sorted, Bz * n2 * sizeof(double)) == hipSuccess;
@@ -1157,6 +1167,12 @@ ttn_status ttn_destroy(ttn_ctx* ctx) {
   for (auto& b : ctx->bufs) hipFree(b.p);
   for (hipEvent_t e : ctx->tune_ev)
     if (e) hipEventDestroy(e);
+  if (ctx->st_aux) {
+    hipStreamSynchronize(ctx->st_aux);
+    hipStreamDestroy(ctx->st_aux);
+  }
+  if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
   for (int c = 0; c < TTN_NCLASS; ++c)
     for (auto& e : ctx->prof_ev[c]) {
       hipEventDestroy(e.first);
