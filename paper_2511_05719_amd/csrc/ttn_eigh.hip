@@ -42,13 +42,11 @@ __device__ inline int pidx(int i, int j, int n) {   // packed upper triangle, i 
   // (both factors are below 2^24: the full-rate 24-bit multiply)
   return (int)((unsigned)__umul24((unsigned)i, (unsigned)(2 * n - i + 1)) >> 1) + (j - i);
 }
-// Problems above 64 whose compacted even size n2 is at least 3/4 of the
+// Problems above 64 whose compacted even size n2 is at least 15/16 of the
 // next power of two are solved by coset-grouped sweeps on the padded matrix;
 // the others by circle-ordered sweeps on n2 (padding would cost more than the
-// grouping saves).  For one size alone the circle order is faster up to
-// n2 = 116 at N = 128; in a batch of mixed sizes the two solvers run as two
-// launches, and moving the sizes from 96 up to the coset launch shortens the
-// circle launch's tail by more than it costs (measured on the d = 5 batch).
+// grouping saves: at N = 128 the circle order is the faster one up to
+// n2 = 116, the coset order from 120).
 __device__ inline int padded_pow2(int n) {
   int N = 4;
   while (N < n) N <<= 1;
@@ -56,7 +54,7 @@ __device__ inline int padded_pow2(int n) {
 }
 __device__ inline bool coset_order(int n) {
   const int n2 = n + (n & 1);
-  return n2 > 64 && 4 * n2 >= 3 * padded_pow2(n2);
+  return n2 > 64 && 16 * n2 >= 15 * padded_pow2(n2);
 }
 
 // circle-method pairing for step s of an even size n (no integer division)

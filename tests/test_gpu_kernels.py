@@ -104,10 +104,10 @@ def test_gram_fp64(dtype, shape, leg, ksplit):
                                     (150, 120), (200, 150), (240, 200), (256, 256), (256, 90)])
 def test_eigh_centre_move_factors(dtype, n, rank):
     # n > 128: chi_max = 128 contexts, packed Gram matrix in device memory.
-    # Above 64, sizes below 3/4 of the next power of two take the circle-
-    # ordered solver (here n = 80, 95 (odd) and 150); the others the coset-
-    # ordered one, padded to 128 or 256 (n = 100, 113, 120, 121, 200, 240)
-    # or not (128, 256).
+    # Above 64, sizes below 15/16 of the next power of two take the circle-
+    # ordered solver (here n = 80, 95 and 113 (odd), 100, 150, 200); the
+    # others the coset-ordered one, padded to 128 or 256 (n = 120, 121 (odd),
+    # 240) or not (128, 256).
     from paper_2511_05719_amd._abi import lib, check
     g = np.random.default_rng(n * 1000 + rank)
     rows, m = 4, max(n, 8) * 3
