@@ -963,6 +963,11 @@ __global__ void __launch_bounds__(1024) k_jacobi_vectors(EighDesc d) {
     order_s[a] = d.order[pid * pb.n + a];
     lam_s[a] = d.lam_sorted[pid * pb.n + a];
   }
+  // the sweep's matchings in LDS: a per-step read from memory would wait
+  // for the log entries prefetched for the next step as well
+  __shared__ unsigned char dseq_s[256];
+  if (cos)
+    for (int i = threadIdx.x; i < N - 1; i += W * 64) dseq_s[i] = c_plan.dseq[kk][i];
   __syncthreads();
   const int steps = d.nsteps[pid];
   const double* log = d.rot_log + pid * d.log_stride;
@@ -1004,7 +1009,7 @@ __global__ void __launch_bounds__(1024) k_jacobi_vectors(EighDesc d) {
 #pragma unroll
         for (int j = 0; j < NPL; ++j) { cc_[j] = nc[j]; s0_[j] = ns0[j]; s1_[j] = ns1[j]; ok_[j] = nok[j]; }
         fetch(st - 1);
-        const int dm = cos ? c_plan.dseq[kk][s] : 1, hb = hibit(dm);
+        const int dm = cos ? dseq_s[s] : 1, hb = hibit(dm);
 #pragma unroll
         for (int j = 0; j < NPL; ++j) {
           const int P = lane + 64 * j;
