@@ -198,8 +198,8 @@ TRAFFIC = {
         "gram": {"bytes_per_launch": 0.5141e9, "source": "ttn_gemm.hip",
                  "sha256": "df0e24b983f08d00be0362e823a71c7ab335629e54e886fbf60a46ef502d37b8"},
         # k_jacobi<false, ...> + k_jacobi_coset<128> + k_jacobi_vectors<128> per launch
-        "eigh_large": {"bytes_per_launch": 5.302e9, "source": "ttn_eigh.hip",
-                       "sha256": "eb3fc587db3114d8543a7960bbd74ccf72a44280e5f7e54d5f851a819a2f8e6c"},
+        "eigh_large": {"bytes_per_launch": 7.779e9, "source": "ttn_eigh.hip",
+                       "sha256": "51cb1fbabc31685b1d4edd54c894a0e16710e6ac98e5e2a1cce0fc55649544d6"},
     },
 }
 
