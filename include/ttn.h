@@ -305,7 +305,7 @@ enum {
   TTN_CLASS_CONTRACT = 0,     /* c64/c128 leg contractions (MFMA)           */
   TTN_CLASS_GRAM = 1,         /* FP64 Gram matrices (MFMA)                  */
   TTN_CLASS_EIGH_SMALL = 2,   /* Jacobi eigensolver, n <= 64, vectors in LDS */
-  TTN_CLASS_EIGH_LARGE = 3,   /* Jacobi eigensolver, n > 64 (both kernels)  */
+  TTN_CLASS_EIGH_LARGE = 3,   /* Jacobi eigensolver, n > 64 (circle- and coset-ordered solvers and the vector replay) */
   TTN_CLASS_LEAF = 4,         /* bottom-node gates, measurements, jumps     */
   TTN_CLASS_EXTEND = 5,       /* controlled-gate index extensions           */
   TTN_CLASS_OTHER = 6,
