@@ -183,22 +183,22 @@ def cpu_oracle(circ, seed):
     return rate, (t2 - t0)
 
 
-# HBM traffic of one launch of a kernel class at this workload and B=2048
+# HBM traffic of one launch of a kernel class at this workload and B=3072
 # (rocprofv3 FETCH_SIZE / WRITE_SIZE passes, each scaled by what the counter
 # reads for a 256 MiB device copy, see the profile named), valid for the
 # source file it was measured on: reported only while that file is unchanged
 TRAFFIC = {
-    "profile": "profiles/ttn_d5_chi64_b2048_hbm_traffic.txt",
-    "batch": 2048,
+    "profile": "profiles/ttn_d5_chi64_b3072_hbm_traffic.txt",
+    "batch": 3072,
     "classes": {
         # k_zgemm<float2, float2, float2, ...>, all tile shapes
-        "contract": {"bytes_per_launch": 1.177e9, "source": "ttn_gemm.hip",
+        "contract": {"bytes_per_launch": 1.766e9, "source": "ttn_gemm.hip",
                      "sha256": "df0e24b983f08d00be0362e823a71c7ab335629e54e886fbf60a46ef502d37b8"},
         # k_zgemm<float2, float2, double2, ...>, all tile shapes
-        "gram": {"bytes_per_launch": 0.5141e9, "source": "ttn_gemm.hip",
+        "gram": {"bytes_per_launch": 0.7721e9, "source": "ttn_gemm.hip",
                  "sha256": "df0e24b983f08d00be0362e823a71c7ab335629e54e886fbf60a46ef502d37b8"},
         # k_jacobi<false, ...> + k_jacobi_coset<128> + k_jacobi_vectors<128> per launch
-        "eigh_large": {"bytes_per_launch": 7.779e9, "source": "ttn_eigh.hip",
+        "eigh_large": {"bytes_per_launch": 11.656e9, "source": "ttn_eigh.hip",
                        "sha256": "51cb1fbabc31685b1d4edd54c894a0e16710e6ac98e5e2a1cce0fc55649544d6"},
     },
 }
@@ -236,7 +236,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=2048)
+    ap.add_argument("--batch", type=int, default=3072)
     ap.add_argument("--rounds", type=int, default=5)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--plain-shots", type=int, default=4)
