@@ -199,7 +199,7 @@ TRAFFIC = {
                  "sha256": "df0e24b983f08d00be0362e823a71c7ab335629e54e886fbf60a46ef502d37b8"},
         # k_jacobi<false, ...> + k_jacobi_coset<128> + k_jacobi_vectors<128> per launch
         "eigh_large": {"bytes_per_launch": 11.656e9, "source": "ttn_eigh.hip",
-                       "sha256": "51cb1fbabc31685b1d4edd54c894a0e16710e6ac98e5e2a1cce0fc55649544d6"},
+                       "sha256": "b7089238a01ebf7eb10ab9b6c5bbe7cf18b1da0d839904710c3ec621df88a52c"},
     },
 }
 

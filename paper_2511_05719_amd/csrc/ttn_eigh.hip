@@ -17,7 +17,9 @@
 // per sweep; a step updates every 2 x 2 block (P, Q) of G by J_P^H G_PQ J_Q.
 // For n <= 64 the eigenvectors are accumulated in LDS next to G; for larger n
 // each step's rotations go to a log that a second kernel replays onto row
-// blocks of V.
+// blocks of V.  Problems above 64 whose size is near a power of two use
+// another cyclic order instead, the XOR matchings grouped by cosets (below),
+// which applies three steps per pass over G.
 //
 // Block-diagonal mode (blocks = 2): while a controlled gate's index rides on
 // a bond, the Gram matrix is block diagonal (the two halves carry orthogonal
@@ -486,7 +488,8 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
 }
 
 // ---------------------------------------------------------------------------
-// Problems above 64: coset-grouped sweeps.
+// Problems above 64 whose compacted size is near a power of two (see
+// coset_order): coset-grouped sweeps.
 //
 // The compacted matrix is padded with zero rows to N = 2^k (zero rows never
 // rotate).  A sweep is the N - 1 matchings M_d = {(i, i ^ d) : i < i ^ d},
@@ -494,10 +497,11 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
 // up to three from one subgroup H = {0, a, b, a ^ b} of (Z_2)^k: {a, b,
 // a ^ b}, {a, b} or {a}.  Every matching of a group maps each coset {r, r ^ a,
 // r ^ b, r ^ a ^ b} of H onto itself, so the group's rotations act inside
-// 4 x 4 blocks: one thread per coset computes them on its diagonal block in
-// registers (one rotation after another, as cyclic Jacobi does), and then
-// every off-diagonal block (Q, R) gets U_Q^H G_QR U_R with one read and one
-// write of G per group instead of one per matching.
+// 4 x 4 blocks: two lanes per coset compute them on its diagonal block in
+// registers (one matching after another, as cyclic Jacobi does; each lane
+// one of the matching's two disjoint rotations), and then every off-diagonal
+// block (Q, R) gets U_Q^H G_QR U_R with one read and one write of G per group
+// instead of one per matching.
 // ---------------------------------------------------------------------------
 constexpr int kPlanMaxK = 8;                  // N <= 256
 struct SweepPlan {
