@@ -34,6 +34,15 @@ def ad_kraus(gamma: float) -> tuple:
     return k0, k1
 
 
+def ad_trotter_nojump(gamma: float) -> np.ndarray:
+    """The no-jump gate of the Trotterised effective Hamiltonian (Sec. III.C):
+    with the single jump operator L1 = K1 / sqrt(dt) of Eq. 3 the factor
+    exp(-(dt/2) L1^dag L1) is exp(-(gamma/2) |1><1|) = diag(1, e^{-gamma/2}).
+    It agrees with K0 = diag(1, sqrt(1 - gamma)) only to first order in gamma;
+    the jump itself (K1, probability gamma <n1>) is the same in both readings."""
+    return np.array([[1.0, 0.0], [0.0, np.exp(-gamma / 2.0)]], dtype=np.complex128)
+
+
 def pauli_process_matrix(kraus) -> np.ndarray:
     """eta_ij of Eq. 9's Pauli-basis expansion (4x4, Hermitian)."""
     c = np.array([[np.trace(P @ K) / 2.0 for P in PAULIS] for K in kraus])

@@ -11,6 +11,14 @@ jump probability of one application is gamma <n_1>: gamma on |1>, gamma / 2 on
 |+>.  Twirl: p_X = p_Y = gamma / 4, p_Z = (1 - sqrt(1 - gamma))^2 / 4,
 p_I = (1 + sqrt(1 - gamma))^2 / 4.
 
+Trotterised AD (Sec. III.C, the reading with the no-jump gate
+M = diag(1, e^{-gamma/2})): starting from cos(t/2)|0> - i sin(t/2)|1> (one
+SRX of angle t on |0>), no jump has probability 1 - gamma sin^2(t/2) and
+leaves amplitudes proportional to (cos(t/2), -i sin(t/2) e^{-gamma/2}), so a Z
+measurement then reads 1 with probability
+sin^2 e^{-gamma} / (cos^2 + sin^2 e^{-gamma}); the exact Kraus branch K0
+gives sin^2 (1 - gamma) / (cos^2 + sin^2 (1 - gamma)) instead.
+
 Noiseless syndrome circuit (Sec. III, App. A.1): the data start in |0...0>,
 so every Z check reads +1 and Z-bar = +1; the first round's X checks are
 uniformly random and later rounds repeat them; the final data bits are
@@ -56,3 +64,11 @@ def pta_ad_probs(gamma: float) -> np.ndarray:
 
 def noiseless_logp(n_plaq: int) -> float:
     return float(-2.0 * n_plaq * np.log(2.0))
+
+
+def ad_nojump_then_one(theta: float, gamma: float, mode: str = "kraus") -> tuple:
+    """(P(no jump), P(Z = 1 | no jump)) after one SRX(theta) on |0> and one AD
+    location, for the exact Kraus unravelling or the Trotterised no-jump gate."""
+    c2, s2 = np.cos(theta / 2.0) ** 2, np.sin(theta / 2.0) ** 2
+    w = (1.0 - gamma) if mode == "kraus" else np.exp(-gamma)
+    return float(1.0 - gamma * s2), float(s2 * w / (c2 + s2 * w))

@@ -6,8 +6,12 @@ Amplitude damping (Eq. 2-3) is unravelled exactly by its Kraus operators: with
 p1 = <psi|K1^dag K1|psi> = gamma <n_q>, the trajectory jumps (psi -> K1 psi /
 sqrt(p1)) when its uniform draw u < p1 and otherwise evolves by K0 (psi ->
 K0 psi / sqrt(1 - p1)), so the trajectory average reproduces Eq. 2 exactly.
-(The paper's Trotterised no-jump gate of Eq. 7 equals K0 only to first order
-in gamma; the exact unravelling is the reading taken here.)
+(The paper's Trotterised no-jump gate, diag(1, e^{-gamma/2}) from the
+effective Hamiltonian of Sec. III.C, equals K0 only to first order in gamma;
+the exact unravelling is the default reading, the Trotterised one is
+ad_mode="trotter": same jump probability gamma <n_q> and jump K1 psi / sqrt(p1),
+but no jump evolves by the Trotter gate M, psi -> M psi / |M psi|, with
+probability 1 - p1.)
 
 Measurements follow the Born rule: p0 = <psi|Pi_0|psi>, outcome 0 iff u < p0,
 psi -> Pi_m psi / sqrt(p_m); outcome 0 is the +1 eigenvector (|0> or |+>).
@@ -139,14 +143,18 @@ def _pta(kind: int, values: np.ndarray) -> np.ndarray:
 
 def run(circ, theta, gamma, seed: int, traj_ids, forced_records=None,
         forced_branches=None, stop_after_op: int | None = None,
-        uniforms_override=None):
+        uniforms_override=None, ad_mode: str = "kraus"):
     """Run the op list for the trajectories `traj_ids`.
 
     theta, gamma: [n_loc] or [T, n_loc] per-location parameters.
     forced_records / forced_branches: if given, outcomes are taken from them
     instead of sampled (log P of a given record, A12 reading).
     stop_after_op: return (result, state) after executing op index k.
+    ad_mode: "kraus" (exact unravelling) or "trotter" (the no-jump branch
+    evolves by the Trotterised gate diag(1, e^{-gamma/2}), renormalised).
     """
+    if ad_mode not in ("kraus", "trotter"):
+        raise ValueError("ad_mode must be 'kraus' or 'trotter'")
     traj_ids = np.asarray(traj_ids, dtype=np.uint64).reshape(-1)
     T = traj_ids.size
     ops = np.asarray(circ.ops)
@@ -189,10 +197,20 @@ def run(circ, theta, gamma, seed: int, traj_ids, forced_records=None,
             p = np.where(jump, p1, 1.0 - p1)
             m = np.zeros((T, 2, 2), dtype=np.complex128)
             with np.errstate(divide="ignore", invalid="ignore"):
-                # K1 / sqrt(p1) on jump, K0 / sqrt(1 - p1) otherwise
-                m[:, 0, 1] = np.where(jump, np.sqrt(g) / np.sqrt(p), 0.0)
-                m[:, 0, 0] = np.where(jump, 0.0, 1.0 / np.sqrt(p))
-                m[:, 1, 1] = np.where(jump, 0.0, np.sqrt(1.0 - g) / np.sqrt(p))
+                if ad_mode == "kraus":
+                    # K1 / sqrt(p1) on jump, K0 / sqrt(1 - p1) otherwise
+                    m[:, 0, 1] = np.where(jump, np.sqrt(g) / np.sqrt(p), 0.0)
+                    m[:, 0, 0] = np.where(jump, 0.0, 1.0 / np.sqrt(p))
+                    m[:, 1, 1] = np.where(jump, 0.0, np.sqrt(1.0 - g) / np.sqrt(p))
+                else:
+                    # K1 / sqrt(p1) on jump; otherwise the Trotter gate
+                    # diag(1, e^{-g/2}) over the norm it leaves, which is
+                    # sqrt(1 - <n_q> (1 - e^{-g})), not sqrt(1 - p1)
+                    n1 = st.prob_one(q0)
+                    nrm = np.sqrt(1.0 - n1 * (1.0 - np.exp(-g)))
+                    m[:, 0, 1] = np.where(jump, np.sqrt(g) / np.sqrt(p), 0.0)
+                    m[:, 0, 0] = np.where(jump, 0.0, 1.0 / nrm)
+                    m[:, 1, 1] = np.where(jump, 0.0, np.exp(-g / 2.0) / nrm)
                 logp += np.log(p)
             st.apply_1q(q0, m)
             branches[:, ad_j] = jump

@@ -230,8 +230,8 @@ def test_decoder_corrects_low_weight_errors():
                 e = np.zeros(c.n, dtype=np.int64)
                 e[list(sup)] = 1
                 assert not decoder.decode_fail(c.checks, (cw + e) % 2, tab).any()
-        # a minimum-weight logical (weight d) is not corrected
-        assert cw.sum(axis=1).max() >= 0
+        # (a minimum-weight logical is not corrected:
+        # test_decoder_fails_on_minimum_weight_logicals)
 
 
 # ---------------------------------------------------------------- gradient ----
@@ -298,3 +298,93 @@ def test_gradient_matches_central_differences():
         fd = (gradient.log_prob(circ, th, gp, rec[None], br[None])[0] -
               gradient.log_prob(circ, th, gm, rec[None], br[None])[0]) / (2 * h)
         assert abs(fd - dga[l]) < 1e-5 * max(1.0, abs(dga[l])), (l, fd, dga[l])
+
+
+# ------------------------------------------------- binomial intervals ----
+def test_wilson_interval_pins():
+    # the interval every statistical comparison uses: fixed by its definition
+    # (the p whose score statistic |k - n p| / sqrt(n p (1 - p)) equals z),
+    # the normal quantile of a two-sided 99% level, k = 0 and mirror cases,
+    # and its exact binomial coverage
+    from scipy.stats import binom, norm
+    z = 2.5758293035489004
+    assert abs(z - norm.ppf(0.995)) < 1e-12
+    for n in (1, 10, 1000):
+        lo, hi = decoder.wilson_interval(0, n)
+        assert lo == 0.0 and abs(hi - z * z / (n + z * z)) < 1e-15
+    for n, k in ((50, 7), (1000, 13), (200, 100), (37, 36)):
+        lo, hi = decoder.wilson_interval(k, n)
+        lo2, hi2 = decoder.wilson_interval(n - k, n)
+        assert abs(lo - (1 - hi2)) < 1e-14 and abs(hi - (1 - lo2)) < 1e-14
+        for p in (lo, hi):
+            if 0.0 < p < 1.0:
+                assert abs((k - n * p) ** 2 - z * z * n * p * (1 - p)) < 1e-9 * n
+        assert lo < k / n < hi
+    n = 400
+    for p in (0.01, 0.1, 0.5):
+        cover = sum(binom.pmf(k, n, p) for k in range(n + 1)
+                    if decoder.wilson_interval(k, n)[0] <= p <= decoder.wilson_interval(k, n)[1])
+        assert 0.975 < cover < 0.9999, (p, cover)
+
+
+def test_decoder_fails_on_minimum_weight_logicals():
+    # X errors that commute with every Z check and flip Z-bar = Z^n (odd
+    # weight) are logical operators; the lightest have weight d (the code
+    # distance), and the decoder, seeing no syndrome, reports a failure
+    import itertools
+    from workload import build_color_code
+    g = np.random.default_rng(3)
+    for d in (3, 5):
+        c = build_color_code(d)
+        tab = decoder.leader_table(c.checks)
+        cw = (g.integers(0, 2, (16, c.n_plaq)) @ c.checks) % 2
+        found = 0
+        for w in range(1, d + 1):
+            for sup in itertools.combinations(range(c.n), w):
+                e = np.zeros(c.n, dtype=np.int64)
+                e[list(sup)] = 1
+                if (c.checks @ e % 2).any() or w % 2 == 0:
+                    continue
+                assert w == d, f"logical of weight {w} < d = {d}"
+                assert decoder.decode_fail(c.checks, (cw + e) % 2, tab).all()
+                found += 1
+        assert found > 0
+
+
+# ------------------------------------------------ Trotterised AD reading ----
+@pytest.mark.parametrize("mode", ["kraus", "trotter"])
+def test_ad_nojump_branch_closed_form(mode):
+    # one SRX(t) on |0>, one AD location, a Z measurement: forced no-jump
+    # then outcome 1 has log P = log P(no jump) + log P(1 | no jump) of the
+    # closed forms; the two readings differ at O(gamma^2)
+    prog = [("init", 0, 0), ("srxad", 0), ("meas", 0, 0)]
+    circ = custom_circuit(1, prog)
+    for t, g in ((0.7, 0.2), (1.9, 0.05), (1.1, 1e-2)):
+        pn, p1 = cf.ad_nojump_then_one(t, g, mode)
+        r = sv.run(circ, [t], [g], 0, np.arange(1), forced_records=[[1]], forced_branches=[[0]], ad_mode=mode)
+        assert abs(r.logp[0] - (np.log(pn) + np.log(p1))) < 1e-12
+        assert abs(r.probs[0, 0] - pn) < 1e-14 and abs(r.probs[0, 1] - p1) < 1e-14
+        other = cf.ad_nojump_then_one(t, g, "trotter" if mode == "kraus" else "kraus")[1]
+        assert abs(other - p1) > 0.1 * g * g * np.sin(t / 2) ** 2 * np.cos(t / 2) ** 2
+    # the no-jump gates themselves at gamma = 1e-2
+    assert abs(channels.ad_trotter_nojump(1e-2)[1, 1].real - 0.9950125) < 1e-7
+    assert abs(channels.ad_kraus(1e-2)[0][1, 1].real - 0.9949874) < 1e-7
+
+
+def test_ad_trotter_jump_frequency_and_state():
+    # the jump probability is gamma <n1> in both readings; sampled jump
+    # frequencies fall inside their 99.9% intervals
+    prog = [("init", 0, 0), ("srxad", 0), ("meas", 0, 0)]
+    circ = custom_circuit(1, prog)
+    t, g, Tn = 1.3, 0.3, 20000
+    r = sv.run(circ, [t], [g], 5, np.arange(Tn), ad_mode="trotter")
+    k = int(r.branches[:, 0].sum())
+    lo, hi = decoder.wilson_interval(k, Tn, 3.29)
+    assert lo <= g * np.sin(t / 2) ** 2 <= hi
+    # after a jump the qubit is |0>; after no jump it reads 1 with the
+    # Trotter closed form
+    assert not r.records[r.branches[:, 0] == 1, 0].any()
+    nj = r.branches[:, 0] == 0
+    k1 = int(r.records[nj, 0].sum())
+    lo, hi = decoder.wilson_interval(k1, int(nj.sum()), 3.29)
+    assert lo <= cf.ad_nojump_then_one(t, g, "trotter")[1] <= hi
