@@ -64,6 +64,15 @@ enum {
 
 enum { TTN_C64 = 0, TTN_C128 = 1 };
 
+/* Amplitude-damping unravelling (Sec. III.C, Eq. 2-3 and the Trotterised
+ * effective Hamiltonian).  Both jump with probability p1 = gamma <n1> to
+ * K1 psi / sqrt(p1).  TTN_AD_KRAUS (default): no jump evolves by
+ * K0 = diag(1, sqrt(1 - gamma)), which makes the trajectory average equal the
+ * channel of Eq. 2 exactly.  TTN_AD_TROTTER: no jump evolves by the paper's
+ * Trotterised gate exp(-(dt/2) L1^dag L1) = diag(1, e^{-gamma/2}) with
+ * L1 = K1 / sqrt(dt), renormalised; it equals K0 to first order in gamma. */
+enum { TTN_AD_KRAUS = 0, TTN_AD_TROTTER = 1 };
+
 /* op-list record: 9 int32 per op (see ttn_oplist_upload) */
 enum { TTN_OP_INIT = 0, TTN_OP_CNOT = 1, TTN_OP_SRX = 2, TTN_OP_AD = 3, TTN_OP_PAULI = 4, TTN_OP_MEAS = 5 };
 
@@ -76,6 +85,7 @@ typedef struct {
   int32_t chi_max;               /* bond-dimension cap (1 .. 128: bonds double to 2 chi_max while a controlled gate rides on them) */
   double cutoff;                 /* keep Schmidt values with s^2 / sum s^2 > cutoff (>= 0) */
   int32_t dtype;                 /* TTN_C64 or TTN_C128 */
+  int32_t ad_mode;               /* TTN_AD_KRAUS or TTN_AD_TROTTER */
   int32_t batch;                 /* B trajectories held by the context (>= 1) */
   uint64_t seed;                 /* random stream key, first word */
   void* stream;                  /* hipStream_t, NULL = default stream */
@@ -107,25 +117,38 @@ const char* ttn_last_error(const ttn_ctx* ctx);
  * basis: host [n_qubits] or NULL (all |0>). */
 ttn_status ttn_init_product(ttn_ctx* ctx, const uint8_t* basis);
 
-/* Apply a 2x2 matrix to qubit q of every row.  u: device float64
- * [rows][2][2][2] = (row-major matrix, re/im); row stride 8 doubles, or 0 to
- * broadcast one matrix.  A unitary on a physical leg keeps the canonical
- * form, so no centre move is made; a non-unitary matrix must be followed by
- * a measurement or explicit renormalisation by the caller. */
+/* Single-qubit gate or error on qubit q of every row: the one-qubit
+ * operations of the circuit model (Sec. II.A, Fig. 1b-e: an error location
+ * after a gate acts on one qubit, e.g. the SRX rotation of Eq. 1), applied to
+ * the qubit's physical leg of its bottom tree node (Sec. III.B).
+ * u: device float64 [rows][2][2][2] = (row-major matrix, re/im); row stride
+ * 8 doubles, or 0 to broadcast one matrix.  A unitary on a physical leg keeps
+ * the canonical form, so no centre move is made; a non-unitary matrix must
+ * be followed by a measurement or explicit renormalisation by the caller.
+ * Errors: TTN_EINVAL for a bad qubit, a null matrix or a negative stride. */
 ttn_status ttn_apply_1q(ttn_ctx* ctx, int32_t q, const double* u, int64_t row_stride);
 
-/* Apply a 4x4 gate (host float64 [4][4][2], row-major, q0 the high bit) to
- * qubits q0 != q1.  Sibling leaves: applied on their shared node.  Otherwise
- * the gate must be controlled on one of the two qubits (block diagonal in
- * its index, e.g. CNOT, CZ): it is split as sum_k |k><k| (x) B_k, the index
- * k is carried along the tree path from one leaf to the other while the
- * centre moves (exact, only numerically zero Schmidt values dropped), and a
- * sweep back truncates every bond of the path to chi_max / cutoff.
- * Returns TTN_EINVAL for a non-controlled gate between non-siblings. */
+/* Two-qubit gate of the syndrome-extraction circuit (the CNOTs of Sec. II.A,
+ * Fig. 1a) on a TTN: applied along the tree path between the two leaves, at a
+ * cost that grows with their distance in the tree, O(log N) (Sec. III.B),
+ * with the bonds it widens truncated by dropping the smallest Schmidt values
+ * (Sec. IV.A).  g: host float64 [4][4][2], row-major, q0 the high bit (a host
+ * matrix: its block structure decides on the host which qubit the zip starts
+ * from; the 16 entries are copied to a context-owned device buffer for the
+ * sibling case), qubits q0 != q1.  Sibling leaves: applied on their shared
+ * node.  Otherwise the gate must be controlled on one of the two qubits
+ * (block diagonal in its index, e.g. CNOT, CZ): it is split as
+ * sum_k |k><k| (x) B_k, the index k is carried along the tree path from one
+ * leaf to the other while the centre moves (exact, only numerically zero
+ * Schmidt values dropped), and a sweep back truncates every bond of the path
+ * to chi_max / cutoff.  Errors: TTN_EINVAL for bad qubits, a non-finite
+ * matrix, or a non-controlled gate between non-siblings. */
 ttn_status ttn_apply_2q(ttn_ctx* ctx, int32_t q0, int32_t q1, const double* g);
 
-/* Born-rule measurement of qubit q in basis 0 (Z) or 1 (X), outcome 0 = the
- * +1 eigenvector.  Moves the isometry centre to q's node, computes
+/* Born-rule measurement of qubit q in basis 0 (Z) or 1 (X): the ancilla
+ * readout of every syndrome round and the final data readout of the memory
+ * experiment (Sec. III, Fig. 1a), sampled per trajectory (Sec. III.C); outcome
+ * 0 = the +1 eigenvector.  Moves the isometry centre to q's node, computes
  * p0 = |Pi_0 psi|^2 / |psi|^2 in FP64, takes outcome 0 iff u < p0 with
  * u = draw `draw` of the row's stream (or the forced outcome), projects and
  * rescales to unit norm, and adds log p(outcome) to logp.
@@ -158,8 +181,14 @@ ttn_status ttn_oplist_upload(ttn_ctx* ctx, const int32_t* ops, int32_t n_ops, in
                              int32_t n_rec, int32_t n_draws, ttn_oplist** out);
 ttn_status ttn_oplist_free(ttn_oplist* ol);
 
-/* Run the whole op list on every row, starting from the product state
- * (ttn_init_product is called internally with every qubit in |0>).
+/* One Monte Carlo shot per row of the memory experiment of Sec. III (Fig. 1):
+ * the data start in |0>, C rounds of syndrome extraction with an error
+ * location after every gate, idle step and (re)initialisation (Fig. 1b-e),
+ * then the final data readout; each row is one quantum trajectory (Sec. III.C)
+ * of the TTN state, so averages over rows estimate the noisy circuit's
+ * output distribution.  Runs the whole op list on every row, starting from
+ * the product state (ttn_init_product is called internally with every qubit
+ * in |0>).
  * theta, gamma: device float64 [rows][n_loc] with row stride params_stride
  * (0 = broadcast one row); may be NULL when the op list has no such op.
  * records: device uint8 [rows][n_rec]; branches: device int8 [rows][n_ad]
@@ -170,8 +199,11 @@ ttn_status ttn_batch_run_circuit(ttn_ctx* ctx, const ttn_oplist* ol, const doubl
                                  const double* gamma, int64_t params_stride, uint64_t traj_offset,
                                  uint8_t* records, int8_t* branches, double* logp, ttn_stats* st);
 
-/* log P(record) of given records and Kraus branches (the sampled events are
- * forced instead of drawn): same op list and parameters as above; records
+/* log P(record) of given records and Kraus branches: the probability of one
+ * trajectory of Sec. III.C, i.e. the product of the Born probabilities of its
+ * measurement outcomes and the jump / no-jump probabilities of its Kraus
+ * branches (Eq. 2-3), computed by one pass with every sampled event forced
+ * instead of drawn.  Same op list and parameters as above; records
  * device uint8 [rows][n_rec], branches device int8 [rows][n_ad] (NULL if
  * no AD op); logp device float64 [rows] (out). */
 ttn_status ttn_log_prob(ttn_ctx* ctx, const ttn_oplist* ol, const uint8_t* records,
@@ -202,6 +234,18 @@ ttn_status ttn_log_prob_grad(ttn_ctx* ctx, const ttn_oplist* ol, const uint8_t* 
                              const int8_t* branches, const double* theta, const double* gamma,
                              int64_t params_stride, double* logp, double* dtheta, double* dgamma,
                              ttn_stats* st);
+
+/* Per-draw probability trace (test and statistics export of the same runs):
+ * with probs set (device float64 [rows][stride], stride >= the op list's
+ * n_draws), every later ttn_batch_run_circuit / ttn_log_prob /
+ * ttn_measure_project / ttn_kraus_jump writes, for each sampled event, the
+ * probability of the outcome taken (the Born probability of a measurement
+ * outcome, the jump or no-jump probability of an AD op, the probability of
+ * the Pauli chosen by a twirled op; Sec. III.C) to probs[row][draw]; columns of
+ * draws that did not happen are left untouched.  probs = NULL stops the
+ * trace.  The buffer must stay allocated while the trace is on.  Errors:
+ * TTN_EINVAL for stride < 1 with a non-null buffer. */
+ttn_status ttn_trace_probs(ttn_ctx* ctx, double* probs, int64_t stride);
 
 /* Logical readout (final-data lookup decoder): fail[row] = parity of the
  * data bits XOR parity of the minimum-weight correction of their Z-check

@@ -153,6 +153,8 @@ struct LeafBatch {
   int8_t* branches; long long br_stride;
   const int8_t* forced_br; long long forced_br_stride;
   double* logp;
+  double* probs; long long probs_stride;             // [rows][stride]: probability of each sampled event (may be null)
+  int ad_trotter;      // 1: LOP_KRAUS_AD without a jump applies diag(1, e^{-gamma/2}), renormalised
   int* flags;
   uint64_t seed;
   uint64_t traj_offset;

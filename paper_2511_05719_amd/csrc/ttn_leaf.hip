@@ -128,6 +128,11 @@ __global__ void __launch_bounds__(256) k_leaf_ops(LeafBatch b) {
         if (u < pI) which = 0;
         else if (u < pI + pX) which = 1;
         else if (u < pI + pX + pY) which = 2;
+        if (b.probs) {
+          const double pz = 1.0 - pI - pX - pY;
+          b.probs[(long long)row * b.probs_stride + op.draw] =
+              which == 0 ? pI : which == 1 ? pX : which == 2 ? pY : (op.kind == LOP_PAULI_SRX ? 0.0 : pz);
+        }
         if (which == 0) break;
         if (which == 1) set_m(m, 0, 1, 1, 0);
         else if (which == 3) set_m(m, 1, 0, 0, -1);
@@ -190,6 +195,7 @@ __global__ void __launch_bounds__(256) k_leaf_ops(LeafBatch b) {
         const double p = mres ? 1.0 - p0 : p0;
         if (p < 1e-300) { b.flags[row] |= 2; if (!b.adjoint) b.logp[row] = -INFINITY; }
         else if (!b.adjoint) b.logp[row] += log(p);
+        if (b.probs && !b.adjoint) b.probs[(long long)row * b.probs_stride + op.draw] = p;
         const double sc = (p > 0.0) ? 1.0 / sqrt(p * tot) : 0.0;
         // projector onto the outcome, rescaled to unit norm
         if (op.arg == 0) {
@@ -237,7 +243,22 @@ __global__ void __launch_bounds__(256) k_leaf_ops(LeafBatch b) {
         const double p = jump ? p1 : 1.0 - p1;
         if (p < 1e-300) { b.flags[row] |= 2; b.logp[row] = -INFINITY; }
         else b.logp[row] += log(p);
-        const double sc = (p > 0.0) ? 1.0 / sqrt(p * tot) : 0.0;
+        if (b.probs) b.probs[(long long)row * b.probs_stride + op.draw] = p;
+        double sc = (p > 0.0) ? 1.0 / sqrt(p * tot) : 0.0;
+        if (b.ad_trotter && op.kind == LOP_KRAUS_AD && !jump) {
+          // the Trotterised no-jump gate diag(1, e^{-g/2}): its norm is not
+          // (1 - p1) |psi|^2, so rescale by the norm it leaves
+          const double g = b.gamma[(long long)row * b.gamma_row_stride + op.loc];
+          set_m(K0, 1, 0, 0, exp(-0.5 * g));
+          double j0 = 0.0;
+          for (int o = 0; o < 2; ++o)
+            for (int u = 0; u < U; ++u) {
+              const int i0 = (op.leg == 0 ? (0 * 2 + o) : (o * 2 + 0)) * U + u;
+              const int i1 = (op.leg == 0 ? (1 * 2 + o) : (o * 2 + 1)) * U + u;
+              j0 += cabs2(cmul(K0[0][0], ld(T, i0))) + cabs2(cmul(K0[1][1], ld(T, i1)));
+            }
+          sc = (j0 > 0.0) ? 1.0 / sqrt(j0) : 0.0;
+        }
         for (int i = 0; i < 2; ++i)
           for (int j = 0; j < 2; ++j) m[i][j] = cscale(jump ? K1[i][j] : K0[i][j], sc);
         apply2(T, U, op.leg, m);

@@ -38,6 +38,7 @@
 
 using namespace ttn;
 
+
 enum {
   CLS_GEMM = TTN_CLASS_CONTRACT, CLS_GRAM = TTN_CLASS_GRAM, CLS_EIGH_SMALL = TTN_CLASS_EIGH_SMALL,
   CLS_EIGH_LARGE = TTN_CLASS_EIGH_LARGE, CLS_LEAF = TTN_CLASS_LEAF, CLS_EXTEND = TTN_CLASS_EXTEND,
@@ -67,6 +68,7 @@ struct ttn_oplist {
 struct ttn_ctx {
   // configuration
   int N = 0, L = 0, B = 0, c128 = 0, chi = 1;
+  int ad_trotter = 0;          // AD without a jump: Trotterised gate instead of K0
   double cutoff = 0.0;
   uint64_t seed = 0;
   hipStream_t st = nullptr;
@@ -104,6 +106,9 @@ struct ttn_ctx {
   double* disc_acc = nullptr;  // [B]
   int* flags = nullptr;        // [B]
   int* degen_acc = nullptr;    // [B]
+  double* gate4 = nullptr;     // [4][4][2] device copy of a sibling two-qubit gate
+  double* trace = nullptr;     // per-draw probability trace (caller's buffer) or null
+  long long trace_stride = 0;
   uint8_t* leader = nullptr;   // decoder table (device)
   size_t leader_bytes = 0;
   int* dec_datarec = nullptr;
@@ -686,6 +691,9 @@ static ttn_status flush_leaf(ttn_ctx* ctx) {
     b.c128 = ctx->c128;
     b.flags = ctx->flags;
     b.seed = ctx->seed;
+    b.ad_trotter = ctx->ad_trotter;
+    b.probs = b.adjoint ? nullptr : ctx->trace;
+    b.probs_stride = ctx->trace_stride;
     ++ctx->launches;
     ProfScope ps(ctx, CLS_LEAF);
     TTN_CHECK_HIP(launch_leaf_ops(b, ctx->st));
@@ -997,6 +1005,8 @@ static ttn_status run_oplist(ttn_ctx* ctx, const ttn_oplist* ol, const double* t
   if (!ol || ol->ctx != ctx) return fail(ctx, TTN_EINVAL, "op list belongs to another context");
   if (!records || !logp) return fail(ctx, TTN_EINVAL, "records and logp are required");
   if (ol->n_ad > 0 && !branches && !forced_br) return fail(ctx, TTN_EINVAL, "branches required (AD ops)");
+  if (ctx->trace && ctx->trace_stride < ol->n_draws)
+    return fail(ctx, TTN_EINVAL, "probability trace narrower than the op list's draws");
   ctx->hops = 0; ctx->launches = 0; ctx->block_hops = 0; ctx->gemm_flops = 0.0; ctx->gram_flops = 0.0;
   TTN_TRY(reset_state(ctx, nullptr));
   TTN_CHECK_HIP(launch_fill_f64(logp, 0.0, ctx->B, ctx->st));
@@ -1027,7 +1037,8 @@ ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {
   if (!cfg || !out) return TTN_EINVAL;
   *out = nullptr;
   if (cfg->n_qubits < 1 || !cfg->leaf_of_qubit || cfg->chi_max < 1 || cfg->batch < 1 ||
-      !(cfg->cutoff >= 0.0) || (cfg->dtype != TTN_C64 && cfg->dtype != TTN_C128))
+      !(cfg->cutoff >= 0.0) || (cfg->dtype != TTN_C64 && cfg->dtype != TTN_C128) ||
+      (cfg->ad_mode != TTN_AD_KRAUS && cfg->ad_mode != TTN_AD_TROTTER))
     return TTN_EINVAL;
   ttn_ctx* ctx = new ttn_ctx();
   ctx->N = cfg->n_qubits;
@@ -1036,6 +1047,7 @@ ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {
   ctx->L = L;
   ctx->B = cfg->batch;
   ctx->c128 = cfg->dtype == TTN_C128;
+  ctx->ad_trotter = cfg->ad_mode == TTN_AD_TROTTER;
   ctx->es = ctx->c128 ? 16 : 8;
   ctx->chi = cfg->chi_max;
   ctx->cutoff = cfg->cutoff;
@@ -1141,6 +1153,7 @@ ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {
   ok &= hipMalloc((void**)&ctx->adim, Bz * L * 3 * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->nk, Bz * 4 * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->nk_max, 4 * sizeof(int)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->gate4, 32 * sizeof(double)) == hipSuccess;
   ok &= hipHostMalloc((void**)&ctx->nk_host, 4 * sizeof(int), hipHostMallocDefault) == hipSuccess;
   if (ok) {
     ctx->ledger[CLS_EIGH_SMALL] = ctx->ledger_mem;
@@ -1180,7 +1193,7 @@ ttn_status ttn_destroy(ttn_ctx* ctx) {
     }
   void* ws[] = {ctx->G, ctx->Wi, ctx->Wa, ctx->rot_log, ctx->gpk, ctx->lam_sorted, ctx->order, ctx->kept,
                 ctx->scale_abs, ctx->nsteps, ctx->rank_table, ctx->ext, ctx->rank_max, ctx->ledger_mem,
-                ctx->adim, ctx->nk, ctx->nk_max,
+                ctx->adim, ctx->nk, ctx->nk_max, ctx->gate4,
                 ctx->disc_acc, ctx->flags,
                 ctx->degen_acc, ctx->leader, ctx->dec_datarec, ctx->dec_masks};
   for (void* p : ws)
@@ -1236,18 +1249,18 @@ ttn_status ttn_apply_2q(ttn_ctx* ctx, int32_t q0, int32_t q1, const double* g) {
         m[(rr * 4 + cc) * 2] = G(r, c, 0);
         m[(rr * 4 + cc) * 2 + 1] = G(r, c, 1);
       }
-    double* dm = nullptr;
-    TTN_CHECK_HIP(hipMalloc((void**)&dm, sizeof(m)));
-    TTN_CHECK_HIP(hipMemcpy(dm, m, sizeof(m), hipMemcpyHostToDevice));
     TTN_TRY(flush_leaf(ctx));
+    // stream-ordered copy into the context's gate buffer: an earlier gate's
+    // kernel has read its matrix before this copy runs
+    TTN_CHECK_HIP(hipMemcpyAsync(ctx->gate4, m, sizeof(m), hipMemcpyHostToDevice, ctx->st));
     ctx->run = LeafBatch{};
-    ctx->run.mat = dm;
+    ctx->run.mat = ctx->gate4;
     ctx->run.mat_row_stride = 0;
     push_leaf(ctx, n0, leaf_op(LOP_GATE4, 0));
     ttn_status s = flush_leaf(ctx);
     ctx->run = LeafBatch{};
-    hipStreamSynchronize(ctx->st);
-    hipFree(dm);
+    // the host copy is thread-local and may be overwritten by the next call
+    TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
     return s;
   }
   // controlled on q0 (block diagonal in q0's index) or on q1
@@ -1289,6 +1302,7 @@ ttn_status ttn_measure_project(ttn_ctx* ctx, int32_t q, int32_t basis, const uin
   if (!ctx) return TTN_EINVAL;
   if (q < 0 || q >= ctx->N || (basis != 0 && basis != 1) || !bits || !logp || draw < 0)
     return fail(ctx, TTN_EINVAL, "bad measurement arguments");
+  if (ctx->trace && draw >= ctx->trace_stride) return fail(ctx, TTN_EINVAL, "draw beyond the probability trace");
   int leg;
   const int node = bottom_of(ctx, q, &leg);
   TTN_TRY(move_centre(ctx, node));
@@ -1311,6 +1325,7 @@ ttn_status ttn_kraus_jump(ttn_ctx* ctx, int32_t q, const double* k, int64_t row_
   if (!ctx) return TTN_EINVAL;
   if (q < 0 || q >= ctx->N || !k || !branch || !logp || row_stride < 0 || draw < 0)
     return fail(ctx, TTN_EINVAL, "bad Kraus arguments");
+  if (ctx->trace && draw >= ctx->trace_stride) return fail(ctx, TTN_EINVAL, "draw beyond the probability trace");
   int leg;
   const int node = bottom_of(ctx, q, &leg);
   TTN_TRY(move_centre(ctx, node));
@@ -1639,6 +1654,7 @@ static ttn_status ensure_twin(ttn_ctx* ctx) {
   cfg.chi_max = ctx->chi;
   cfg.cutoff = ctx->cutoff;
   cfg.dtype = ctx->c128 ? TTN_C128 : TTN_C64;
+  cfg.ad_mode = ctx->ad_trotter ? TTN_AD_TROTTER : TTN_AD_KRAUS;
   cfg.batch = ctx->B;
   cfg.seed = ctx->seed;
   cfg.stream = ctx->st;
@@ -1759,6 +1775,8 @@ ttn_status ttn_log_prob_grad(ttn_ctx* ctx, const ttn_oplist* ol, const uint8_t* 
   if (!records || !theta || !gamma || !logp || !dtheta || !dgamma || params_stride < 0)
     return fail(ctx, TTN_EINVAL, "records, parameters and outputs are required");
   if (ol->n_ad > 0 && !branches) return fail(ctx, TTN_EINVAL, "branches required (AD ops)");
+  if (ctx->ad_trotter && ol->n_ad > 0)
+    return fail(ctx, TTN_EINVAL, "the gradient is defined for the exact Kraus unravelling (ad_mode TTN_AD_KRAUS)");
   for (int k = 0; k < ol->n_ops; ++k)
     if (ol->ops[(size_t)k * 9] == TTN_OP_PAULI)
       return fail(ctx, TTN_EINVAL, "the gradient needs the non-twirled channels (op list has twirled ops)");
@@ -1789,17 +1807,22 @@ ttn_status ttn_log_prob_grad(ttn_ctx* ctx, const ttn_oplist* ol, const uint8_t* 
   return s;
 }
 
-ttn_status ttn_decode(ttn_ctx* ctx, const uint8_t* records, int32_t n_rec, const int32_t* data_rec, int32_t n_data,
-                      const uint8_t* checks, int32_t n_checks, uint8_t* fail_out) {
+ttn_status ttn_trace_probs(ttn_ctx* ctx, double* probs, int64_t stride) {
   if (!ctx) return TTN_EINVAL;
-  if (!records || !data_rec || !checks || !fail_out || n_data < 1 || n_data > 64 || n_checks < 0 ||
-      n_checks > 24 || n_rec < 1)
-    return fail(ctx, TTN_EINVAL, "bad decoder arguments");
-  for (int k = 0; k < n_data; ++k)
-    if (data_rec[k] < 0 || data_rec[k] >= n_rec) return fail(ctx, TTN_EINVAL, "bad data record index");
-  // syndrome of each single flip
+  if (probs && stride < 1) return fail(ctx, TTN_EINVAL, "trace stride must be >= 1");
+  ctx->trace = probs;
+  ctx->trace_stride = probs ? stride : 0;
+  return TTN_OK;
+}
+
+// Leader-parity table of the final-data decoder: par[s] = parity of the
+// first minimum-weight flip pattern that breadth-first search over single
+// flips (qubits in ascending order) reaches with syndrome s; masks: the check
+// rows as two 32-bit words over the data index.
+static void decoder_table(const uint8_t* checks, int n_checks, int n_data, std::vector<uint8_t>& par,
+                          std::vector<uint32_t>& masks) {
   std::vector<uint32_t> col(n_data, 0);
-  std::vector<uint32_t> masks(2 * (size_t)std::max(n_checks, 1), 0);
+  masks.assign(2 * (size_t)std::max(n_checks, 1), 0);
   for (int p = 0; p < n_checks; ++p)
     for (int k = 0; k < n_data; ++k)
       if (checks[(size_t)p * n_data + k]) {
@@ -1807,9 +1830,9 @@ ttn_status ttn_decode(ttn_ctx* ctx, const uint8_t* records, int32_t n_rec, const
         if (k < 32) masks[2 * p] |= 1u << k;
         else masks[2 * p + 1] |= 1u << (k - 32);
       }
-  // breadth-first search over single flips: first-reached leader per syndrome
   const size_t S = (size_t)1 << n_checks;
-  std::vector<uint8_t> par(S, 0), seen(S, 0);
+  par.assign(S, 0);
+  std::vector<uint8_t> seen(S, 0);
   std::deque<uint32_t> dq;
   seen[0] = 1;
   dq.push_back(0);
@@ -1833,6 +1856,28 @@ ttn_status ttn_decode(ttn_ctx* ctx, const uint8_t* records, int32_t n_rec, const
       dq.push_back(s2);
     }
   }
+}
+
+static ttn_status decode_args(ttn_ctx* ctx, const uint8_t* records, int32_t n_rec, const int32_t* data_rec,
+                              int32_t n_data, const uint8_t* checks, int32_t n_checks, uint8_t* fail_out,
+                              int max_checks) {
+  if (!records || !data_rec || !checks || !fail_out || n_data < 1 || n_data > 64 || n_checks < 0 ||
+      n_checks > max_checks || n_rec < 1)
+    return fail(ctx, TTN_EINVAL, "bad decoder arguments (n_data 1..64, n_checks 0.." +
+                                     std::to_string(max_checks) + ")");
+  for (int k = 0; k < n_data; ++k)
+    if (data_rec[k] < 0 || data_rec[k] >= n_rec) return fail(ctx, TTN_EINVAL, "bad data record index");
+  return TTN_OK;
+}
+
+ttn_status ttn_decode(ttn_ctx* ctx, const uint8_t* records, int32_t n_rec, const int32_t* data_rec, int32_t n_data,
+                      const uint8_t* checks, int32_t n_checks, uint8_t* fail_out) {
+  if (!ctx) return TTN_EINVAL;
+  TTN_TRY(decode_args(ctx, records, n_rec, data_rec, n_data, checks, n_checks, fail_out, 24));
+  std::vector<uint8_t> par;
+  std::vector<uint32_t> masks;
+  decoder_table(checks, n_checks, n_data, par, masks);
+  const size_t S = par.size();
   if (ctx->leader_bytes < S) {
     if (ctx->leader) hipFree(ctx->leader);
     ctx->leader = nullptr;

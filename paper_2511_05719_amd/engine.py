@@ -61,7 +61,8 @@ class TTNEngine:
     """B trajectories of an N-qubit binary tree tensor network on one GPU."""
 
     def __init__(self, n_qubits: int, batch: int, leaf_of_qubit=None, chi_max: int = 64,
-                 cutoff: float = 1e-10, dtype: str = "c64", seed: int = 0, device: str = "cuda:0"):
+                 cutoff: float = 1e-10, dtype: str = "c64", seed: int = 0, device: str = "cuda:0",
+                 ad_mode: str = "kraus"):
         if not torch.cuda.is_available():
             raise RuntimeError("TTNEngine needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.device = torch.device(device)
@@ -79,6 +80,8 @@ class TTNEngine:
         cfg.chi_max = int(chi_max)
         cfg.cutoff = float(cutoff)
         cfg.dtype = {"c64": _abi.TTN_C64, "c128": _abi.TTN_C128}[dtype]
+        cfg.ad_mode = {"kraus": _abi.TTN_AD_KRAUS, "trotter": _abi.TTN_AD_TROTTER}[ad_mode]
+        self.ad_mode = ad_mode
         cfg.batch = self.batch
         cfg.seed = self.seed
         cfg.stream = C.c_void_p(self.stream.cuda_stream)
@@ -216,6 +219,19 @@ class TTNEngine:
         if code not in (0, _abi.TTN_EPROB):
             check(code, self._ctx)
         return logp, dth[:, :ol.n_loc], dga[:, :ol.n_loc], st.as_dict()
+
+    def trace_probs(self, probs: torch.Tensor | None):
+        """Record the probability of every sampled event of later runs into
+        probs [rows, n_draws] (float64, on the device); None stops it."""
+        if probs is None:
+            check(lib().ttn_trace_probs(self._ctx, None, 0), self._ctx)
+            self._trace = None
+            return
+        if probs.dtype != torch.float64 or probs.dim() != 2 or probs.shape[0] != self.batch or \
+                not probs.is_contiguous() or probs.device != self.device:
+            raise ValueError("probs must be a contiguous float64 [batch, n] tensor on the engine's device")
+        check(lib().ttn_trace_probs(self._ctx, _ptr(probs), int(probs.shape[1])), self._ctx)
+        self._trace = probs
 
     def decode(self, records: torch.Tensor, data_rec, checks) -> torch.Tensor:
         data_rec = np.ascontiguousarray(np.asarray(data_rec, dtype=np.int32))

@@ -267,14 +267,15 @@ def test_autotuned_tile_shapes_keep_parity(dtype):
     # the oracle's and log P agrees; forgetting the choices returns to the
     # fixed rule
     circ = build_circuit(3, 3, "srx+ad")
-    rows = 32
+    rows = 256
     g = np.random.default_rng(11)
     th = g.uniform(0.02, 0.3, (rows, circ.n_loc))
     ga = g.uniform(1e-3, 2e-2, (rows, circ.n_loc))
     ref = sv.run(circ, th, ga, 4, np.arange(rows))
     eng = _engine(circ, rows, dtype=dtype, seed=4)
     ol = eng.upload(circ)
-    tol = 1e-9 if dtype == "c128" else 2e-4
+    # complex64: log P sums ~300 log terms, each probability within ~1e-5
+    tol = 1e-9 if dtype == "c128" else 1e-4
     for on in (True, False):
         eng.autotune(on)
         res = eng.run_circuit(ol, theta=th, gamma=ga)
@@ -283,7 +284,9 @@ def test_autotuned_tile_shapes_keep_parity(dtype):
         if dtype == "c128":
             assert same.all()
         else:
-            assert same.mean() >= 0.9
+            # complex64 rows may take another branch only where a draw lands
+            # within the complex64 rounding of a probability
+            assert same.mean() >= 0.99, same.mean()
         assert np.abs(glp[same] - ref.logp[same]).max() < tol
     shapes, changed = eng.autotune(False)
     assert shapes > 0 and 0 <= changed <= shapes

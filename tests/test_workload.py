@@ -147,3 +147,44 @@ def test_optimized_layout_keeps_the_circuit():
     assert a.n_ops == b.n_ops and a.n_loc == b.n_loc and a.n_rec == b.n_rec
     key = lambda ops: sorted(map(tuple, ops[:, [0, 1, 2, 3, 8]].tolist()))
     assert key(a.ops) == key(b.ops)
+
+
+def test_snake_layout_is_a_path_through_the_lattice():
+    # App. B (Fig. 8a): consecutive qubits of the snake sit on the same or
+    # neighbouring lattice points, and the map is a bijection onto leaves 0..N-1
+    from workload import build_color_code, snake_layout
+    nb = {(1, 0), (-1, 0), (0, 1), (0, -1), (1, -1), (-1, 1), (0, 0)}
+    for d in (3, 5, 7):
+        c = build_color_code(d)
+        leaf = snake_layout(c)
+        assert sorted(leaf.tolist()) == list(range(c.n_qubits))
+        order = np.argsort(leaf)
+        for a, b in zip(order[:-1], order[1:]):
+            pa, pb = c.coords[int(a)], c.coords[int(b)]
+            assert (pb[0] - pa[0], pb[1] - pa[1]) in nb, (d, a, b, pa, pb)
+
+
+# Exact bond dimension of the Clifford skeleton (gates, resets and
+# measurements without noise) for the three orderings of App. B, Table III,
+# on this build's schedule: (d, C) -> (default, snake, optimized).  The paper's
+# AD values are d3C1 8/8/8 and d5C1 512/256/16 (C=1 columns reproduced
+# except the d=5 snake, whose path the text does not give); at C = d the
+# paper's AD runs grow further (d3C3 32/16/16, d5C5 2048/1024/256) because
+# damping leaves the stabilizer states that the skeleton keeps; d7C1: paper
+# >=2048/2048/256.
+TABLE_III_SKELETON = {(3, 1): (8, 8, 8), (3, 3): (16, 8, 8), (5, 1): (512, 512, 16), (5, 5): (512, 512, 16),
+                      (7, 1): (4096, 4096, 512)}
+
+
+@pytest.mark.parametrize("d,C", sorted(TABLE_III_SKELETON))
+def test_table3_orderings_exact_bond_dimension(d, C):
+    from workload import exact_bond_dim, optimized_layout
+    want = TABLE_III_SKELETON[(d, C)]
+    got = []
+    for lay in ("default", "snake"):
+        sk = build_circuit(d, C, "none", leaf_of_qubit=lay)
+        got.append(exact_bond_dim(sk.ops, sk.n_qubits, sk.leaf_of_qubit))
+    sk = build_circuit(d, C, "none")
+    got.append(optimized_layout(sk.ops, sk.n_qubits)[1])
+    assert tuple(got) == want
+    assert got[2] <= got[1] <= got[0]

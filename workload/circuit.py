@@ -186,6 +186,29 @@ def default_layout(code: ColorCode) -> np.ndarray:
     return np.arange(code.n_qubits, dtype=np.int32)
 
 
+def snake_layout(code: ColorCode) -> np.ndarray:
+    """The snake ordering of App. B (Fig. 8a, Table III): a path through the
+    lattice that runs along each row of points and turns back at its end,
+    so consecutive rows are swept in opposite directions (a face centre
+    contributes its X- and then its Z-ancilla); qubit number k on the path
+    goes to leaf k.  The figure's path is not reproduced in the text; this is
+    the boustrophedon of the same row sweep that defines the default labels."""
+    m = 3 * (code.d - 1) // 2
+    at = {}
+    for lab in sorted(code.coords):
+        at.setdefault(tuple(code.coords[lab]), []).append(lab)
+    path = []
+    for j in range(m + 1):
+        row = [(i, j) for i in range(m + 1 - j)]
+        if j % 2 == 1:
+            row.reverse()
+        for pt in row:
+            path += at[pt]
+    leaf = np.empty(code.n_qubits, dtype=np.int32)
+    leaf[np.asarray(path)] = np.arange(len(path), dtype=np.int32)
+    return leaf
+
+
 def n_leaves_for(n_qubits: int) -> int:
     L = 2
     while L < n_qubits:
@@ -196,8 +219,9 @@ def n_leaves_for(n_qubits: int) -> int:
 def build_circuit(d: int, rounds: int, channel: str,
                   leaf_of_qubit: np.ndarray | str | None = None) -> Circuit:
     """leaf_of_qubit: an explicit qubit -> leaf map, "default" / None (qubit i
-    on leaf i), or "optimized" (App. B, Algorithm 1: best of 8 clustered
-    layouts by the exact bond dimension of the circuit's Clifford skeleton)."""
+    on leaf i), "snake" (App. B, Fig. 8a), or "optimized" (App. B,
+    Algorithm 1: best of 8 clustered layouts by the exact bond dimension of
+    the circuit's Clifford skeleton)."""
     if channel not in CHANNELS:
         raise ValueError(f"unknown channel {channel!r}")
     if rounds < 1:
@@ -210,6 +234,8 @@ def build_circuit(d: int, rounds: int, channel: str,
         leaf_of_qubit, _ = optimized_layout(skeleton.ops, N)
     elif leaf_of_qubit is None or (isinstance(leaf_of_qubit, str) and leaf_of_qubit == "default"):
         leaf_of_qubit = default_layout(code)
+    elif isinstance(leaf_of_qubit, str) and leaf_of_qubit == "snake":
+        leaf_of_qubit = snake_layout(code)
     leaf_of_qubit = np.asarray(leaf_of_qubit, dtype=np.int32)
     L = n_leaves_for(N)
     if sorted(leaf_of_qubit.tolist()) != sorted(set(leaf_of_qubit.tolist())) or \
