@@ -257,6 +257,25 @@ ttn_status ttn_trace_probs(ttn_ctx* ctx, double* probs, int64_t stride);
 ttn_status ttn_decode(ttn_ctx* ctx, const uint8_t* records, int32_t n_rec, const int32_t* data_rec,
                       int32_t n_data, const uint8_t* checks, int32_t n_checks, uint8_t* fail);
 
+/* Logical readout as ttn_decode, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the leader-parity table (2^n_checks bytes), the data
+ * record columns and the check masks are staged in a fixed library-owned
+ * device array of TTN_DECODE_STATIC_SCRATCH_BYTES per GPU, held until the
+ * process ends (its address on a device is resolved when the first context
+ * is created there), instead of buffers the context allocates on first use.
+ * Limit: n_checks <= TTN_DECODE_STATIC_MAX_CHECKS (16; d <= 7 colour codes
+ * have at most 18 plaquettes, so d = 7 needs ttn_decode), n_data <= 64;
+ * larger sizes return TTN_EINVAL.  Every call on a GPU shares that GPU's
+ * array and overwrites every byte the kernel reads: calls that overlap on one
+ * GPU (other streams, other threads) race.  [sync]: returns after the decode
+ * has run (the table is built on the host and copied with the call).  Same
+ * arguments and outputs as ttn_decode. */
+#define TTN_DECODE_STATIC_MAX_CHECKS 16
+#define TTN_DECODE_STATIC_SCRATCH_BYTES (65536 + 512)
+ttn_status ttn_decode_static(ttn_ctx* ctx, const uint8_t* records, int32_t n_rec, const int32_t* data_rec,
+                             int32_t n_data, const uint8_t* checks, int32_t n_checks, uint8_t* fail);
+
 /* Move the isometry centre through every node (depth-first) so each bond is
  * re-decomposed and truncated with the context's rule; afterwards the bond
  * dimensions are the Schmidt ranks above the cutoff. */

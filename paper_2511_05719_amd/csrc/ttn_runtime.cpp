@@ -29,6 +29,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -38,6 +39,39 @@
 
 using namespace ttn;
 
+// Device scratch of ttn_decode_static: the decoder's leader-parity table
+// (2^n_checks bytes, n_checks <= 16), then the data-record columns (64 int32)
+// and the check masks (24 x 2 uint32).  One copy per GPU, held until the
+// process ends; its device address is looked up once per device when the
+// first context on that device is created (the host-side name is only a
+// stand-in and is never passed to a kernel or a copy).
+constexpr size_t kScratchTable = (size_t)1 << 16;
+constexpr size_t kScratchDataRec = kScratchTable;              // 64 int32
+constexpr size_t kScratchMasks = kScratchDataRec + 64 * sizeof(int);   // 48 uint32
+constexpr size_t kScratchBytes = kScratchMasks + 256;
+static_assert(((size_t)1 << TTN_DECODE_STATIC_MAX_CHECKS) == kScratchTable, "table size");
+static_assert(kScratchBytes == TTN_DECODE_STATIC_SCRATCH_BYTES, "scratch size");
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// the current device's copy of `scratch` (looked up on first use there)
+static hipError_t scratch_for_current_device(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 enum {
   CLS_GEMM = TTN_CLASS_CONTRACT, CLS_GRAM = TTN_CLASS_GRAM, CLS_EIGH_SMALL = TTN_CLASS_EIGH_SMALL,
@@ -107,6 +141,7 @@ struct ttn_ctx {
   int* flags = nullptr;        // [B]
   int* degen_acc = nullptr;    // [B]
   double* gate4 = nullptr;     // [4][4][2] device copy of a sibling two-qubit gate
+  uint8_t* scratch_dev = nullptr;  // device address of `scratch` on the context's GPU
   double* trace = nullptr;     // per-draw probability trace (caller's buffer) or null
   long long trace_stride = 0;
   uint8_t* leader = nullptr;   // decoder table (device)
@@ -1167,6 +1202,11 @@ ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {
   ok &= hipMalloc((void**)&ctx->flags, Bz * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->degen_acc, Bz * sizeof(int)) == hipSuccess;
   if (!ok) return bail(TTN_ENOMEM);
+  {
+    void* sp = nullptr;
+    if (scratch_for_current_device(&sp) != hipSuccess) return bail(TTN_EDEVICE);
+    ctx->scratch_dev = (uint8_t*)sp;
+  }
   if (reset_state(ctx, nullptr) != TTN_OK) return bail(TTN_EDEVICE);
   if (hipStreamSynchronize(ctx->st) != hipSuccess) return bail(TTN_EDEVICE);
   *out = ctx;
@@ -1892,6 +1932,30 @@ ttn_status ttn_decode(ttn_ctx* ctx, const uint8_t* records, int32_t n_rec, const
   TTN_CHECK_HIP(hipMemcpy(ctx->dec_masks, masks.data(), masks.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
   TTN_CHECK_HIP(launch_decode(records, n_rec, ctx->dec_datarec, n_data, ctx->dec_masks, n_checks, ctx->leader,
                               fail_out, ctx->B, ctx->st));
+  return TTN_OK;
+}
+
+ttn_status ttn_decode_static(ttn_ctx* ctx, const uint8_t* records, int32_t n_rec, const int32_t* data_rec,
+                             int32_t n_data, const uint8_t* checks, int32_t n_checks, uint8_t* fail_out) {
+  if (!ctx) return TTN_EINVAL;
+  TTN_TRY(decode_args(ctx, records, n_rec, data_rec, n_data, checks, n_checks, fail_out, TTN_DECODE_STATIC_MAX_CHECKS));
+  if (!ctx->scratch_dev) return fail(ctx, TTN_EDEVICE, "static scratch not resolved for this device");
+  std::vector<uint8_t> par;
+  std::vector<uint32_t> masks;
+  decoder_table(checks, n_checks, n_data, par, masks);
+  // every byte the kernel reads is rewritten here: the table's 2^n_checks
+  // entries, the n_data record columns and the n_checks mask pairs
+  uint8_t* base = ctx->scratch_dev;
+  int* d_datarec = (int*)(base + kScratchDataRec);
+  uint32_t* d_masks = (uint32_t*)(base + kScratchMasks);
+  TTN_CHECK_HIP(hipMemcpyAsync(base, par.data(), par.size(), hipMemcpyHostToDevice, ctx->st));
+  TTN_CHECK_HIP(hipMemcpyAsync(d_datarec, data_rec, n_data * sizeof(int), hipMemcpyHostToDevice, ctx->st));
+  TTN_CHECK_HIP(hipMemcpyAsync(d_masks, masks.data(), masks.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                               ctx->st));
+  TTN_CHECK_HIP(launch_decode(records, n_rec, d_datarec, n_data, d_masks, n_checks, base, fail_out, ctx->B,
+                              ctx->st));
+  // the host-side table must outlive the copies
+  TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
   return TTN_OK;
 }
 
