@@ -12,7 +12,10 @@ Tolerances (absolute, per probability), from the arithmetic:
 * complex128 with no cutoff (every non-zero Gram eigenvalue kept): the FP64
   Gram route resolves a bond's squared Schmidt weights to ~1e-16 of its total,
   so a probability carries ~1e-12..1e-11 after a few hundred centre moves
-  (config 1: 1e-12; the 3-round AD circuit: 2e-11).  Any cutoff w > 0 drops
+  (config 1: 1e-12; the 3-round AD circuit: 2e-11).  Wide Schmidt spectra
+  (damping up to 0.3) lose more: the Gram route gives a Schmidt value s a
+  relative accuracy of ~1e-16 s_max^2 / s^2, so there 99.9% of the
+  probabilities agree to 1e-12 and all to 1e-9.  Any cutoff w > 0 drops
   weights whose amplitude sqrt(w) can interfere with kept ones: at the
   rounding-floor cutoff 1e-15 probabilities move by up to ~4e-10, which is
   why these comparisons keep everything.
@@ -147,10 +150,10 @@ def test_trotter_ad_reading_matches_oracle(dtype):
     res, probs = _traced_run(eng, circ, th, ga)
     ref = sv.run(circ, th, ga, 2, np.arange(rows), ad_mode="trotter")
     if dtype == "c128":
-        same, _ = _compare(res, probs, ref, 2e-11, 0.0)
+        same, _ = _compare(res, probs, ref, 1e-9, 0.0, tol999=1e-12)
     else:
         same, _ = _compare(res, probs, ref, 1e-4, 0.01, tol999=1e-5)
-    assert np.abs(res.logp.cpu().numpy()[same] - ref.logp[same]).max() < (1e-10 if dtype == "c128" else 1e-3)
+    assert np.abs(res.logp.cpu().numpy()[same] - ref.logp[same]).max() < (1e-8 if dtype == "c128" else 1e-3)
     kraus = sv.run(circ, th, ga, 2, np.arange(rows))
     assert np.abs(kraus.logp - ref.logp).max() > 1e-6
     eng.close()
