@@ -270,10 +270,17 @@ def cpu_oracle(circ, seed, n_ops=10):
 # reads for a 256 MiB device copy, see the profile named), valid for the
 # source file it was measured on: reported only while that file is unchanged
 TRAFFIC = {
-    "profile": None,
-    "batch": None,
-    "layout": None,
-    "classes": {},
+    "profile": "profiles/ttn_d5_chi64_b2048_clustered_hbm_traffic.txt",
+    "batch": 2048,
+    "layout": "optimized",
+    "classes": {
+        # k_zgemm<float2, float2, float2, ...>, all tile shapes: 277.8 MB read + 182.8 MB written
+        "contract": {"bytes_per_launch": 460.6e6, "source": "ttn_gemm.hip",
+                     "sha256": "df0e24b983f08d00be0362e823a71c7ab335629e54e886fbf60a46ef502d37b8"},
+        # k_zgemm<float2, float2, double2, ...>, all tile shapes: 234.3 MB read + 27.6 MB written
+        "gram": {"bytes_per_launch": 261.9e6, "source": "ttn_gemm.hip",
+                 "sha256": "df0e24b983f08d00be0362e823a71c7ab335629e54e886fbf60a46ef502d37b8"},
+    },
 }
 
 
@@ -304,6 +311,14 @@ def copy_calibration():
     print("copied 3 x 256 MiB", flush=True)
 
 
+# machine balance: below this many algorithmic flops per algorithmic byte a
+# class is bound by HBM bandwidth, above it by its MFMA pipe
+RIDGE = {"contract": PEAK["fp32_mfma"] / PEAK["hbm"], "gram": PEAK["fp64_mfma"] / PEAK["hbm"]}
+PER_UNIT_BYTES = {
+    "contract": "8 ((n + k) r + 2 k n) bytes per centre move and side (complex64: node read once, factor read "
+                "once, result written once at the actual dimensions; per diagonal block in block moves)",
+    "gram": "8 n r + 16 n^2 bytes per Gram matrix (node rows read once, FP64 complex result written once)",
+}
 PER_UNIT = {
     "eigh": "36 n^3 real flops per n x n complex Hermitian eigen-decomposition with vectors, "
             "n = actual bond dimension (non-zero Gram eigenvalues)",
@@ -373,24 +388,39 @@ def main():
     classes = {}
     for k, (bound, peak) in BOUND_OF.items():
         v = prof[k]
-        ach = v["alg_flops"] / max(v["ms"] / 1e3, 1e-12)
-        classes[k] = {"share": v["ms"] / total_ms, "launches": v["launches"],
-                      "avg_ms": v["ms"] / max(v["launches"], 1), "achieved_tflops": ach / 1e12,
-                      "frac": ach / peak, "bound": bound}
+        sec = max(v["ms"] / 1e3, 1e-12)
+        ach = v["alg_flops"] / sec
+        c = {"share": v["ms"] / total_ms, "launches": v["launches"], "avg_ms": v["ms"] / max(v["launches"], 1),
+             "achieved_tflops": ach / 1e12, "frac_of_flop_peak": ach / peak, "bound": bound, "frac": ach / peak}
+        if v.get("alg_bytes"):
+            ai = v["alg_flops"] / v["alg_bytes"]
+            c["flops_per_byte"] = ai
+            c["achieved_tbs"] = v["alg_bytes"] / sec / 1e12
+            c["frac_of_hbm_peak"] = v["alg_bytes"] / sec / PEAK["hbm"]
+            if ai < RIDGE.get(k, 0.0):
+                c["bound"], c["frac"] = "hbm", c["frac_of_hbm_peak"]
         # flops the launches executed on their padded shapes (the statistics
         # run's count against one run's share of the time)
         padded = {"contract": st.get("gemm_flops"), "gram": st.get("gram_flops")}.get(k)
         if padded:
-            classes[k]["executed_tflops"] = padded / max(v["ms"] / 1e3 / max(steps, 1), 1e-12) / 1e12
+            c["executed_tflops"] = padded / max(v["ms"] / 1e3 / max(steps, 1), 1e-12) / 1e12
+        classes[k] = c
     dom = max(BOUND_OF, key=lambda k: prof[k]["ms"])
-    d = prof[dom]
-    bound, peak = BOUND_OF[dom]
-    achieved = d["alg_flops"] / max(d["ms"] / 1e3, 1e-12)
+    d, cd = prof[dom], classes[dom]
+    sec = max(d["ms"] / 1e3, 1e-12)
     traffic = class_traffic(dom, args.batch, args.layout)
-    roof = {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": traffic, "kernel_class": dom, "launches": d["launches"],
-            "avg_ms": d["ms"] / max(d["launches"], 1), "share_of_gpu_time": d["ms"] / total_ms,
-            "per_unit": PER_UNIT["eigh" if dom.startswith("eigh") else dom]}
+    per_launch = max(d["launches"], 1)
+    if cd["bound"] == "hbm":
+        roof = {"bound": "hbm", "achieved": d["alg_bytes"] / sec / 1e9, "peak": PEAK["hbm"] / 1e9,
+                "unit": "GB/s", "frac": cd["frac"], "alg_bytes_per_launch": d["alg_bytes"] / per_launch,
+                "per_unit": PER_UNIT_BYTES[dom], "flops_per_byte": cd["flops_per_byte"],
+                "achieved_tflops": cd["achieved_tflops"], "frac_of_flop_peak": cd["frac_of_flop_peak"]}
+    else:
+        roof = {"bound": cd["bound"], "achieved": cd["achieved_tflops"], "peak": BOUND_OF[dom][1] / 1e12,
+                "unit": "TFLOP/s", "frac": cd["frac"], "alg_flops_per_launch": d["alg_flops"] / per_launch,
+                "per_unit": PER_UNIT["eigh" if dom.startswith("eigh") else dom]}
+    roof.update({"traffic": traffic, "kernel_class": dom, "launches": d["launches"], "avg_ms": cd["avg_ms"],
+                 "share_of_gpu_time": cd["share"]})
     if traffic is not None:
         roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 PMC, " + TRAFFIC["profile"] + ")"
         roof["traffic_rate_tbs"] = traffic / (roof["avg_ms"] / 1e3) / 1e12

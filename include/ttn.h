@@ -359,11 +359,17 @@ ttn_status ttn_test_move(ttn_ctx* ctx, int32_t rows, int32_t n, int32_t new_pad,
  *                 Cholesky factorisation of rank r and the inverse of its
  *                 r x r triangle (n = the problem size after dropping zero
  *                 rows).
+ * The Gram and contraction classes also ledger algorithmic HBM bytes: every
+ * operand read once and every result written once at the actual dimensions
+ * (complex64 / complex128 tensor elements, FP64 complex Gram entries), i.e.
+ * Gram  es (n0 + n1) r + 16 (n0^2 + n1^2),  contraction  es ((n + k) r + 2 k n)
+ * per side of the move and per diagonal block.
  * The Gram and contraction ledgers track the actual leg dimensions from the
  * last state reset (ttn_init_product, or the start of a run) on: enable
  * profiling before it.  Enabling resets the counters.  ttn_profile_read
  * [sync] returns, for one class, the summed elapsed milliseconds, the number
- * of launches and the ledgered flops (0 for classes without a ledger). */
+ * of launches, the ledgered flops and (alg_bytes may be null) the ledgered
+ * bytes (0 for classes without a ledger). */
 enum {
   TTN_CLASS_CONTRACT = 0,     /* c64/c128 leg contractions (MFMA)           */
   TTN_CLASS_GRAM = 1,         /* FP64 Gram matrices (MFMA)                  */
@@ -376,7 +382,8 @@ enum {
   TTN_NCLASS = 8
 };
 ttn_status ttn_profile_enable(ttn_ctx* ctx, int32_t on);
-ttn_status ttn_profile_read(ttn_ctx* ctx, int32_t cls, double* ms, int64_t* launches, double* alg_flops);
+ttn_status ttn_profile_read(ttn_ctx* ctx, int32_t cls, double* ms, int64_t* launches, double* alg_flops,
+                            double* alg_bytes);
 
 /* Tile-shape tuner for the batched contractions and Gram matrices (no
  * passage of the paper: launch tuning of this library).  Every such launch

@@ -83,7 +83,7 @@ def lib() -> C.CDLL:
         "ttn_test_leg_apply": (i32, [vp, i32, vp, i32, vp, i64, vp, i64, i32, vp, i64]),
         "ttn_test_gram": (i32, [vp, i32, vp, i32, vp, i64, vp, i64, i32]),
         "ttn_profile_enable": (i32, [vp, i32]),
-        "ttn_profile_read": (i32, [vp, i32, C.POINTER(dbl), C.POINTER(i64), C.POINTER(dbl)]),
+        "ttn_profile_read": (i32, [vp, i32, C.POINTER(dbl), C.POINTER(i64), C.POINTER(dbl), C.POINTER(dbl)]),
         "ttn_autotune": (i32, [vp, i32, C.POINTER(i64), C.POINTER(i64)]),
         "ttn_test_eigh": (i32, [vp, i32, i32, i32, i32, dbl, vp, i64, vp, vp, i64, vp, vp, i32]),
         "ttn_test_move": (i32, [vp, i32, i32, i32, i32, dbl, vp, i64, vp, vp, i64, vp, i32]),

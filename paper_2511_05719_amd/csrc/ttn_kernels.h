@@ -213,6 +213,12 @@ struct LedgerHop {
   int x, lx, y, ly;     // centre moved from x (leg lx) to y (leg ly)
   double* gram_acc;     // [B]
   double* contract_acc; // [B]
+  // algorithmic HBM bytes of the same launches (each operand read once, each
+  // result written once, at the actual dimensions): es bytes per tensor
+  // element, 16 per FP64 complex Gram entry
+  double* gram_bytes;   // [B]
+  double* contract_bytes; // [B]
+  int es;
 };
 hipError_t launch_ledger_hop(const LedgerHop& d, int batch, hipStream_t st);
 hipError_t launch_ledger_double(int* adim, int L, int node, int l0, int l1, int batch, hipStream_t st);

@@ -428,6 +428,11 @@ __global__ void k_ledger_hop(LedgerHop d, int batch) {
   const double na0 = nk[0], k0 = nk[1], na1 = nk[2], k1 = nk[3];
   d.gram_acc[t] += 8.0 * (na0 * na0 + na1 * na1) * rx;
   d.contract_acc[t] += 8.0 * (k0 * na0 + k1 * na1) * (rx + ry);
+  // Gram: the node's rows of the bond read once, G written once (FP64
+  // complex); contraction, per diagonal block and per side: the node block,
+  // the factor block and the result
+  d.gram_bytes[t] += d.es * (na0 + na1) * rx + 16.0 * (na0 * na0 + na1 * na1);
+  d.contract_bytes[t] += d.es * ((na0 + k0 + na1 + k1) * (rx + ry) + 2.0 * (k0 * na0 + k1 * na1));
   ax[d.lx] = nk[1] + nk[3];
   ay[d.ly] = nk[1] + nk[3];
 }

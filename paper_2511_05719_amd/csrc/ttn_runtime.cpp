@@ -157,7 +157,9 @@ struct ttn_ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[TTN_NCLASS];
   size_t prof_used[TTN_NCLASS] = {0};
   double* ledger[TTN_NCLASS] = {nullptr};   // device [B] algorithmic flops per class (or null)
-  double* ledger_mem = nullptr;             // [5][B]: eigh small, eigh large, Gram, contraction, move
+  double* ledger_bytes[TTN_NCLASS] = {nullptr};   // device [B] algorithmic HBM bytes (Gram, contraction)
+  double* ledger_mem = nullptr;             // [7][B]: flops of eigh small, eigh large, Gram, contraction,
+                                            // move; bytes of Gram, contraction
   int* adim = nullptr;                      // [B][L][3] actual leg dimensions (profiling)
   int* nk = nullptr;                        // [B][4] eigensolver counts of the last move
   int* nk_max = nullptr;                    // [4] their maxima over rows (device)
@@ -682,6 +684,9 @@ static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int ne
     lh.x = x; lh.lx = lx; lh.y = y; lh.ly = ly;
     lh.gram_acc = ctx->ledger[CLS_GRAM];
     lh.contract_acc = ctx->ledger[CLS_GEMM];
+    lh.gram_bytes = ctx->ledger_bytes[CLS_GRAM];
+    lh.contract_bytes = ctx->ledger_bytes[CLS_GEMM];
+    lh.es = (int)ctx->es;
     TTN_CHECK_HIP(launch_ledger_hop(lh, ctx->B, ctx->st));
   }
   return TTN_OK;
@@ -1184,7 +1189,7 @@ ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {
   ok &= hipMalloc((void**)&ctx->rank_table, Bz * L * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->ext, Bz * L * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->rank_max, Bz * L * sizeof(int)) == hipSuccess;
-  ok &= hipMalloc((void**)&ctx->ledger_mem, 5 * Bz * sizeof(double)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->ledger_mem, 7 * Bz * sizeof(double)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->adim, Bz * L * 3 * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->nk, Bz * 4 * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->nk_max, 4 * sizeof(int)) == hipSuccess;
@@ -1196,7 +1201,9 @@ ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {
     ctx->ledger[CLS_GRAM] = ctx->ledger_mem + 2 * Bz;
     ctx->ledger[CLS_GEMM] = ctx->ledger_mem + 3 * Bz;
     ctx->ledger[CLS_MOVE] = ctx->ledger_mem + 4 * Bz;
-    ok &= launch_fill_f64(ctx->ledger_mem, 0.0, 5ll * ctx->B, ctx->st) == hipSuccess;
+    ctx->ledger_bytes[CLS_GRAM] = ctx->ledger_mem + 5 * Bz;
+    ctx->ledger_bytes[CLS_GEMM] = ctx->ledger_mem + 6 * Bz;
+    ok &= launch_fill_f64(ctx->ledger_mem, 0.0, 7ll * ctx->B, ctx->st) == hipSuccess;
   }
   ok &= hipMalloc((void**)&ctx->disc_acc, Bz * sizeof(double)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->flags, Bz * sizeof(int)) == hipSuccess;
@@ -2102,11 +2109,12 @@ ttn_status ttn_profile_enable(ttn_ctx* ctx, int32_t on) {
   TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
   ctx->prof = on != 0;
   for (int c = 0; c < TTN_NCLASS; ++c) ctx->prof_used[c] = 0;
-  TTN_CHECK_HIP(launch_fill_f64(ctx->ledger_mem, 0.0, 5ll * ctx->B, ctx->st));
+  TTN_CHECK_HIP(launch_fill_f64(ctx->ledger_mem, 0.0, 7ll * ctx->B, ctx->st));
   return TTN_OK;
 }
 
-ttn_status ttn_profile_read(ttn_ctx* ctx, int32_t cls, double* ms, int64_t* launches, double* alg_flops) {
+ttn_status ttn_profile_read(ttn_ctx* ctx, int32_t cls, double* ms, int64_t* launches, double* alg_flops,
+                            double* alg_bytes) {
   if (!ctx) return TTN_EINVAL;
   if (cls < 0 || cls >= TTN_NCLASS || !ms || !launches || !alg_flops) return fail(ctx, TTN_EINVAL, "bad class");
   TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
@@ -2123,6 +2131,14 @@ ttn_status ttn_profile_read(ttn_ctx* ctx, int32_t cls, double* ms, int64_t* laun
     std::vector<double> f(ctx->B);
     TTN_CHECK_HIP(hipMemcpy(f.data(), ctx->ledger[cls], ctx->B * sizeof(double), hipMemcpyDeviceToHost));
     for (double v : f) *alg_flops += v;
+  }
+  if (alg_bytes) {
+    *alg_bytes = 0.0;
+    if (ctx->ledger_bytes[cls]) {
+      std::vector<double> f(ctx->B);
+      TTN_CHECK_HIP(hipMemcpy(f.data(), ctx->ledger_bytes[cls], ctx->B * sizeof(double), hipMemcpyDeviceToHost));
+      for (double v : f) *alg_bytes += v;
+    }
   }
   return TTN_OK;
 }

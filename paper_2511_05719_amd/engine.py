@@ -259,9 +259,10 @@ class TTNEngine:
     def profile_read(self) -> dict:
         out = {}
         for name, cls in _abi.CLASSES.items():
-            ms, n, fl = C.c_double(), C.c_int64(), C.c_double()
-            check(lib().ttn_profile_read(self._ctx, cls, C.byref(ms), C.byref(n), C.byref(fl)), self._ctx)
-            out[name] = {"ms": ms.value, "launches": n.value, "alg_flops": fl.value}
+            ms, n, fl, by = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
+            check(lib().ttn_profile_read(self._ctx, cls, C.byref(ms), C.byref(n), C.byref(fl), C.byref(by)),
+                  self._ctx)
+            out[name] = {"ms": ms.value, "launches": n.value, "alg_flops": fl.value, "alg_bytes": by.value}
         return out
 
     # ------------------------------------------------------------ exports ----
