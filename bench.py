@@ -190,6 +190,32 @@ def run_layout_leg(args, layout, batch):
             "max_rank": st.get("max_rank"), "note": "the timed step includes filling the statistics"}
 
 
+def run_graph_leg(args, circ, batch):
+    """The same workload in the two other run modes of the batch driver: static
+    shapes (no host read per centre move) eagerly, and the whole op list
+    captured once into a HIP graph and replayed; one untimed call each
+    (the graph mode's captures), then one timed call, against the dynamic mode."""
+    import torch
+    from paper_2511_05719_amd import TTNEngine
+    th = torch.as_tensor(theta_rows(circ, batch, 0), device="cuda")
+    eng = TTNEngine(circ.n_qubits, batch, circ.leaf_of_qubit, chi_max=64, cutoff=1e-10, dtype="c64",
+                    seed=args.seed)
+    ol = eng.upload(circ)
+    out = eng.outputs(ol)
+    res = {"batch": batch}
+    for mode in ("dynamic", "static", "graph"):
+        eng.run_mode(mode)
+        eng.run_circuit(ol, theta=th, traj_offset=0, out=out, stats=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eng.run_circuit(ol, theta=th, traj_offset=batch, out=out, stats=False)
+        torch.cuda.synchronize()
+        res[mode + "_shots_per_s"] = batch / (time.perf_counter() - t0)
+    res["graph_captures"], res["graph_replays"] = eng.run_mode("graph")
+    eng.close()
+    return res
+
+
 def run_gradient(args):
     """log P and its adjoint gradient for records of the differentiation
     workload (d=5, 3 rounds, SRX theta = 0.1 and AD gamma = 5e-3 at every
@@ -372,7 +398,7 @@ def main():
     circ = build_circuit(5, args.rounds, "srx", leaf_of_qubit=lay)
     ops = ops_per_shot(circ)
     # the batched run gets the budget minus what the legs after it need
-    legs_s = (0 if args.no_plain else 25) + (0 if args.no_cpu else 40) + (0 if args.no_extra else 60)
+    legs_s = (0 if args.no_plain else 25) + (0 if args.no_cpu else 40) + (0 if args.no_extra else 80)
     budget_end = args.budget - legs_s
     log(f"workload built ({args.layout} layout); batched run until {budget_end:.0f} s")
 
@@ -442,7 +468,7 @@ def main():
                          f"timed as the difference of two runs from the start ({wall:.1f} s of CPU work)",
                "host_cpu": model, "host_nproc": nproc}
         log(f"cpu oracle: {rate:.3f} trajectory-gates/s")
-    other = grad = None
+    other = grad = graph = None
     if not args.no_extra:
         if elapsed() < args.budget - 45:
             other = run_layout_leg(args, "default" if args.layout == "optimized" else "optimized", 1024)
@@ -450,6 +476,9 @@ def main():
         if elapsed() < args.budget - 15:
             grad = run_gradient(args)
             log(f"gradient: {grad['records_per_s']:.1f} records/s")
+        if elapsed() < args.budget - 20:
+            graph = run_graph_leg(args, circ, 256)
+            log(f"run modes at B=256: {graph}")
 
     out = {
         "metric": METRIC,
@@ -482,6 +511,7 @@ def main():
         "p_fail_by_theta": pf,
         "other_layout": other,
         "log_prob_grad": grad,
+        "run_modes": graph,
         "run_stats": {"max_rank": st.get("max_rank"),
                       "mean_discarded_weight": (st["discarded_weight"] / args.batch
                                                 if "discarded_weight" in st else None),

@@ -199,6 +199,30 @@ ttn_status ttn_batch_run_circuit(ttn_ctx* ctx, const ttn_oplist* ol, const doubl
                                  const double* gamma, int64_t params_stride, uint64_t traj_offset,
                                  uint8_t* records, int8_t* branches, double* logp, ttn_stats* st);
 
+/* Launch mode of ttn_batch_run_circuit (no passage of the paper: how the
+ * library issues the work of Sec. III.C's trajectories).
+ *  TTN_RUN_DYNAMIC (default): after each centre move the host reads the
+ *    batch's largest kept count and pads the new bond to it (one small
+ *    device-to-host read per move; shapes follow the batch's ranks).
+ *  TTN_RUN_STATIC: no host read; every bond keeps its static padded bound
+ *    (chi_max or the bond's physical bound, doubled while a controlled gate
+ *    rides on it); each row's kept values are a prefix and the rest is zero,
+ *    so results agree with the dynamic mode up to floating-point summation
+ *    order (tile shapes follow the padded dimensions).  Launch shapes depend
+ *    only on the op list.
+ *  TTN_RUN_GRAPH: static shapes, and the whole op list is captured once into
+ *    a HIP graph per (op list, argument buffers, probability trace) on a
+ *    stream the context owns and replayed on later calls, ordered after the
+ *    context's stream by events; the first call with new buffers runs eagerly
+ *    and captures, later calls write the trajectory offset to device memory
+ *    and launch the graph (bit-identical to TTN_RUN_STATIC).  Profiling is
+ *    unavailable in this mode (TTN_EINVAL).
+ * Changing the mode waits for the stream and drops a captured graph.
+ * captures / replays (may be null) receive the graph counts so far.
+ * Errors: TTN_EINVAL for an unknown mode. */
+enum { TTN_RUN_DYNAMIC = 0, TTN_RUN_STATIC = 1, TTN_RUN_GRAPH = 2 };
+ttn_status ttn_set_run_mode(ttn_ctx* ctx, int32_t mode, int64_t* captures, int64_t* replays);
+
 /* log P(record) of given records and Kraus branches: the probability of one
  * trajectory of Sec. III.C, i.e. the product of the Born probabilities of its
  * measurement outcomes and the jump / no-jump probabilities of its Kraus

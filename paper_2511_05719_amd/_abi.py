@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(_HERE, "libttn.so")
 TTN_OK, TTN_EINVAL, TTN_ENOMEM, TTN_EDEVICE, TTN_ENONFINITE, TTN_EPROB = 0, -1, -2, -3, -4, -5
 TTN_C64, TTN_C128 = 0, 1
 TTN_AD_KRAUS, TTN_AD_TROTTER = 0, 1
+TTN_RUN_DYNAMIC, TTN_RUN_STATIC, TTN_RUN_GRAPH = 0, 1, 2
 TTN_DECODE_STATIC_MAX_CHECKS = 16
 STATUS_NAMES = {0: "TTN_OK", -1: "TTN_EINVAL", -2: "TTN_ENOMEM", -3: "TTN_EDEVICE",
                 -4: "TTN_ENONFINITE", -5: "TTN_EPROB"}
@@ -17,7 +18,7 @@ STATUS_NAMES = {0: "TTN_OK", -1: "TTN_EINVAL", -2: "TTN_ENOMEM", -3: "TTN_EDEVIC
 # every symbol the header declares
 SYMBOLS = ("ttn_create", "ttn_destroy", "ttn_last_error", "ttn_init_product", "ttn_apply_1q",
            "ttn_apply_2q", "ttn_measure_project", "ttn_kraus_jump", "ttn_oplist_upload",
-           "ttn_oplist_free", "ttn_batch_run_circuit", "ttn_log_prob", "ttn_log_prob_grad", "ttn_trace_probs",
+           "ttn_oplist_free", "ttn_batch_run_circuit", "ttn_set_run_mode", "ttn_log_prob", "ttn_log_prob_grad", "ttn_trace_probs",
            "ttn_decode", "ttn_decode_static",
            "ttn_compress",
            "ttn_to_statevector", "ttn_bond_dims", "ttn_uniforms", "ttn_philox_uniform_host",
@@ -70,6 +71,7 @@ def lib() -> C.CDLL:
         "ttn_oplist_free": (i32, [vp]),
         "ttn_batch_run_circuit": (i32, [vp, vp, vp, vp, i64, u64, vp, vp, vp, C.POINTER(Stats)]),
         "ttn_log_prob": (i32, [vp, vp, vp, vp, vp, vp, i64, vp, C.POINTER(Stats)]),
+        "ttn_set_run_mode": (i32, [vp, i32, C.POINTER(i64), C.POINTER(i64)]),
         "ttn_log_prob_grad": (i32, [vp, vp, vp, vp, vp, vp, i64, vp, vp, vp, C.POINTER(Stats)]),
         "ttn_trace_probs": (i32, [vp, vp, i64]),
         "ttn_decode": (i32, [vp, vp, i32, vp, i32, vp, i32, vp]),

@@ -1580,21 +1580,36 @@ int eigh_padded_size(int n) {
   return N;
 }
 
+// Kernel attributes and the coset sweep plans of the current device, set up
+// before the first launch (and before any graph capture, which may not copy
+// to constant memory)
+hipError_t eigh_prepare() {
+  if (!g_attr_done) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_jacobi<true, kThreadsSmall, double2, 128>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_jacobi<true, kThreadsSmall, float2, 128>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_jacobi<false, kThreadsLarge, double2, 128>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_jacobi_coset<128>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              140 * 1024);
+    if (e != hipSuccess) return e;
+    g_attr_done = true;
+  }
+  return upload_plans();
+}
+
 hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st) {
   if (batch <= 0) return hipSuccess;
   const int nb = d.blocks > 1 ? 2 : 1;
   if (d.n < 1 || d.n > 256 || d.new_pad < 1 || (nb == 2 && ((d.n & 1) || (d.new_pad & 1))))
     return hipErrorInvalidValue;
   if (!g_attr_done) {
-    hipFuncSetAttribute((const void*)k_jacobi<true, kThreadsSmall, double2, 128>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
-    hipFuncSetAttribute((const void*)k_jacobi<true, kThreadsSmall, float2, 128>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
-    hipFuncSetAttribute((const void*)k_jacobi<false, kThreadsLarge, double2, 128>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
-    hipFuncSetAttribute((const void*)k_jacobi_coset<128>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        140 * 1024);
-    g_attr_done = true;
+    hipError_t e = eigh_prepare();
+    if (e != hipSuccess) return e;
   }
   const int nsub = d.n / nb;
   const int n2 = nsub + (nsub & 1);

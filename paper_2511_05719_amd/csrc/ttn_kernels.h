@@ -99,6 +99,8 @@ struct EighDesc {
   hipEvent_t ev_fork, ev_join;
 };
 hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st);
+// one-time set-up of the eigensolver kernels on the current device (idempotent)
+hipError_t eigh_prepare();
 // Exact (non-truncating) centre-move factors by pivoted Cholesky of G, same
 // outputs as launch_eigh (rank = pivots above cutoff x trace, at most cap);
 // problems of size <= 64 (per block)
@@ -158,6 +160,7 @@ struct LeafBatch {
   int* flags;
   uint64_t seed;
   uint64_t traj_offset;
+  const uint64_t* traj_offset_dev;   // if set, the offset is read from device memory (graph replays)
   int adjoint;         // 1: apply each op's adjoint (SRX, INIT, CNOT, forced MEAS and
                        //    KRAUS_AD), rescaled to unit norm; no log P, records or branches
 };
@@ -194,6 +197,7 @@ struct InitDesc {
 hipError_t launch_init_product(const InitDesc& d, int batch, hipStream_t st);
 hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t st);
 hipError_t launch_fill_f64(double* p, double value, long long n, hipStream_t st);
+hipError_t launch_fill_u64(uint64_t* p, uint64_t value, long long n, hipStream_t st);
 // n complex ones (complex64 or complex128)
 hipError_t launch_fill_cone(void* p, int c128, long long n, hipStream_t st);
 

@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(256) k_leaf_ops(LeafBatch b) {
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= b.n_rows) return;
   const double r2 = 0.70710678118654752440;
-  const uint64_t traj = b.traj_offset + (uint64_t)row;
+  const uint64_t traj = (b.traj_offset_dev ? *b.traj_offset_dev : b.traj_offset) + (uint64_t)row;
   for (int k = 0; k < b.n_ops; ++k) {
     const LeafOp op = b.ops[k];
     const int U = b.node_u[k];
@@ -523,6 +523,15 @@ __global__ void k_fill_i32(int* p, int v, long long n) {
 __global__ void k_fill_f64(double* p, double v, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
+}
+__global__ void k_fill_u64(uint64_t* p, uint64_t v, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+hipError_t launch_fill_u64(uint64_t* p, uint64_t value, long long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, value, n);
+  return hipGetLastError();
 }
 hipError_t launch_fill_i32(int* p, int value, long long n, hipStream_t st) {
   if (n <= 0) return hipSuccess;

@@ -177,6 +177,18 @@ struct ttn_ctx {
   hipStream_t st_aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   ttn_ctx* adj = nullptr;      // twin context holding the adjoint state (created on first use)
+  // run modes (ttn_set_run_mode): dynamic shapes with one host read per move,
+  // or static shapes (bonds padded to their static bounds, no host read),
+  // eager or captured once into a HIP graph and replayed
+  int run_mode = TTN_RUN_DYNAMIC;
+  bool capturing = false;
+  uint64_t* d_traj = nullptr;  // device copy of the trajectory offset of static-shape runs
+  hipStream_t st_graph = nullptr;               // capture / replay stream (created on first use)
+  hipEvent_t ev_gin = nullptr, ev_gout = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::array<uintptr_t, 8> graph_key{};
+  int64_t graph_captures = 0, graph_replays = 0;
   double gemm_flops = 0.0, gram_flops = 0.0;
   std::string err;
 };
@@ -427,7 +439,7 @@ static ttn_status run_gemm(ttn_ctx* ctx, const GemmDesc& g, int kind) {
                                          g.a_m_fast, g.b_n_fast, g.conjA, g.conjB, g.ext != nullptr, ctx->B};
   auto it = ctx->tune.find(key);
   int cfg = it != ctx->tune.end() ? it->second : -1;
-  if (cfg < 0 && ctx->tune_on) {
+  if (cfg < 0 && ctx->tune_on && !ctx->capturing) {
     if (!ctx->tune_ev[0]) {
       TTN_CHECK_HIP(hipEventCreate(&ctx->tune_ev[0]));
       TTN_CHECK_HIP(hipEventCreate(&ctx->tune_ev[1]));
@@ -583,6 +595,9 @@ static void eigh_ws(const ttn_ctx* ctx, EighDesc& ed) {
   ed.lam_sorted = ctx->lam_sorted; ed.order = ctx->order; ed.kept = ctx->kept;
   ed.scale_abs = ctx->scale_abs; ed.nsteps = ctx->nsteps; ed.gpk = ctx->gpk;
   ed.aux_stream = ctx->st_aux; ed.ev_fork = ctx->ev_fork; ed.ev_join = ctx->ev_join;
+  if (ctx->capturing) {        // one stream inside a captured graph
+    ed.aux_stream = nullptr; ed.ev_fork = nullptr; ed.ev_join = nullptr;
+  }
 }
 
 // Move the isometry centre from x to its neighbour y (Sec. III.B: the
@@ -646,7 +661,14 @@ static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int ne
     TTN_CHECK_HIP(launch_eigh(ed, ctx->B, ctx->st));
   }
   int kb[2];
-  TTN_TRY(read_kept(ctx, kb));
+  if (ctx->run_mode == TTN_RUN_DYNAMIC) {
+    TTN_TRY(read_kept(ctx, kb));
+  } else {
+    // static shapes: the new bond keeps its padded bound (each row's kept
+    // values are a prefix, the rest of the factor rows are zero)
+    kb[0] = blocks > 1 ? new_pad / 2 : new_pad;
+    kb[1] = blocks > 1 ? new_pad / 2 : 0;
+  }
   if (kb[0] < 0 || kb[1] < 0 || kb[0] + kb[1] > new_pad || (blocks > 1 && std::max(kb[0], kb[1]) > new_pad / 2))
     return fail(ctx, TTN_EDEVICE, "internal: kept count out of range");
   int newd = blocks > 1 ? kb[0] + kb[1] : kb[0];
@@ -986,6 +1008,7 @@ static void setup_run(ttn_ctx* ctx, const ttn_oplist* ol, const double* theta, c
   r.forced_br = forced_br; r.forced_br_stride = ol->n_ad;
   r.logp = logp;
   r.traj_offset = traj_offset;
+  r.traj_offset_dev = ctx->run_mode != TTN_RUN_DYNAMIC ? ctx->d_traj : nullptr;
   r.adjoint = adjoint;
 }
 
@@ -1050,6 +1073,8 @@ static ttn_status run_oplist(ttn_ctx* ctx, const ttn_oplist* ol, const double* t
   ctx->hops = 0; ctx->launches = 0; ctx->block_hops = 0; ctx->gemm_flops = 0.0; ctx->gram_flops = 0.0;
   TTN_TRY(reset_state(ctx, nullptr));
   TTN_CHECK_HIP(launch_fill_f64(logp, 0.0, ctx->B, ctx->st));
+  if (ctx->run_mode != TTN_RUN_DYNAMIC && !ctx->capturing)
+    TTN_CHECK_HIP(launch_fill_u64(ctx->d_traj, traj_offset, 1, ctx->st));
   setup_run(ctx, ol, theta, gamma, pstride, traj_offset, records, branches, logp, forced_rec, forced_br, 0);
   for (int k = 0; k < ol->n_ops; ++k) TTN_TRY(exec_op(ctx, ol, k));
   TTN_TRY(flush_leaf(ctx));
@@ -1194,6 +1219,7 @@ ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {
   ok &= hipMalloc((void**)&ctx->nk, Bz * 4 * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->nk_max, 4 * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->gate4, 32 * sizeof(double)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->d_traj, sizeof(uint64_t)) == hipSuccess;
   ok &= hipHostMalloc((void**)&ctx->nk_host, 4 * sizeof(int), hipHostMallocDefault) == hipSuccess;
   if (ok) {
     ctx->ledger[CLS_EIGH_SMALL] = ctx->ledger_mem;
@@ -1214,6 +1240,7 @@ ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {
     if (scratch_for_current_device(&sp) != hipSuccess) return bail(TTN_EDEVICE);
     ctx->scratch_dev = (uint8_t*)sp;
   }
+  if (eigh_prepare() != hipSuccess) return bail(TTN_EDEVICE);
   if (reset_state(ctx, nullptr) != TTN_OK) return bail(TTN_EDEVICE);
   if (hipStreamSynchronize(ctx->st) != hipSuccess) return bail(TTN_EDEVICE);
   *out = ctx;
@@ -1233,6 +1260,14 @@ ttn_status ttn_destroy(ttn_ctx* ctx) {
   }
   if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
+  if (ctx->graph_exec) hipGraphExecDestroy(ctx->graph_exec);
+  if (ctx->graph) hipGraphDestroy(ctx->graph);
+  if (ctx->st_graph) {
+    hipStreamSynchronize(ctx->st_graph);
+    hipStreamDestroy(ctx->st_graph);
+  }
+  if (ctx->ev_gin) hipEventDestroy(ctx->ev_gin);
+  if (ctx->ev_gout) hipEventDestroy(ctx->ev_gout);
   for (int c = 0; c < TTN_NCLASS; ++c)
     for (auto& e : ctx->prof_ev[c]) {
       hipEventDestroy(e.first);
@@ -1240,7 +1275,7 @@ ttn_status ttn_destroy(ttn_ctx* ctx) {
     }
   void* ws[] = {ctx->G, ctx->Wi, ctx->Wa, ctx->rot_log, ctx->gpk, ctx->lam_sorted, ctx->order, ctx->kept,
                 ctx->scale_abs, ctx->nsteps, ctx->rank_table, ctx->ext, ctx->rank_max, ctx->ledger_mem,
-                ctx->adim, ctx->nk, ctx->nk_max, ctx->gate4,
+                ctx->adim, ctx->nk, ctx->nk_max, ctx->gate4, ctx->d_traj,
                 ctx->disc_acc, ctx->flags,
                 ctx->degen_acc, ctx->leader, ctx->dec_datarec, ctx->dec_masks};
   for (void* p : ws)
@@ -1426,15 +1461,111 @@ ttn_status ttn_oplist_free(ttn_oplist* ol) {
   return TTN_OK;
 }
 
+// Graph mode: the op list is captured once per (op list, argument buffers)
+// on the context's own capture stream (a graph cannot be captured on the
+// default stream) and launched there, ordered after the caller's stream by
+// events; the trajectory offset is the only argument that changes between
+// launches, and it lives in device memory (ctx->d_traj), written before
+// each launch.  Capturing executes nothing, so the host's record of the
+// node buffers after the capture is that of the graph's end state, which
+// every launch reproduces.  (The eigensolver's one-time set-up, which may
+// not be captured, runs at context creation.)
+static ttn_status graph_run(ttn_ctx* ctx, const ttn_oplist* ol, const double* theta, const double* gamma,
+                            int64_t pstride, uint64_t traj_offset, uint8_t* records, int8_t* branches,
+                            double* logp, ttn_stats* st) {
+  if (ctx->prof) return fail(ctx, TTN_EINVAL, "profiling is not available in graph mode");
+  if (!ol || ol->ctx != ctx) return fail(ctx, TTN_EINVAL, "op list belongs to another context");
+  if (!ctx->st_graph) {
+    TTN_CHECK_HIP(hipStreamCreateWithFlags(&ctx->st_graph, hipStreamNonBlocking));
+    TTN_CHECK_HIP(hipEventCreateWithFlags(&ctx->ev_gin, hipEventDisableTiming));
+    TTN_CHECK_HIP(hipEventCreateWithFlags(&ctx->ev_gout, hipEventDisableTiming));
+  }
+  const std::array<uintptr_t, 8> key = {(uintptr_t)ol, (uintptr_t)theta, (uintptr_t)gamma, (uintptr_t)pstride,
+                                        (uintptr_t)records, (uintptr_t)branches, (uintptr_t)logp,
+                                        (uintptr_t)ctx->trace};
+  TTN_TRY(flush_leaf(ctx));   // pending single-qubit ops, on the caller's stream
+  hipStream_t caller = ctx->st;
+  TTN_CHECK_HIP(hipEventRecord(ctx->ev_gin, caller));
+  TTN_CHECK_HIP(hipStreamWaitEvent(ctx->st_graph, ctx->ev_gin, 0));
+  ttn_status s = TTN_OK;
+  ctx->st = ctx->st_graph;
+  if (!ctx->graph_exec || key != ctx->graph_key) {
+    if (ctx->graph_exec) hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) hipGraphDestroy(ctx->graph);
+    ctx->graph_exec = nullptr;
+    ctx->graph = nullptr;
+    {
+      hipError_t e = hipStreamBeginCapture(ctx->st, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) {
+        s = fail(ctx, TTN_EDEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+      } else {
+        ctx->capturing = true;
+        const ttn_status sc = run_oplist(ctx, ol, theta, gamma, pstride, traj_offset, records, branches, logp,
+                                         nullptr, nullptr, nullptr);
+        ctx->capturing = false;
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(ctx->st, &g);
+        if (sc != TTN_OK) {
+          s = sc;
+        } else if (e != hipSuccess || !g) {
+          s = fail(ctx, TTN_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        } else {
+          ctx->graph = g;
+          e = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
+          if (e != hipSuccess) {
+            ctx->graph_exec = nullptr;
+            s = fail(ctx, TTN_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+          } else {
+            ctx->graph_key = key;
+            ++ctx->graph_captures;
+          }
+        }
+        if (s != TTN_OK && g && !ctx->graph) hipGraphDestroy(g);
+      }
+    }
+  }
+  if (s == TTN_OK) {
+    hipError_t e = launch_fill_u64(ctx->d_traj, traj_offset, 1, ctx->st);
+    if (e == hipSuccess) e = hipGraphLaunch(ctx->graph_exec, ctx->st);
+    if (e != hipSuccess) s = fail(ctx, TTN_EDEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    else ++ctx->graph_replays;
+  }
+  ctx->st = caller;
+  TTN_CHECK_HIP(hipEventRecord(ctx->ev_gout, ctx->st_graph));
+  TTN_CHECK_HIP(hipStreamWaitEvent(caller, ctx->ev_gout, 0));
+  if (s == TTN_OK && st) TTN_TRY(fill_stats(ctx, st));
+  return s;
+}
+
 ttn_status ttn_batch_run_circuit(ttn_ctx* ctx, const ttn_oplist* ol, const double* theta, const double* gamma,
                                  int64_t params_stride, uint64_t traj_offset, uint8_t* records, int8_t* branches,
                                  double* logp, ttn_stats* st) {
   if (!ctx) return TTN_EINVAL;
   if (params_stride < 0) return fail(ctx, TTN_EINVAL, "negative parameter stride");
-  ttn_status s = run_oplist(ctx, ol, theta, gamma, params_stride, traj_offset, records, branches, logp,
-                            nullptr, nullptr, st);
+  ttn_status s;
+  if (ctx->run_mode == TTN_RUN_GRAPH)
+    s = graph_run(ctx, ol, theta, gamma, params_stride, traj_offset, records, branches, logp, st);
+  else
+    s = run_oplist(ctx, ol, theta, gamma, params_stride, traj_offset, records, branches, logp, nullptr, nullptr, st);
   if (s == TTN_OK && st && st->flagged_rows > 0) return TTN_ENONFINITE;
   return s;
+}
+
+ttn_status ttn_set_run_mode(ttn_ctx* ctx, int32_t mode, int64_t* captures, int64_t* replays) {
+  if (!ctx) return TTN_EINVAL;
+  if (mode < TTN_RUN_DYNAMIC || mode > TTN_RUN_GRAPH) return fail(ctx, TTN_EINVAL, "unknown run mode");
+  TTN_TRY(flush_leaf(ctx));
+  if (ctx->run_mode != mode) {
+    TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
+    if (ctx->graph_exec) hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) hipGraphDestroy(ctx->graph);
+    ctx->graph_exec = nullptr;
+    ctx->graph = nullptr;
+    ctx->run_mode = mode;
+  }
+  if (captures) *captures = ctx->graph_captures;
+  if (replays) *replays = ctx->graph_replays;
+  return TTN_OK;
 }
 
 ttn_status ttn_log_prob(ttn_ctx* ctx, const ttn_oplist* ol, const uint8_t* records, const int8_t* branches,

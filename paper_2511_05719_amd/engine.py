@@ -176,12 +176,18 @@ class TTNEngine:
             raise ValueError("theta and gamma must have the same column count")
         return th, ga, stride
 
+    def outputs(self, ol: OpList) -> tuple:
+        """Record, branch and log P buffers for run_circuit(out=...): a graph
+        captured in "graph" mode is replayed only while the same buffers (and
+        parameter tensors) are passed."""
+        return (torch.zeros(self.batch, max(ol.n_rec, 1), dtype=torch.uint8, device=self.device),
+                torch.zeros(self.batch, max(ol.n_ad, 1), dtype=torch.int8, device=self.device),
+                torch.zeros(self.batch, dtype=torch.float64, device=self.device))
+
     def run_circuit(self, ol: OpList, theta=None, gamma=None, traj_offset: int = 0,
-                    stats: bool = True) -> RunResult:
+                    stats: bool = True, out=None) -> RunResult:
         th, ga, stride = self._params(ol, theta, gamma)
-        rec = torch.zeros(self.batch, max(ol.n_rec, 1), dtype=torch.uint8, device=self.device)
-        br = torch.zeros(self.batch, max(ol.n_ad, 1), dtype=torch.int8, device=self.device)
-        logp = torch.zeros(self.batch, dtype=torch.float64, device=self.device)
+        rec, br, logp = self.outputs(ol) if out is None else out
         st = _abi.Stats()
         code = lib().ttn_batch_run_circuit(self._ctx, ol._h, _ptr(th), _ptr(ga), stride, int(traj_offset),
                                            _ptr(rec), _ptr(br), _ptr(logp), C.byref(st) if stats else None)
@@ -219,6 +225,17 @@ class TTNEngine:
         if code not in (0, _abi.TTN_EPROB):
             check(code, self._ctx)
         return logp, dth[:, :ol.n_loc], dga[:, :ol.n_loc], st.as_dict()
+
+    def run_mode(self, mode: str) -> tuple:
+        """"dynamic" (default), "static" or "graph" (see ttn_set_run_mode).
+        Returns (graph captures, graph replays) so far."""
+        modes = {"dynamic": _abi.TTN_RUN_DYNAMIC, "static": _abi.TTN_RUN_STATIC, "graph": _abi.TTN_RUN_GRAPH}
+        if mode not in modes:
+            raise ValueError(f"run mode must be one of {sorted(modes)}")
+        m = modes[mode]
+        cap, rep = C.c_int64(0), C.c_int64(0)
+        check(lib().ttn_set_run_mode(self._ctx, m, C.byref(cap), C.byref(rep)), self._ctx)
+        return cap.value, rep.value
 
     def trace_probs(self, probs: torch.Tensor | None):
         """Record the probability of every sampled event of later runs into
