@@ -1298,132 +1298,153 @@ __global__ void __launch_bounds__(256) k_jacobi_wave(EighDesc d, long long nprob
 // in the same [new_pad][n] row layout as the eigensolver's, rows >= rank
 // zero.  For moves that keep every value above the cutoff (the forward
 // moves of a controlled gate, plain moves of the centre); truncation to chi
-// stays with the eigensolver.  One workgroup of 256 threads per problem
-// (a row, or one diagonal block of a row), n <= 64 after the compaction.
-template <int NMAX>
-__global__ void __launch_bounds__(256) k_pchol(EighDesc d) {
-  static_assert(NMAX == 64, "one lane per column");
+// stays with the eigensolver.  One workgroup of NW waves per problem (a
+// row, or one diagonal block of a row) of size n <= NMAX (16, 32 or 64 by
+// the uncompacted size, with one, two or four waves).
+//
+// The columns z_a of W_iso come out of the same right-looking sweep: with
+// y_j = e_j - sum_{c<k} R[c][j] z_c for each remaining column j, the pivot p
+// of step k gives z_k = y_p / R_kk, and every remaining y_j loses
+// R[k][j] z_k.  y_j lives on the columns pivoted so far, where row j of the
+// residual is zero, so each row of A holds the residual on the remaining
+// columns and y_j on the pivoted ones, and one update per row and step
+// serves both.  After step k, row p holds R[k][c] on the columns pivoted at
+// step k or later (R_kk on the diagonal) and z_k[c] on those pivoted before.
+//
+// Lane j of every wave holds column j.  Each step costs one barrier: every
+// wave keeps the residual diagonal in a register and picks the pivot itself
+// (a wave maximum of a 32-bit key), reads the pivot row and updates its own
+// share of the remaining rows (i = wave mod NW), in one batch of independent LDS
+// accesses; the pivot row's final values are written by the wave owning that
+// row at the next step, when no wave reads it any more.
+__device__ inline unsigned wave_max_u32(unsigned v) {
+  // quad_perm(1,0,3,2), quad_perm(2,3,0,1), row_half_mirror, row_mirror:
+  // the maximum over each row of 16 lanes, then over the four rows
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+  const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)v, 0), b = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
+  const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)v, 32), e = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+  return max(max(a, b), max(c, e));
+}
+__device__ inline double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ inline double wave_sum_d(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+template <int NMAX, int NW>
+__global__ void __launch_bounds__(64 * NW) k_pchol(EighDesc d) {
+  static_assert(NMAX <= 64 && NMAX % NW == 0 && (NW == 1 || NW == 2 || NW == 4 || NW == 8), "one lane per column");
   constexpr int LD = NMAX + 1;
-  // A: the residual; after step k row order[k] holds row k of R on the
-  // columns pivoted at step k or later, and (after the inverse) X = R11^-1
-  // on the columns pivoted before: X[c][a] (c < a) at A[order[a]][order[c]]
+  constexpr int RPW = NMAX / NW;          // rows per wave
+  constexpr unsigned long long kRows = NW == 8 ? 0x0101010101010101ull : NW == 4 ? 0x1111111111111111ull
+                                     : NW == 2 ? 0x5555555555555555ull : ~0ull;
   __shared__ double2 A[NMAX * LD];
-  __shared__ int cidx[NMAX], inv[NMAX], wcount[4];
+  __shared__ int cidx[64], inv[64], wcount[NW];
   __shared__ int pos[NMAX], order[NMAX];
-  __shared__ double red[256];
-  __shared__ double dmax_s;
-  __shared__ int piv_s;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ double red[2][NW];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // (uniform: scalar row bookkeeping)
   const long long pid = blockIdx.x;
   const Problem pb = problem_of(d, pid);
   const long long t = pb.t;
   const double2* G = d.G + t * (long long)d.n * d.n;
-  const int n = compact_rows<4>(d, G, pb, cidx, inv, wcount);
-  for (int i = wave; i < n; i += 4)
+  // (compaction: one original row per thread, pb.n <= 64 * NW; the
+  // launcher picks NMAX >= pb.n)
+  const int n = compact_rows<NW>(d, G, pb, cidx, inv, wcount);
+  for (int i = wave; i < n; i += NW)
     if (lane < n) A[i * LD + lane] = gram_at(d, G, (long long)(pb.off + cidx[i]) * d.n + pb.off + cidx[lane]);
   if (threadIdx.x < NMAX) pos[threadIdx.x] = -1;
   // trace of the whole matrix (both blocks), and of this problem
   double part = 0.0, own = 0.0;
   for (int i = threadIdx.x; i < d.n; i += blockDim.x) part += gram_at(d, G, (long long)i * d.n + i).x;
   if (threadIdx.x < n) own = gram_at(d, G, (long long)(pb.off + cidx[threadIdx.x]) * d.n + pb.off + cidx[threadIdx.x]).x;
-  red[threadIdx.x] = part;
+  part = wave_sum_d(part);
+  own = wave_sum_d(own);
+  if (lane == 0) { red[0][wave] = part; red[1][wave] = own; }
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double tr = red[0];
-  __syncthreads();
-  red[threadIdx.x] = own;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double mine = red[0];
+  double tr = 0.0, mine = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) { tr += red[0][w]; mine += red[1][w]; }
   const bool finite = isfinite(tr) && tr > 0.0;
   const double tot = d.blocks > 1 ? tr : mine;
   const double tol = d.cutoff * tot;
   const int lim = min(min(d.cap, pb.pad), n);
+  const unsigned long long live = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+  const bool in = lane < n;
+  double dj = in ? A[lane * LD + lane].x : 0.0;         // residual diagonal (every wave alike)
+  unsigned long long piv = 0;                           // pivoted columns
+  double2 prow = make_double2(0.0, 0.0);                // final values of the last pivot row
+  int pprev = -1;
   int k = 0;
   if (finite) {
     for (; k < lim; ++k) {
-      // pivot: the largest remaining diagonal entry (ties: lowest index)
-      if (wave == 0) {
-        double v = (lane < n && pos[lane] < 0) ? A[lane * LD + lane].x : -1.0;
-        int vi = lane;
-        for (int o = 32; o > 0; o >>= 1) {
-          const double ov = __shfl_xor(v, o);
-          const int oi = __shfl_xor(vi, o);
-          if (ov > v || (ov == v && oi < vi)) { v = ov; vi = oi; }
+      if (pprev >= 0 && pprev % NW == wave && in) A[pprev * LD + lane] = prow;
+      // pivot: the largest remaining diagonal entry (a float key with the
+      // lowest index winning near-ties; 0: no column left)
+      const bool before = (piv >> lane) & 1ull;         // pivoted at an earlier step
+      unsigned key = 0;
+      if (in && !before) key = ((__float_as_uint((float)fmax(dj, 0.0)) + 64u) & ~63u) | (unsigned)(63 - lane);
+      key = wave_max_u32(key);
+      if (key == 0u) break;
+      const int p = 63 - (int)(key & 63u);
+      const double dm = readlane_d(dj, p);
+      if (!(dm > tol) || !isfinite(dm)) break;          // (uniform: every wave alike)
+      const double rkk = sqrt(dm);
+      const double irkk = 1.0 / rkk;
+      piv |= 1ull << p;
+      const bool colj = in && !((piv >> lane) & 1ull); // still unpivoted after this step
+      const double2 arow = A[p * LD + lane];
+      // u = row k of R on the remaining columns; z = z_k on the pivoted ones
+      const double2 u = colj ? cscale(arow, irkk) : make_double2(0.0, 0.0);
+      const double2 z = before ? cscale(arow, irkk) : make_double2(lane == p ? irkk : 0.0, 0.0);
+      const double2 w = colj ? u : z;
+      if (colj) dj = fma(-u.x, u.x, fma(-u.y, u.y, dj));
+      // each remaining row j: A_jc -= conj(u_j) u_c (remaining c), y_j -= u_j z_k
+      unsigned long long rows = live & ~piv & (kRows << wave);
+      int ii[RPW];
+#pragma unroll
+      for (int q = 0; q < RPW; ++q) {
+        ii[q] = rows ? __builtin_ctzll(rows) : -1;
+        rows &= rows - 1ull;
+      }
+      double2 v[RPW];
+#pragma unroll
+      for (int q = 0; q < RPW; ++q)
+        if (ii[q] >= 0) v[q] = A[ii[q] * LD + lane];
+#pragma unroll
+      for (int q = 0; q < RPW; ++q)
+        if (ii[q] >= 0) {
+          // u_j from the pivot row as loaded (a cross-lane read of a value
+          // that no per-lane condition defines)
+          const double ujx = readlane_d(arow.x, ii[q]) * irkk;
+          const double ujy0 = readlane_d(arow.y, ii[q]) * irkk;
+          const double ujy = colj ? -ujy0 : ujy0;        // conj on the residual
+          double2 o = lane == p ? make_double2(0.0, 0.0) : v[q];
+          o.x = fma(-ujx, w.x, fma(ujy, w.y, o.x));
+          o.y = fma(-ujx, w.y, fma(-ujy, w.x, o.y));
+          if (in) A[ii[q] * LD + lane] = o;
         }
-        if (lane == 0) { dmax_s = v; piv_s = vi; }
+      if (threadIdx.x == 0) {
+        order[k] = p;
+        pos[p] = k;
       }
-      __syncthreads();
-      const double dm = dmax_s;
-      const int p = piv_s;
-      if (!(dm > tol) || !isfinite(dm)) break;          // (uniform: shared values)
-      // rank-one update of the residual with the unscaled pivot row:
-      // A_ij -= conj(A_pi) A_pj / A_pp  (rows by wave, columns by lane)
-      const double idm = 1.0 / dm;
-      const bool colj = lane < n && lane != p && pos[lane] < 0;
-      const double2 apj = colj ? cscale(A[p * LD + lane], idm) : make_double2(0.0, 0.0);
-      for (int i = wave; i < n; i += 4) {
-        if (i == p || pos[i] >= 0) continue;            // (uniform per wave)
-        const double2 api = cconj(A[p * LD + i]);
-        if (colj) A[i * LD + lane] = csub(A[i * LD + lane], cmul(api, apj));
-      }
-      __syncthreads();
-      // row k of R = row p scaled by 1 / sqrt(A_pp); the pivot leaves the
-      // residual
-      if (wave == 0) {
-        const double rkk = sqrt(dm);
-        if (colj) A[p * LD + lane] = cscale(A[p * LD + lane], 1.0 / rkk);
-        if (lane == 0) {
-          A[p * LD + p] = make_double2(rkk, 0.0);
-          pos[p] = k;
-          order[k] = p;
-        }
-      }
+      prow = colj ? u : (lane == p ? make_double2(rkk, 0.0) : z);
+      pprev = p;
       __syncthreads();
     }
   }
+  if (pprev >= 0 && pprev % NW == wave && in) A[pprev * LD + lane] = prow;
   const int r = k;
-  // R11^-1 by columns: 4 neighbouring lanes per column b (b < r), each
-  // summing a quarter of every dot product; X[a][b] for a = b - 1 .. 0 goes
-  // to A[order[b]][order[a]] (X[b][b] = 1 / R[b][b] is not stored)
-  {
-    const int b = threadIdx.x >> 2, sub = threadIdx.x & 3;
-    const bool act = b < r;
-    const int bb = act ? b : 0;                       // the 4 lanes of a column iterate alike
-    const int rowb = act ? order[b] : 0;
-    for (int a = bb - 1; a >= 0; --a) {
-      double2 s = make_double2(0.0, 0.0);
-      if (act) {
-        const int rowa = order[a];
-        for (int c = a + 1 + sub; c <= b; c += 4) {
-          const double2 xcb = (c == b) ? make_double2(1.0 / A[rowb * LD + rowb].x, 0.0) : A[rowb * LD + order[c]];
-          s = cadd(s, cmul(A[rowa * LD + order[c]], xcb));
-        }
-      }
-      s.x += __shfl_xor(s.x, 1); s.y += __shfl_xor(s.y, 1);
-      s.x += __shfl_xor(s.x, 2); s.y += __shfl_xor(s.y, 2);
-      if (act && sub == 0) A[rowb * LD + order[a]] = cscale(s, -1.0 / A[order[a] * LD + order[a]].x);
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-    }
-  }
-  __syncthreads();
   // kept weight, normalisation, counts
-  double resid = 0.0;
-  if (threadIdx.x < n && pos[threadIdx.x] < 0) resid = fmax(A[threadIdx.x * LD + threadIdx.x].x, 0.0);
-  red[threadIdx.x] = resid;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double kept = fmax(mine - red[0], 0.0);
+  const double resid = wave_sum_d((in && !((piv >> lane) & 1ull)) ? fmax(dj, 0.0) : 0.0);
+  const double kept = fmax(mine - resid, 0.0);
   double scale;
   int kk = r;
   if (d.blocks > 1) {
@@ -1458,6 +1479,7 @@ __global__ void __launch_bounds__(256) k_pchol(EighDesc d) {
     }
     if (d.sweeps_out) d.sweeps_out[t] = 0;
   }
+  __syncthreads();
   // factors: own block rows pad_off + a, columns off + i; zeros in the other
   // block's columns
   const long long base = t * (long long)d.new_pad * d.n;
@@ -1469,11 +1491,12 @@ __global__ void __launch_bounds__(256) k_pchol(EighDesc d) {
     if (a < kk && c >= 0) {
       const int pc = pos[c];
       const int ra = order[a];
-      // R[a][c]: row a of R holds the columns pivoted at step a or later
-      if (pc < 0 || pc >= a) wa = cscale(A[ra * LD + c], scale);
-      // (P R11^-1)[c][a] = X[pos c][a] for a kept pivot c (X upper triangular)
-      if (pc == a) wi = make_double2(1.0 / A[ra * LD + ra].x, 0.0);
-      else if (pc >= 0 && pc < a) wi = A[ra * LD + c];
+      const double2 x = A[ra * LD + c];
+      // R[a][c] on the columns pivoted at step a or later (and never)
+      if (pc < 0 || pc >= a) wa = cscale(x, scale);
+      // (P R11^-1)[c][a] = z_a[c]: 1 / R_aa at the pivot, stored before it
+      if (pc == a) wi = make_double2(1.0 / x.x, 0.0);
+      else if (pc >= 0 && pc < a) wi = x;
     }
     const long long o = base + (long long)(pb.pad_off + a) * d.n + pb.off + i;
     if (d.out_c128) { ((double2*)d.W_iso)[o] = wi; ((double2*)d.W_abs)[o] = wa; }
@@ -1491,7 +1514,11 @@ hipError_t launch_pchol(const EighDesc& d, int batch, hipStream_t st) {
   const int nb = d.blocks > 1 ? 2 : 1;
   if (d.n < 1 || d.new_pad < 1 || (nb == 2 && ((d.n & 1) || (d.new_pad & 1))) || d.n / nb > 64)
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_pchol<64>, dim3((unsigned)((long long)batch * nb)), dim3(256), 0, st, d);
+  const int nsub = d.n / nb;
+  const dim3 grid((unsigned)((long long)batch * nb));
+  if (nsub <= 16) hipLaunchKernelGGL((k_pchol<16, 1>), grid, dim3(64), 0, st, d);
+  else if (nsub <= 32) hipLaunchKernelGGL((k_pchol<32, 2>), grid, dim3(128), 0, st, d);
+  else hipLaunchKernelGGL((k_pchol<64, 4>), grid, dim3(256), 0, st, d);
   return hipGetLastError();
 }
 
