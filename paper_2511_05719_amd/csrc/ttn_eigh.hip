@@ -190,13 +190,15 @@ __device__ void write_factors(const EighDesc& d, const Problem& pb, const VT* V 
 }
 
 // Convergence.  A pair is rotated while |g_pq| > tol sqrt(g_pp g_qq) (and
-// above 0.1 tol of the trace); the solver stops after a sweep that rotated
-// nothing.  With early_stop it also stops after a sweep whose largest rotated
-// ratio |g_pq| / sqrt(g_pp g_qq) stayed below sqrt(tol) / 4: cyclic Jacobi
-// converges quadratically, so the next sweep would typically find nothing
-// above tol, but a rotation between nearly equal diagonal entries moves
-// off-diagonal mass at first order, so this bound on what is left is
-// sqrt(tol) / 4, not tol (used for complex64 runs only).
+// above 0.1 tol of the trace).  After each sweep the whole matrix is
+// checked: the solver stops when no off-diagonal entry passes that test (the
+// next sweep would rotate nothing), or, with early_stop, when none reaches
+// sqrt(tol) / 4 of sqrt(g_pp g_qq) (cyclic Jacobi converges quadratically,
+// so the next sweep would typically leave nothing above tol; complex64 runs
+// only).  The check reads the matrix, not the ratios met at the rotations:
+// a rotation between nearly equal diagonal entries turns by up to 45 degrees
+// however small its own entry, and can carry large entries past the pairs
+// the sweep has already visited.
 // VT: element type of the eigenvector matrix kept in LDS (kVinLds).  Runs
 // whose factors are complex64 accumulate it in complex64, which halves its
 // LDS footprint so that two problems share a CU.
@@ -230,9 +232,6 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
   __shared__ double lam[NMAX];
   __shared__ int order_s[NMAX];
   __shared__ double red[NT];
-  __shared__ double wave_ratio[NT / 64];
-  __shared__ int any_rot;
-  __shared__ double sweep_ratio;
   __shared__ double trace_s;
 
   for (int idx = threadIdx.x; idx < npk; idx += blockDim.x) {
@@ -274,9 +273,6 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
     const int vgroups = NT / h;                 // V update: row groups of h threads
     const int vP = threadIdx.x % h, vr0 = threadIdx.x / h;
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
-      if (threadIdx.x == 0) any_rot = 0;
-      __syncthreads();
-      double my_ratio = 0.0;     // rotation threads: 1 once they rotated a pair at or above the stop ratio
       for (int s = 0; s < n2 - 1; ++s) {
         // -- rotation parameters of the n2/2 pairs (the tests on squares,
         //    one reciprocal square root for |b| and one for c: the serial
@@ -294,7 +290,6 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
           RotT r;
           r.c = 1.0; r.t = make_double2(0.0, 0.0); r.delta = 0.0;
           if (ab2 > tol * tol * ad && ab2 > floor2 && ab2 > 0.0) {
-            if (ab2 >= stop_ratio2 * ad) my_ratio = 1.0;
             const double inv_ab = rsqrt(ab2);
             const double th = 0.5 * (dd - a) * inv_ab;
             const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
@@ -302,7 +297,6 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
             r.c = rsqrt(1.0 + tt * tt);
             r.t = make_double2(tn * b.x, tn * b.y);
             r.delta = tt * (ab2 * inv_ab);
-            any_rot = 1;
             // the pair's own 2x2 diagonal block (no other block of this
             // step touches these three entries)
             Gp[rbp + p] = make_double2(a - r.delta, 0.0);
@@ -379,21 +373,18 @@ __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
         __syncthreads();
       }
       ++sweeps_done;
-      // the rotation threads are the first h <= NMAX / 2 (one or two wavefronts)
-      if (threadIdx.x < NMAX / 2) {
-        double m = my_ratio;
-        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
-        if ((threadIdx.x & 63) == 0) wave_ratio[threadIdx.x >> 6] = m;
+      // converged: no off-diagonal entry left that passes the rotation test
+      // and reaches the stop ratio
+      int big = 0;
+      for (int e = threadIdx.x; e < n2 * n2; e += blockDim.x) {
+        const int i = e / n2, j = e - (e / n2) * n2;
+        if (j <= i) continue;
+        const int rbi = pidx(i, i, n2) - i;
+        const double ad = fabs(Gp[rbi + i].x * Gp[pidx(j, j, n2)].x);
+        const double ab2 = cabs2(Gp[rbi + j]);
+        if (ab2 > tol * tol * ad && ab2 > floor2 && ab2 > 0.0 && ab2 >= stop_ratio2 * ad) big = 1;
       }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        double m = 0.0;
-        for (int w = 0; w * 64 < NMAX / 2 && w < NT / 64; ++w) m = fmax(m, wave_ratio[w]);
-        sweep_ratio = m;
-      }
-      __syncthreads();
-      if (any_rot == 0 || sweep_ratio == 0.0) break;
-      __syncthreads();
+      if (!__syncthreads_or(big)) break;
     }
   }
   // -- eigenvalues, descending order, truncation --
@@ -716,8 +707,6 @@ __global__ void __launch_bounds__(kThreadsCoset) k_jacobi_coset(EighDesc d) {
   __shared__ double lam[NMAX];
   __shared__ int order_s[NMAX];
   __shared__ double wsum[NT / 64];
-  __shared__ int any_big;
-  __shared__ int any_rot;
   __shared__ double trace_s;
 
   for (int idx = threadIdx.x; idx < npk; idx += NT) {
@@ -762,9 +751,7 @@ __global__ void __launch_bounds__(kThreadsCoset) k_jacobi_coset(EighDesc d) {
   constexpr unsigned long long kSign = 0x8000000000000000ull;
   if (n >= 2 && finite) {
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
-      if (threadIdx.x == 0) { any_rot = 0; any_big = 0; }
-      __syncthreads();
-      bool my_big = false;       // coset lanes: rotated a pair at or above the stop ratio this sweep
+      bool my_big = false;       // (the rotations' own stop-ratio flags; convergence is checked below)
       for (int g = 0; g < ngroups; ++g) {
         const unsigned gi = c_plan.grp[kk][g];
         const int ga = gi & 0xff, gbv = (gi >> 8) & 0xff, m = (int)(gi >> 16);
@@ -802,7 +789,6 @@ __global__ void __launch_bounds__(kThreadsCoset) k_jacobi_coset(EighDesc d) {
           if (m > 2)
             act |= coset_matching<2>(B, sig, isig, v, ga ^ gbv, ln, rc, lg + 2 * hN * 3, rq[Q][2], &my_big);
           if (act) {
-            any_rot = 1;
             // (both lanes hold the same block; each stores half of it)
 #define COSET_ST(S, U, CS, CU)                                                                       \
   *reinterpret_cast<double2*>(Gw + coset_off(v16.CS, rb16.CS, v16.CU, rb16.CU)) =                       \
@@ -856,10 +842,18 @@ __global__ void __launch_bounds__(kThreadsCoset) k_jacobi_coset(EighDesc d) {
         __syncthreads();
       }
       ++sweeps_done;
-      if (my_big) any_big = 1;
-      __syncthreads();
-      if (any_rot == 0 || any_big == 0) break;
-      __syncthreads();
+      // converged: no off-diagonal entry left that passes the rotation test
+      // and reaches the stop ratio
+      int big = 0;
+      for (int e = threadIdx.x; e < N * N; e += NT) {
+        const int i = e >> kk, j = e & (N - 1);
+        if (j <= i) continue;
+        const int rbi = pidx(i, i, N) - i;
+        const double ad = fabs(Gp[rbi + i].x * Gp[pidx(j, j, N)].x);
+        const double ab2 = cabs2(Gp[rbi + j]);
+        if (ab2 > tol * tol * ad && ab2 > floor2 && ab2 > 0.0 && ab2 >= stop_ratio2 * ad) big = 1;
+      }
+      if (!__syncthreads_or(big)) break;
     }
   }
   // -- eigenvalues, descending order, truncation --
@@ -1125,10 +1119,7 @@ __global__ void __launch_bounds__(256) k_jacobi_wave(EighDesc d, long long nprob
   const double stop_ratio = d.early_stop ? 0.25 * sqrt(tol) : 0.0;
   if (n2 >= 2 && finite) {
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
-      bool rotated = false;
-      double my_ratio = 0.0;
       for (int s = 0; s < n2 - 1; ++s) {
-        bool mine = false;
         if (lane < h) {
           int p, q;
           pair_of(n2, s, lane, &p, &q);
@@ -1138,7 +1129,6 @@ __global__ void __launch_bounds__(256) k_jacobi_wave(EighDesc d, long long nprob
           Rot r;
           r.c = 1.0; r.s = make_double2(0.0, 0.0); r.delta = 0.0;
           if (ab > tol * sqrt(fabs(a * dd)) && ab > 0.1 * tol * tr && ab > 0.0) {
-            my_ratio = fmax(my_ratio, ab / fmax(sqrt(fabs(a * dd)), 1e-300));
             const double th = (dd - a) / (2.0 * ab);
             const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
             const double c = 1.0 / sqrt(1.0 + tt * tt);
@@ -1146,11 +1136,9 @@ __global__ void __launch_bounds__(256) k_jacobi_wave(EighDesc d, long long nprob
             r.c = c;
             r.s = make_double2(sn * b.x / ab, sn * b.y / ab);
             r.delta = tt * ab;
-            mine = true;
           }
           rots[wave][lane] = r;
         }
-        rotated |= __any(mine);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         // G <- J^H G J over every 2x2 block (P, Q)
@@ -1196,9 +1184,17 @@ __global__ void __launch_bounds__(256) k_jacobi_wave(EighDesc d, long long nprob
         __builtin_amdgcn_wave_barrier();
       }
       ++sweeps_done;
-      double m = my_ratio;
-      for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
-      if (!rotated || m < stop_ratio) break;
+      // converged: no off-diagonal entry left that passes the rotation test
+      // and reaches the stop ratio
+      bool big = false;
+      for (int idx = lane; idx < n2 * n2; idx += 64) {
+        const int i = idx / n2, j = idx - (idx / n2) * n2;
+        if (j <= i) continue;
+        const double ad = fabs(G[i * n2 + i].x * G[j * n2 + j].x);
+        const double ab = sqrt(cabs2(G[idx]));
+        if (ab > tol * sqrt(ad) && ab > 0.1 * tol * tr && ab > 0.0 && ab >= stop_ratio * sqrt(ad)) big = true;
+      }
+      if (!__any(big)) break;
     }
   }
   // eigenvalues, descending order, truncation

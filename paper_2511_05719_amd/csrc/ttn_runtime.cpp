@@ -617,9 +617,12 @@ static ttn_status read_kept(ttn_ctx* ctx, int kb[2]) {
   return TTN_OK;
 }
 
-// exact: the move keeps every value above the cutoff (the cap cannot bind);
-// complex64 contexts then factor by pivoted Cholesky (QR) instead of the
-// eigensolver when the problem fits it (n <= 64 per block).
+// exact: the move keeps every value above the cutoff (the cap cannot bind).
+// Complex64 contexts factor such moves, and truncating moves whose bond is
+// no wider than the cap (only the cutoff can drop values), by pivoted
+// Cholesky (QR) instead of the eigensolver when the problem fits it (n <= 64
+// per block): the bond then keeps a basis of the same kept space rather than
+// the Schmidt basis, which nothing downstream needs.
 static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int new_pad, int blocks = 1,
                       int in_leg = -1, const int* kin = nullptr, const Partner* px = nullptr,
                       const Partner* py = nullptr, bool exact = false) {
@@ -642,7 +645,7 @@ static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int ne
   ed.rank_max = blocks > 1 ? nullptr : ctx->rank_max + e;
   ed.rank_stride = ctx->L;
   const bool large = (n / blocks + ((n / blocks) & 1)) > 64;
-  const bool qr = exact && !ctx->c128 && !large && (blocks > 1 || n <= cap);
+  const bool qr = !ctx->c128 && !large && (blocks > 1 ? exact : n <= cap);
   ed.flops_acc = ctx->ledger[qr ? CLS_MOVE : large ? CLS_EIGH_LARGE : CLS_EIGH_SMALL];
   ed.disc_acc = ctx->disc_acc; ed.flags = ctx->flags; ed.degen_acc = ctx->degen_acc;
   eigh_ws(ctx, ed);
@@ -2353,6 +2356,9 @@ ttn_status ttn_test_eigh(ttn_ctx* ctx, int32_t rows, int32_t n, int32_t new_pad,
   ed.rank_out = blocks == 1 ? rank : nullptr; ed.rank_stride = 1;
   eigh_ws(ctx, ed);
   ed.nk_out = ctx->prof ? ctx->nk : nullptr;
+  // the convergence settings of the batch driver's moves
+  ed.tol = ctx->c128 ? 1e-15 : 1e-10;
+  ed.early_stop = ctx->c128 ? 0 : 1;
   TTN_CHECK_HIP(launch_eigh(ed, rows, ctx->st));
   TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
   return TTN_OK;

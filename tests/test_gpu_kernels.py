@@ -26,6 +26,18 @@ def _host_complex(t):
     return a[..., 0].astype(np.float64) + 1j * a[..., 1].astype(np.float64)
 
 
+def _kept_band(w, cutoff, dtype):
+    # the kept counts a solve may return for normalised eigenvalues w: exact
+    # in complex128; complex64 contexts stop the Jacobi sweeps once every
+    # off-diagonal ratio is below sqrt(1e-10) / 4, which resolves eigenvalues
+    # to ~1e-11 of the trace, so a value within that of the cutoff may fall
+    # either side
+    if dtype == "c128":
+        k = int((w > cutoff).sum())
+        return k, k
+    return int((w > cutoff + 1e-11).sum()), int((w > cutoff - 1e-11).sum())
+
+
 def test_device_uniforms_match_oracle_stream():
     from oracle.rng import uniforms
     eng = _engine()
@@ -128,8 +140,8 @@ def test_eigh_centre_move_factors(dtype, n, rank):
     Wi, Wa, rk = _host_complex(Wi), _host_complex(Wa), rk.cpu().numpy()
     for t in range(rows):
         s = np.linalg.svd(M[t], compute_uv=False)
-        k_ref = int((s ** 2 > cutoff * (s ** 2).sum()).sum())
-        assert rk[t] == k_ref
+        k_lo, k_hi = _kept_band(s ** 2 / (s ** 2).sum(), cutoff, dtype)
+        assert k_lo <= rk[t] <= k_hi
         k = rk[t]
         # c128: components of weight near the cutoff mix across it by
         # ~eps * |G| / gap, i.e. up to ~1e-3 sqrt(cutoff) in amplitude
@@ -210,9 +222,10 @@ def test_eigh_zero_rows_are_compacted(dtype, n, blocks):
             Mb = M[t][:, sl]
             s = np.linalg.svd(Mb, compute_uv=False)
             tot = np.linalg.norm(M[t]) ** 2
-            k = int((s ** 2 > cutoff * tot).sum()) if tot > 0 else 0
+            k_lo, k_hi = _kept_band(s ** 2 / tot, cutoff, dtype) if tot > 0 else (0, 0)
             wi, wa = Wi[t, sl, sl], Wa[t, sl, sl]
-            assert int(np.sum(np.linalg.norm(wa, axis=1) > 0)) == k, (t, b, k)
+            k = int(np.sum(np.linalg.norm(wa, axis=1) > 0))
+            assert k_lo <= k <= k_hi, (t, b, k, k_lo, k_hi)
             if blocks == 1:
                 assert rk[t] == k
             assert np.all(wi[k:] == 0) and np.all(wa[k:] == 0)
@@ -369,18 +382,61 @@ def test_eigh_block_diagonal(dtype, m):
         for b in range(2):
             Mb = Ms[b][t]
             s = np.linalg.svd(Mb, compute_uv=False)
-            k = int((s ** 2 > cutoff).sum())          # the trace is 1
+            k_lo, k_hi = _kept_band(s ** 2, cutoff, dtype)     # the trace is 1
             rws = slice(b * m, (b + 1) * m)
             own = slice(b * m, (b + 1) * m)
             other = slice((1 - b) * m, (2 - b) * m)
             assert np.all(Wi[t, rws, other] == 0) and np.all(Wa[t, rws, other] == 0)
             wi, wa = Wi[t, rws, own], Wa[t, rws, own]
-            kept = int(np.sum(np.linalg.norm(wa, axis=1) > 0))
-            assert kept == k, (b, kept, k)
+            k = int(np.sum(np.linalg.norm(wa, axis=1) > 0))
+            assert k_lo <= k <= k_hi, (b, k, k_lo, k_hi)
             assert np.all(wi[k:] == 0) and np.all(wa[k:] == 0)
             u_, s_, vh_ = np.linalg.svd(Mb, full_matrices=False)
             Mk = (u_[:, :k] * s_[:k]) @ vh_[:k]
             U = Mb @ wi[:k].T
             assert np.abs(U @ wa[:k] - Mk).max() < tol * max(1.0, s[0])
             assert np.abs(np.linalg.norm(wa[:k], axis=1) - s[:k]).max() < tol * s[0]
+    eng.close()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("m", [1, 8, 32])
+def test_eigh_degenerate_diagonal_converges(dtype, m):
+    # A Gram matrix whose diagonal is exactly degenerate and whose large
+    # entries sit beside noise-sized ones (the stabilizer-state Gram matrices
+    # of complex64 runs, where the noise is the storage rounding): the
+    # noise-driven rotations turn by 45 degrees and move the large entries
+    # around within a sweep, so convergence must be judged on the whole
+    # matrix after the sweep.  G = A (x) I_m + E with A = [[1,0,1,0],
+    # [0,1,0,-1], [1,0,1,0], [0,-1,0,1]] / 4 (eigenvalues 1/2, 1/2, 0, 0), E
+    # Hermitian of size ~3e-8; the cap keeps the 2m values near 1/2.
+    from paper_2511_05719_amd._abi import lib, check
+    g = np.random.default_rng(m)
+    A = np.array([[1, 0, 1, 0], [0, 1, 0, -1], [1, 0, 1, 0], [0, -1, 0, 1]], float) / 4
+    n, cap, rows = 4 * m, 2 * m, 3
+    G = np.zeros((rows, n, n), complex)
+    for t in range(rows):
+        E = 3e-8 * (g.normal(size=(n, n)) + (1j * g.normal(size=(n, n)) if t == 2 else 0))
+        E = (E + E.conj().T) / 2
+        np.fill_diagonal(E, 0.0)
+        G[t] = np.kron(A, np.eye(m)) + E
+    eng = _engine(dtype, chi=128)
+    Gd = torch.view_as_real(torch.as_tensor(G)).contiguous().cuda()
+    wdt = torch.float64 if dtype == "c128" else torch.float32
+    Wi = torch.zeros(rows, cap, n, 2, dtype=wdt, device="cuda")
+    Wa = torch.zeros(rows, cap, n, 2, dtype=wdt, device="cuda")
+    rk = torch.zeros(rows, dtype=torch.int32, device="cuda")
+    check(lib().ttn_test_eigh(eng._ctx, rows, n, cap, cap, 1e-10, Gd.data_ptr(), rows * n * n, Wi.data_ptr(),
+                              Wa.data_ptr(), rows * cap * n, rk.data_ptr(), None, 1), eng._ctx)
+    Wi, Wa = _host_complex(Wi), _host_complex(Wa)
+    assert (rk.cpu().numpy() == cap).all()
+    tol = 1e-9 if dtype == "c128" else 1e-5
+    for t in range(rows):
+        w, v = np.linalg.eigh(G[t])
+        P = v[:, -cap:] @ v[:, -cap:].conj().T                # the kept eigenspace
+        Gk = P @ G[t] @ P
+        iso = Wi[t].conj() @ G[t] @ Wi[t].T
+        assert np.abs(iso - np.eye(cap)).max() < tol, t
+        rec = Wa[t].conj().T @ Wa[t] * np.trace(Gk).real     # W_abs is renormalised by the kept weight
+        assert np.abs(rec - Gk).max() < tol, (t, np.abs(rec - Gk).max())
     eng.close()
