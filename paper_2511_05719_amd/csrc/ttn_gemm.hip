@@ -94,8 +94,10 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
   const R sgnB = d.conjB ? (R)-1 : (R)1;
 
   // this trajectory's extents: rows, columns and K terms that can be
-  // non-zero; a tile beyond them only writes its zeros
-  int Mt = d.M, Nt = d.N, Kt = d.K, Kin = d.Kin;
+  // non-zero; a tile beyond them only writes its zeros.  A split N index
+  // bounds its inner part by Nt and its outer part by No.
+  const bool nsplit = d.Nin > 0 && d.Nin < d.N;
+  int Mt = d.M, Nt = nsplit ? d.Nin : d.N, No = nsplit ? d.N / d.Nin : 1, Kt = d.K, Kin = d.Kin;
   if (d.ext) {
     const int* ex = d.ext + t * d.ext_stride;
     const int kn = d.knew ? d.knew[t * 4] : 0;
@@ -103,15 +105,24 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
     int ht = d.H, ko = d.K / d.Kin, ki = d.Kin;
     if (d.eM) Mt = min(Mt, extent(d.eM) * d.mM);
     if (d.eN) Nt = min(Nt, extent(d.eN) * d.mN);
+    if (nsplit && d.eNo) No = min(No, extent(d.eNo));
     if (d.eH) ht = min(ht, extent(d.eH));
     if (d.eKo) ko = min(ko, extent(d.eKo));
     if (d.eKi) ki = min(ki, extent(d.eKi));
     Kin = max(ki, 1);
     Kt = max(ko, 0) * max(ki, 0);
-    if (h >= ht || m0 >= Mt || n0 >= Nt) Kt = 0;
+    if (h >= ht || m0 >= Mt || n0 >= (nsplit ? No * d.Nin : Nt)) Kt = 0;
   }
-  if (d.band && (m0 >= d.bM1 || m0 + TM <= d.bM0 || n0 >= d.bN1 || n0 + TN <= d.bN0 || h < d.bH0 || h >= d.bH1))
-    Kt = 0;
+  if (d.band) {
+    bool out = m0 >= d.bM1 || m0 + TM <= d.bM0 || h < d.bH0 || h >= d.bH1;
+    if (nsplit) {
+      const int qlo = n0 / d.Nin, qhi = (min(n0 + TN, d.N) - 1) / d.Nin;
+      out = out || qhi < d.bNo0 || qlo >= d.bNo1;
+    } else {
+      out = out || n0 >= d.bN1 || n0 + TN <= d.bN0;
+    }
+    if (out) Kt = 0;
+  }
   // K slice of this split (an empty slice still writes its zero partials)
   const int nchunks = (Kt + TK - 1) / TK;
   const int per = (nchunks + d.ksplit - 1) / d.ksplit;
@@ -150,7 +161,14 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
     const int nn = d.b_n_fast ? e % TN : e / TK;
     const int kk = d.b_n_fast ? e / TN : e % TK;
     const int gn = n0 + nn;
-    b_co[r] = gn < Nt ? __umul24((unsigned)gn, (unsigned)d.sBj) : -1;
+    if (nsplit) {
+      const int q = gn / d.Nin, rj = gn - q * d.Nin;
+      const bool ok = gn < d.N && q < No && rj < Nt &&
+                      (!d.band || (rj >= d.bN0 && rj < d.bN1 && q >= d.bNo0 && q < d.bNo1));
+      b_co[r] = ok ? q * (int)d.sBj1 + rj * (int)d.sBj : -1;
+    } else {
+      b_co[r] = gn < Nt ? __umul24((unsigned)gn, (unsigned)d.sBj) : -1;
+    }
     b_kk[r] = kk;
     b_ls[r] = kk * (TN + PADL) + nn;
   }
@@ -288,7 +306,12 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
         const int gj = n0 + wn * 32 + b * 16 + li;
         if (gi < d.M && gj < d.N) {
           double2 v = make_double2((double)acc_re[a][b][r], (double)acc_im[a][b][r]);
-          C[(long long)gi * d.sCi + (long long)gj * d.sCj] = from_d2<SC>(v);
+          long long oj = (long long)gj * d.sCj;
+          if (nsplit) {
+            const int q = gj / d.Nin;
+            oj = (long long)q * d.sCj1 + (long long)(gj - q * d.Nin) * d.sCj;
+          }
+          C[(long long)gi * d.sCi + oj] = from_d2<SC>(v);
         }
       }
 }
@@ -349,7 +372,10 @@ hipError_t launch_zgemm_t(GemmDesc d, int batch, hipStream_t st, int cfg) {
       if (sA[i] < 0 || sA[i] >= lim24 || sB[i] < 0 || sB[i] >= lim24) return hipErrorInvalidValue;
     if (d.M >= lim24 || d.N >= lim24 || d.K >= (1 << 22)) return hipErrorInvalidValue;
     const long long ea = (long long)(d.M - 1) * d.sAi + kq * d.sAl1 + kr * d.sAl2;
-    const long long eb = (long long)(d.N - 1) * d.sBj + kq * d.sBl1 + kr * d.sBl2;
+    const bool nsplit = d.Nin > 0 && d.Nin < d.N;
+    if (nsplit && (d.N % d.Nin != 0 || d.sBj1 < 0)) return hipErrorInvalidValue;
+    const long long eb = (nsplit ? (long long)(d.N / d.Nin - 1) * d.sBj1 + (long long)(d.Nin - 1) * d.sBj
+                                 : (long long)(d.N - 1) * d.sBj) + kq * d.sBl1 + kr * d.sBl2;
     if (ea >= (1ll << 31) || eb >= (1ll << 31)) return hipErrorInvalidValue;
   }
   if (d.ext && (d.eM < 0 || d.eN < 0 || d.eH < 0 || d.eKo < 0 || d.eKi < 0) && !d.knew) return hipErrorInvalidValue;

@@ -13,6 +13,10 @@ struct GemmDesc {
   const void* B;
   void* C;
   int M, N, K, Kin;   // K index l = (l / Kin, l % Kin) with strides (l1, l2)
+  // N index j = (j / Nin, j % Nin) with strides (sBj1, sBj) on B and (sCj1,
+  // sCj) on C when 0 < Nin < N (N a multiple of Nin); otherwise one stride
+  int Nin;
+  long long sBj1, sCj1;
   int H;              // inner batch size (>= 1)
   int G2;             // block batch size (0 or 1: none; 2: the two diagonal
                       // blocks of a block-diagonal operand, strides s?g)
@@ -37,13 +41,16 @@ struct GemmDesc {
   const int* knew;
   long long ext_stride;
   int eM, eN, eH;           // M <= extent(eM) * mM, N <= extent(eN) * mN, H <= extent(eH)
-  int mM, mN;
+  int mM, mN;               // (with Nin: eN, mN bound j % Nin, eNo bounds j / Nin)
+  int eNo;
   int eKo, eKi;             // outer (l / Kin) and inner (l % Kin) parts of K
   // Bands (optional, band = 1): only rows [bM0, bM1), columns [bN0, bN1) and
   // inner batches [bH0, bH1) can be non-zero; output tiles wholly outside
-  // are written as zeros without K work (a block-structured leg of the node)
+  // are written as zeros without K work (a block-structured leg of the node).
+  // With Nin, [bN0, bN1) bounds j % Nin (element by element) and [bNo0,
+  // bNo1) bounds j / Nin.
   int band;
-  int bM0, bM1, bN0, bN1, bH0, bH1;
+  int bM0, bM1, bN0, bN1, bH0, bH1, bNo0, bNo1;
 };
 
 // cfg: one of the kZgemmCfgs tile shapes (64x64, 128x32, 32x128, 32x32 with
@@ -87,7 +94,7 @@ struct EighDesc {
   int* nsteps;          // [batch]
   int* nk_out;          // [batch][4]: (non-zero eigenvalues, kept) of block 0, block 1 (may be null)
   double tol;           // rotate a pair while |g_pq| > tol sqrt(g_pp g_qq) (0: 1e-15)
-  int early_stop;       // 1: stop after a sweep whose rotated ratios all stayed below sqrt(tol) / 4
+  int early_stop;       // 1: also stop once every off-diagonal ratio is below sqrt(tol) / 4
   int gsplit;           // G is the sum of gsplit partial products (0 or 1: one)
   long long gslice;     // element stride between them
   long long log_stride; // doubles of rot_log per problem (problem = row, or (row, block))

@@ -299,11 +299,17 @@ static long long extent(long long batch, long long sT, int G2, long long sG, int
 static bool gemm_fits(const GemmDesc& g, int batch, long long capA, long long capB, long long capC) {
   if (g.M < 1 || g.N < 1 || g.K < 1 || g.H < 1 || g.Kin < 1) return false;
   const int G2 = std::max(g.G2, 1);
+  const bool nsplit = g.Nin > 0 && g.Nin < g.N;
+  if (nsplit && g.N % g.Nin != 0) return false;
+  // the largest column offset on B and C (a split index: both parts at their last value)
+  const long long jB = nsplit ? (long long)(g.N / g.Nin - 1) * g.sBj1 + (long long)(g.Nin - 1) * g.sBj
+                              : (long long)(g.N - 1) * g.sBj;
+  const long long jC = nsplit ? (long long)(g.N / g.Nin - 1) * g.sCj1 + (long long)(g.Nin - 1) * g.sCj
+                              : (long long)(g.N - 1) * g.sCj;
   const long long eA = extent(batch, g.sAt, G2, g.sAg, g.H, g.sAh, g.M, g.sAi, g.K, g.Kin, g.sAl1, g.sAl2);
-  const long long eB = extent(batch, g.sBt, G2, g.sBg, g.H, g.sBh, g.N, g.sBj, g.K, g.Kin, g.sBl1, g.sBl2);
+  const long long eB = extent(batch, g.sBt, G2, g.sBg, g.H, g.sBh, 1, 0, g.K, g.Kin, g.sBl1, g.sBl2) + jB;
   const long long eC = (long long)(batch - 1) * g.sCt + (long long)(G2 - 1) * g.sCg + (long long)(g.H - 1) * g.sCh +
-                       (long long)(g.M - 1) * g.sCi + (long long)(g.N - 1) * g.sCj +
-                       (long long)(std::max(g.ksplit, 1) - 1) * g.sCz + 1;
+                       (long long)(g.M - 1) * g.sCi + jC + (long long)(std::max(g.ksplit, 1) - 1) * g.sCz + 1;
   return eA <= capA && eB <= capB && eC <= capC;
 }
 
@@ -331,11 +337,12 @@ static GemmDesc leg_desc(const void* T, std::array<int, 3> d, int leg, const voi
     g.C = out; g.sCt = sO; g.sCi = newd; g.sCj = 1;
     g.M = (int)R; g.N = newd; g.K = n;
   } else {
-    g.H = d[0];
-    g.A = W; g.sAt = (long long)wrows * n; g.sAh = 0; g.sAi = n; g.sAl2 = 1; g.a_m_fast = 0;
-    g.B = T; g.sBt = sT; g.sBh = (long long)n * d[2]; g.sBl2 = d[2]; g.sBj = 1; g.b_n_fast = 1;
-    g.C = out; g.sCt = sO; g.sCh = (long long)newd * d[2]; g.sCi = d[2]; g.sCj = 1;
-    g.M = newd; g.N = d[2]; g.K = n;
+    // the middle leg: one GEMM per row over the split column index (a, u)
+    // of T[a][i][u] (strides (n d2, 1)) and of the output (newd d2, 1)
+    g.A = W; g.sAt = (long long)wrows * n; g.sAi = n; g.sAl2 = 1; g.a_m_fast = 0;
+    g.B = T; g.sBt = sT; g.sBl2 = d[2]; g.sBj = 1; g.sBj1 = (long long)n * d[2]; g.b_n_fast = d[2] >= 4;
+    g.C = out; g.sCt = sO; g.sCi = d[2]; g.sCj = 1; g.sCj1 = (long long)newd * d[2];
+    g.M = newd; g.N = d[0] * d[2]; g.Nin = d[2]; g.K = n;
   }
   g.Kin = g.K;
   return g;
@@ -405,7 +412,7 @@ static void ext_leg(const ttn_ctx* ctx, GemmDesc& g, int node, std::array<int, 3
   } else if (leg == 2) {
     g.eM = ext_bond(ctx, node, 0); g.mM = d[1]; g.eN = bn; g.mN = 1;
   } else {
-    g.eH = ext_bond(ctx, node, 0); g.eM = bn; g.mM = 1; g.eN = ext_bond(ctx, node, 2); g.mN = 1;
+    g.eNo = ext_bond(ctx, node, 0); g.eM = bn; g.mM = 1; g.eN = ext_bond(ctx, node, 2); g.mN = 1;
   }
   g.eKi = bk;
 }
@@ -485,11 +492,12 @@ struct Partner {
 static void set_band(GemmDesc& g, std::array<int, 3> d, int leg, const Partner& pt, int b) {
   const int lo = pt.lo[b], hi = pt.hi[b];
   g.bM0 = 0; g.bM1 = 1 << 30; g.bN0 = 0; g.bN1 = 1 << 30; g.bH0 = 0; g.bH1 = 1 << 30;
+  g.bNo0 = 0; g.bNo1 = 1 << 30;
   g.band = 1;
   if (leg == 0 && pt.leg == 1) { g.bN0 = lo * d[2]; g.bN1 = hi * d[2]; }
   else if (leg == 2 && pt.leg == 0) { g.bM0 = lo * d[1]; g.bM1 = hi * d[1]; }
-  else if (leg == 1 && pt.leg == 0) { g.bH0 = lo; g.bH1 = hi; }
-  else if (leg == 1 && pt.leg == 2) { g.bN0 = lo; g.bN1 = hi; }
+  else if (leg == 1 && pt.leg == 0) { g.bNo0 = lo; g.bNo1 = hi; }    // the outer part (a) of the split index
+  else if (leg == 1 && pt.leg == 2) { g.bN0 = lo; g.bN1 = hi; }      // its inner part (u)
   else g.band = 0;
 }
 
