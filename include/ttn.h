@@ -361,8 +361,11 @@ ttn_status ttn_test_eigh(ttn_ctx* ctx, int32_t rows, int32_t n, int32_t new_pad,
                          int32_t* rank, int32_t* sweeps, int32_t blocks);
 /* ttn_test_move: the factors of an exact centre move by pivoted Cholesky
  * (the QR route of complex64 contexts): same arguments and outputs as
- * ttn_test_eigh (without sweeps), n <= 64 per diagonal block; the rank is
- * the number of pivots above cutoff x trace, at most cap. */
+ * ttn_test_eigh (without sweeps), n <= 64 per diagonal block, or n <= 128
+ * without blocks; the rank is the number of pivots above cutoff x trace, at
+ * most cap.  For n > 64 the call behaves as the batch driver's try before a
+ * truncating eigen-decomposition: a row whose weight above the cutoff needs
+ * more than cap pivots gets rank -1 and its W rows are left untouched. */
 ttn_status ttn_test_move(ttn_ctx* ctx, int32_t rows, int32_t n, int32_t new_pad, int32_t cap, double cutoff,
                          const double* G, int64_t g_elems, void* W_iso, void* W_abs, int64_t w_elems,
                          int32_t* rank, int32_t blocks);

@@ -208,6 +208,7 @@ template <bool kVinLds, int NT, typename VT, int NMAX>
 __global__ void __launch_bounds__(NT) k_jacobi(EighDesc d) {
   extern __shared__ double2 smem[];
   const long long pid = blockIdx.x;                    // problem: a row, or (row, block)
+  if (!kVinLds && d.done && d.done[pid]) return;       // factored by the pivoted Cholesky
   const Problem pb = problem_of(d, pid);
   const long long t = pb.t;
   const double2* G = d.G + t * (long long)d.n * d.n;
@@ -682,6 +683,7 @@ __global__ void __launch_bounds__(kThreadsCoset) k_jacobi_coset(EighDesc d) {
   constexpr int NQ = NMAX / 4;
   extern __shared__ double2 smem[];
   const long long pid = blockIdx.x;
+  if (d.done && d.done[pid]) return;                   // factored by the pivoted Cholesky
   const Problem pb = problem_of(d, pid);
   const long long t = pb.t;
   const double2* G = d.G + t * (long long)d.n * d.n;
@@ -943,6 +945,7 @@ __global__ void __launch_bounds__(1024) k_jacobi_vectors(EighDesc d) {
   __shared__ int order_s[NMAX];
   __shared__ double lam_s[NMAX];
   const long long pid = blockIdx.x;
+  if (d.done && d.done[pid]) return;                   // factored by the pivoted Cholesky
   const Problem pb = problem_of(d, pid);
   const long long t = pb.t;
   // the same compaction as the solver's (G is unchanged)
@@ -1505,14 +1508,217 @@ __global__ void __launch_bounds__(64 * NW) k_pchol(EighDesc d) {
   }
 }
 
+// Problems of 65 to 128 columns (one row, no blocks): the same sweep with
+// the rows in registers.  Eight waves; wave w holds rows i = 8 q + w (q <
+// 16), lane j columns j and j + 64 of each.  At each step the wave owning
+// the pivot row publishes it through LDS (two buffers by the step's parity,
+// one barrier per step), every wave updates its own rows in registers, and
+// the owner then keeps the row's final values in place of the residual.
+// With d.done set (the try before a truncating eigen-decomposition): a
+// problem whose weight above the cutoff needs more than the cap's pivots
+// writes done = 0 and nothing else, the others write their factors and
+// done = 1.  Without it the factorisation stops at the cap.
+template <int NMAX>
+__global__ void __launch_bounds__(512) k_pchol_reg(EighDesc d) {
+  static_assert(NMAX == 128, "two columns per lane, sixteen rows per wave");
+  constexpr int NW = 8, RPW = NMAX / NW, CPL = NMAX / 64;
+  __shared__ int cidx[NMAX], inv[NMAX], wcount[NW];
+  __shared__ int pos[NMAX], order[NMAX];
+  __shared__ double2 pbuf[2][NMAX];
+  __shared__ double red[2][NW];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const long long pid = blockIdx.x;
+  const Problem pb = problem_of(d, pid);
+  const long long t = pb.t;
+  const double2* G = d.G + t * (long long)d.n * d.n;
+  const int n = compact_rows<NW>(d, G, pb, cidx, inv, wcount);
+  if (threadIdx.x < NMAX) pos[threadIdx.x] = -1;
+  double2 A[RPW][CPL];
+#pragma unroll
+  for (int q = 0; q < RPW; ++q)
+#pragma unroll
+    for (int s = 0; s < CPL; ++s) {
+      const int i = NW * q + wave, c = lane + 64 * s;
+      A[q][s] = (i < n && c < n) ? gram_at(d, G, (long long)(pb.off + cidx[i]) * d.n + pb.off + cidx[c])
+                                 : make_double2(0.0, 0.0);
+    }
+  double dj[CPL];
+#pragma unroll
+  for (int s = 0; s < CPL; ++s) {
+    const int c = lane + 64 * s;
+    dj[s] = c < n ? gram_at(d, G, (long long)(pb.off + cidx[c]) * d.n + pb.off + cidx[c]).x : 0.0;
+  }
+  double part = 0.0, own = 0.0;
+  for (int i = threadIdx.x; i < d.n; i += blockDim.x) part += gram_at(d, G, (long long)i * d.n + i).x;
+#pragma unroll
+  for (int s = 0; s < CPL; ++s) own += dj[s];
+  part = wave_sum_d(part);
+  own = wave_sum_d(own);
+  if (lane == 0) { red[0][wave] = part; red[1][wave] = own; }
+  __syncthreads();
+  double tr = 0.0, mine = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) tr += red[0][w];
+  // (every wave holds every column's diagonal: the problem's trace once)
+  mine = red[1][0];
+  const bool finite = isfinite(tr) && tr > 0.0;
+  const double tol = d.cutoff * mine;
+  const int lim = min(min(d.cap, pb.pad), n);
+  unsigned long long piv[CPL] = {0ull, 0ull};          // pivoted columns (uniform)
+  int k = 0;
+  bool fail = false;
+  if (finite) {
+    for (; k <= lim; ++k) {
+      unsigned key = 0;
+#pragma unroll
+      for (int s = 0; s < CPL; ++s) {
+        const int c = lane + 64 * s;
+        if (c < n && !((piv[s] >> lane) & 1ull))
+          key = max(key, ((__float_as_uint((float)fmax(dj[s], 0.0)) + 128u) & ~127u) | (unsigned)(127 - c));
+      }
+      key = wave_max_u32(key);
+      if (key == 0u) break;
+      const int p = 127 - (int)(key & 127u);
+      const double dm = readlane_d(p >= 64 ? dj[1] : dj[0], p & 63);
+      if (!(dm > tol) || !isfinite(dm)) break;         // (uniform: every wave alike)
+      if (k == lim) { fail = true; break; }            // weight above the cutoff beyond the cap
+      const double rkk = sqrt(dm);
+      const double irkk = 1.0 / rkk;
+      const int qp = p / NW;
+      const bool owner = (p % NW) == wave;
+      if (owner) {
+#pragma unroll
+        for (int q = 0; q < RPW; ++q)
+          if (q == qp)
+#pragma unroll
+            for (int s = 0; s < CPL; ++s) pbuf[k & 1][lane + 64 * s] = A[q][s];
+      }
+      __syncthreads();
+      double2 arow[CPL], u[CPL], z[CPL], w[CPL];
+      bool colj[CPL];
+#pragma unroll
+      for (int s = 0; s < CPL; ++s) {
+        const int c = lane + 64 * s;
+        arow[s] = pbuf[k & 1][c];
+        const bool before = (piv[s] >> lane) & 1ull;
+        colj[s] = c < n && !before && c != p;
+        u[s] = colj[s] ? cscale(arow[s], irkk) : make_double2(0.0, 0.0);
+        z[s] = before ? cscale(arow[s], irkk) : make_double2(c == p ? irkk : 0.0, 0.0);
+        w[s] = colj[s] ? u[s] : z[s];
+        if (colj[s]) dj[s] = fma(-u[s].x, u[s].x, fma(-u[s].y, u[s].y, dj[s]));
+      }
+      if (p >= 64) piv[1] |= 1ull << (p - 64);
+      else piv[0] |= 1ull << p;
+      if (owner) {
+#pragma unroll
+        for (int q = 0; q < RPW; ++q)
+          if (q == qp)
+#pragma unroll
+            for (int s = 0; s < CPL; ++s)
+              A[q][s] = colj[s] ? u[s] : ((lane + 64 * s) == p ? make_double2(rkk, 0.0) : z[s]);
+      }
+      // each remaining row j: A_jc -= conj(u_j) u_c (remaining c), y_j -= u_j z_k
+#pragma unroll
+      for (int q = 0; q < RPW; ++q) {
+        const int i = NW * q + wave;                    // (q / 8: the word and register half of row i)
+        if (i < n && !((piv[q / 8] >> (i & 63)) & 1ull)) {
+          const double ujx = readlane_d(arow[q / 8].x, i & 63) * irkk;
+          const double ujy0 = readlane_d(arow[q / 8].y, i & 63) * irkk;
+#pragma unroll
+          for (int s = 0; s < CPL; ++s) {
+            const int c = lane + 64 * s;
+            const double ujy = colj[s] ? -ujy0 : ujy0;
+            double2 o = c == p ? make_double2(0.0, 0.0) : A[q][s];
+            o.x = fma(-ujx, w[s].x, fma(ujy, w[s].y, o.x));
+            o.y = fma(-ujx, w[s].y, fma(-ujy, w[s].x, o.y));
+            if (c < n) A[q][s] = o;
+          }
+        }
+      }
+      if (threadIdx.x == 0) {
+        order[k] = p;
+        pos[p] = k;
+      }
+    }
+  }
+  if (d.done) {
+    if (threadIdx.x == 0) d.done[pid] = fail ? 0 : 1;
+    if (fail) return;                                   // (uniform) left to the eigensolver
+  }
+  const int r = k;
+  double rs = 0.0;
+#pragma unroll
+  for (int s = 0; s < CPL; ++s)
+    if (lane + 64 * s < n && !((piv[s] >> lane) & 1ull)) rs += fmax(dj[s], 0.0);
+  const double resid = wave_sum_d(rs);
+  const double kept = fmax(mine - resid, 0.0);
+  double scale;
+  int kk = r;
+  if (!(kept > 0.0) || !isfinite(kept) || r == 0) {
+    kk = 0;
+    scale = 0.0;
+  } else {
+    scale = 1.0 / sqrt(kept);
+  }
+  if (threadIdx.x == 0) {
+    if (kk == 0 && d.flags) d.flags[t] |= 1;
+    if (d.disc_acc && mine > 0.0) d.disc_acc[t] += (mine - kept) / mine;
+    if (d.rank_out) d.rank_out[t * d.rank_stride] = kk;
+    if (d.rank_max) d.rank_max[t * d.rank_stride] = max(d.rank_max[t * d.rank_stride], kk);
+    if (d.flops_acc)
+      d.flops_acc[t] += 8.0 * ((double)r * r * (3.0 * n - 2.0 * r) / 3.0 + (double)r * r * r / 3.0);
+    if (d.nk_out) {
+      d.nk_out[t * 4] = r;
+      d.nk_out[t * 4 + 1] = kk;
+      d.nk_out[t * 4 + 2] = 0;
+      d.nk_out[t * 4 + 3] = 0;
+    }
+    if (d.sweeps_out) d.sweeps_out[t] = 0;
+  }
+  __syncthreads();                                      // pos, order
+  // zeros: rows a >= kk, and the dead columns of the kept rows
+  const long long base = t * (long long)d.new_pad * d.n;
+  const int nr = pb.n;
+  for (int idx = threadIdx.x; idx < pb.pad * nr; idx += blockDim.x) {
+    const int a = idx / nr, i = idx - (idx / nr) * nr;
+    if (a < kk && inv[i] >= 0) continue;
+    const long long o = base + (long long)(pb.pad_off + a) * d.n + pb.off + i;
+    if (d.out_c128) { ((double2*)d.W_iso)[o] = make_double2(0, 0); ((double2*)d.W_abs)[o] = make_double2(0, 0); }
+    else { ((float2*)d.W_iso)[o] = make_float2(0, 0); ((float2*)d.W_abs)[o] = make_float2(0, 0); }
+  }
+  // the kept rows, from the registers of the waves that own their pivots:
+  // W_abs row a = R[a] on the columns pivoted at step a or later (scaled),
+  // W_iso row a = z_a (1 / R_aa at the pivot, stored on the earlier pivots)
+#pragma unroll
+  for (int q = 0; q < RPW; ++q) {
+    const int i = NW * q + wave;
+    const int a = i < n ? pos[i] : -1;
+    if (a < 0 || a >= kk) continue;                     // (uniform)
+#pragma unroll
+    for (int s = 0; s < CPL; ++s) {
+      const int c = lane + 64 * s;
+      if (c >= n) continue;
+      const int pc = pos[c];
+      const double2 x = A[q][s];
+      const double2 wa = (pc < 0 || pc >= a) ? cscale(x, scale) : make_double2(0.0, 0.0);
+      const double2 wi = pc == a ? make_double2(1.0 / x.x, 0.0) : ((pc >= 0 && pc < a) ? x : make_double2(0.0, 0.0));
+      const long long o = base + (long long)(pb.pad_off + a) * d.n + pb.off + cidx[c];
+      if (d.out_c128) { ((double2*)d.W_iso)[o] = wi; ((double2*)d.W_abs)[o] = wa; }
+      else { ((float2*)d.W_iso)[o] = from_d2<float2>(wi); ((float2*)d.W_abs)[o] = from_d2<float2>(wa); }
+    }
+  }
+}
+
 hipError_t launch_pchol(const EighDesc& d, int batch, hipStream_t st) {
   if (batch <= 0) return hipSuccess;
   const int nb = d.blocks > 1 ? 2 : 1;
-  if (d.n < 1 || d.new_pad < 1 || (nb == 2 && ((d.n & 1) || (d.new_pad & 1))) || d.n / nb > 64)
+  if (d.n < 1 || d.new_pad < 1 || (nb == 2 && ((d.n & 1) || (d.new_pad & 1))) || d.n / nb > (nb == 2 ? 64 : 128))
     return hipErrorInvalidValue;
   const int nsub = d.n / nb;
   const dim3 grid((unsigned)((long long)batch * nb));
-  if (nsub <= 16) hipLaunchKernelGGL((k_pchol<16, 1>), grid, dim3(64), 0, st, d);
+  if (nsub > 64) hipLaunchKernelGGL((k_pchol_reg<128>), grid, dim3(512), 0, st, d);
+  else if (nsub <= 16) hipLaunchKernelGGL((k_pchol<16, 1>), grid, dim3(64), 0, st, d);
   else if (nsub <= 32) hipLaunchKernelGGL((k_pchol<32, 2>), grid, dim3(128), 0, st, d);
   else hipLaunchKernelGGL((k_pchol<64, 4>), grid, dim3(256), 0, st, d);
   return hipGetLastError();

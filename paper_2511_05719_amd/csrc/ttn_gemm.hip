@@ -77,7 +77,15 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
   const int wave = tid >> 6;
   const int kw = wave / (WM * WN);
   const int wm = (wave % (WM * WN)) / WN, wn = wave % WN;
-  const long long bx = blockIdx.x;
+  // XCD-aware order: the chip deals consecutive workgroups out to its 8
+  // XCDs in turn, so workgroup x is given logical tile (x % 8) * (nx / 8) +
+  // x / 8 and each XCD runs a contiguous range of tiles, the N tiles of a
+  // row together: the row's W block stays in that XCD's L2
+  long long bx = blockIdx.x;
+  {
+    const long long nx = gridDim.x;
+    if (nx % 8 == 0) bx = (bx & 7) * (nx >> 3) + (bx >> 3);
+  }
   const int tile_n = (int)(bx % d.tilesN);
   const long long bh = bx / d.tilesN;            // flattened (t, g, h)
   const int h = (int)(bh % d.H);

@@ -93,6 +93,10 @@ struct EighDesc {
   double* scale_abs;    // [batch]
   int* nsteps;          // [batch]
   int* nk_out;          // [batch][4]: (non-zero eigenvalues, kept) of block 0, block 1 (may be null)
+  // [problems] (may be null): the pivoted Cholesky of 65..128 columns writes
+  // 1 where it has written the factors, 0 where the weight above the cutoff
+  // needs more than cap pivots; the large eigensolver skips the 1s
+  int* done;
   double tol;           // rotate a pair while |g_pq| > tol sqrt(g_pp g_qq) (0: 1e-15)
   int early_stop;       // 1: also stop once every off-diagonal ratio is below sqrt(tol) / 4
   int gsplit;           // G is the sum of gsplit partial products (0 or 1: one)
@@ -110,7 +114,7 @@ hipError_t launch_eigh(const EighDesc& d, int batch, hipStream_t st);
 hipError_t eigh_prepare();
 // Exact (non-truncating) centre-move factors by pivoted Cholesky of G, same
 // outputs as launch_eigh (rank = pivots above cutoff x trace, at most cap);
-// problems of size <= 64 (per block)
+// problems of size <= 64 per block, or <= 128 without blocks (with done)
 hipError_t launch_pchol(const EighDesc& d, int batch, hipStream_t st);
 int eigh_max_sweeps();
 // size that the solver pads a problem above 64 to (a power of two, >= 4):

@@ -162,6 +162,7 @@ struct ttn_ctx {
                                             // move; bytes of Gram, contraction
   int* adim = nullptr;                      // [B][L][3] actual leg dimensions (profiling)
   int* nk = nullptr;                        // [B][4] eigensolver counts of the last move
+  int* qr_done = nullptr;                   // [B] rows of a move factored by the pivoted Cholesky
   int* nk_max = nullptr;                    // [4] their maxima over rows (device)
   int* nk_host = nullptr;                   // [4] pinned host copy
   // stats
@@ -662,10 +663,28 @@ static ttn_status hop(ttn_ctx* ctx, int x, int y, double cutoff, int cap, int ne
   // entries below 1e-12 of the diagonal change nothing they hold
   ed.tol = ctx->c128 ? 1e-15 : 1e-10;
   ed.early_stop = ctx->c128 ? 0 : 1;
+  // complex64 rows without blocks of 65..128 columns: the pivoted Cholesky
+  // first, which factors every row whose weight above the cutoff fits the
+  // cap (the move then drops nothing but that cutoff); the eigensolver
+  // takes the rest
+  const bool try_qr = !ctx->c128 && large && blocks == 1 && n <= 128;
   if (qr) {
     ++ctx->launches;
     ProfScope ps(ctx, CLS_MOVE);
     TTN_CHECK_HIP(launch_pchol(ed, ctx->B, ctx->st));
+  } else if (try_qr) {
+    {
+      EighDesc eq = ed;
+      eq.flops_acc = ctx->ledger[CLS_MOVE];
+      eq.done = ctx->qr_done;
+      ++ctx->launches;
+      ProfScope ps(ctx, CLS_MOVE);
+      TTN_CHECK_HIP(launch_pchol(eq, ctx->B, ctx->st));
+    }
+    ed.done = ctx->qr_done;
+    ctx->launches += 2;
+    ProfScope ps(ctx, CLS_EIGH_LARGE);
+    TTN_CHECK_HIP(launch_eigh(ed, ctx->B, ctx->st));
   } else {
     ctx->launches += large ? 2 : 1;
     ProfScope ps(ctx, large ? CLS_EIGH_LARGE : CLS_EIGH_SMALL);
@@ -1228,6 +1247,7 @@ ttn_status ttn_create(const ttn_config* cfg, ttn_ctx** out) {
   ok &= hipMalloc((void**)&ctx->ledger_mem, 7 * Bz * sizeof(double)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->adim, Bz * L * 3 * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->nk, Bz * 4 * sizeof(int)) == hipSuccess;
+  ok &= hipMalloc((void**)&ctx->qr_done, Bz * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->nk_max, 4 * sizeof(int)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->gate4, 32 * sizeof(double)) == hipSuccess;
   ok &= hipMalloc((void**)&ctx->d_traj, sizeof(uint64_t)) == hipSuccess;
@@ -1286,7 +1306,7 @@ ttn_status ttn_destroy(ttn_ctx* ctx) {
     }
   void* ws[] = {ctx->G, ctx->Wi, ctx->Wa, ctx->rot_log, ctx->gpk, ctx->lam_sorted, ctx->order, ctx->kept,
                 ctx->scale_abs, ctx->nsteps, ctx->rank_table, ctx->ext, ctx->rank_max, ctx->ledger_mem,
-                ctx->adim, ctx->nk, ctx->nk_max, ctx->gate4, ctx->d_traj,
+                ctx->adim, ctx->nk, ctx->qr_done, ctx->nk_max, ctx->gate4, ctx->d_traj,
                 ctx->disc_acc, ctx->flags,
                 ctx->degen_acc, ctx->leader, ctx->dec_datarec, ctx->dec_masks};
   for (void* p : ws)
@@ -2314,10 +2334,11 @@ ttn_status ttn_test_move(ttn_ctx* ctx, int32_t rows, int32_t n, int32_t new_pad,
                          const double* G, int64_t g_elems, void* W_iso, void* W_abs, int64_t w_elems,
                          int32_t* rank, int32_t blocks) {
   if (!ctx) return TTN_EINVAL;
-  if (rows < 1 || rows > ctx->B || n < 1 || n / blocks > 64 || new_pad < 1 || new_pad > ctx->nmax || cap < 1 ||
-      !G || !W_iso || !W_abs || (blocks != 1 && blocks != 2) || (blocks == 1 && !rank) ||
-      (blocks == 2 && ((n & 1) || (new_pad & 1))))
-    return fail(ctx, TTN_EINVAL, "bad arguments (rows <= batch, n <= 64 per block, new_pad <= workspace)");
+  if (rows < 1 || rows > ctx->B || n < 1 || n / blocks > (blocks == 1 ? 128 : 64) || new_pad < 1 ||
+      new_pad > ctx->nmax || cap < 1 || !G || !W_iso || !W_abs || (blocks != 1 && blocks != 2) ||
+      (blocks == 1 && !rank) || (blocks == 2 && ((n & 1) || (new_pad & 1))))
+    return fail(ctx, TTN_EINVAL,
+                "bad arguments (rows <= batch, n <= 128, or <= 64 per block, new_pad <= workspace)");
   if (g_elems < (int64_t)rows * n * n || w_elems < (int64_t)rows * new_pad * n)
     return fail(ctx, TTN_EINVAL, "buffers too small for the factorisation");
   EighDesc ed{};
@@ -2325,8 +2346,18 @@ ttn_status ttn_test_move(ttn_ctx* ctx, int32_t rows, int32_t n, int32_t new_pad,
   ed.W_iso = W_iso; ed.W_abs = W_abs; ed.out_c128 = ctx->c128;
   ed.blocks = blocks;
   ed.rank_out = blocks == 1 ? rank : nullptr; ed.rank_stride = 1;
+  const bool tried = blocks == 1 && n > 64;
+  if (tried) ed.done = ctx->qr_done;
   TTN_CHECK_HIP(launch_pchol(ed, rows, ctx->st));
   TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
+  if (tried) {
+    std::vector<int> dn(rows), rk(rows);
+    TTN_CHECK_HIP(hipMemcpy(dn.data(), ctx->qr_done, rows * sizeof(int), hipMemcpyDeviceToHost));
+    TTN_CHECK_HIP(hipMemcpy(rk.data(), rank, rows * sizeof(int), hipMemcpyDeviceToHost));
+    for (int t = 0; t < rows; ++t)
+      if (!dn[t]) rk[t] = -1;
+    TTN_CHECK_HIP(hipMemcpy(rank, rk.data(), rows * sizeof(int), hipMemcpyHostToDevice));
+  }
   return TTN_OK;
 }
 

@@ -247,7 +247,8 @@ def test_eigh_zero_rows_are_compacted(dtype, n, blocks):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("n,rank,blocks", [(1, 1, 1), (5, 3, 1), (16, 16, 1), (40, 17, 1), (64, 64, 1), (64, 30, 1),
-                                           (32, 9, 2), (128, 50, 2)])
+                                           (32, 9, 2), (128, 50, 2), (65, 65, 1), (100, 70, 1), (128, 128, 1),
+                                           (128, 20, 1)])
 def test_exact_move_factors(dtype, n, rank, blocks):
     # pivoted Cholesky centre move: x W_iso^T must be an isometry and, since
     # nothing above the cutoff is dropped, (x W_iso^T) W_abs must rebuild the
@@ -277,7 +278,7 @@ def test_exact_move_factors(dtype, n, rank, blocks):
     for b in range(blocks):
         sl = slice(b * h, (b + 1) * h)
         G[:, sl, sl] = np.einsum("tki,tkj->tij", M[:, :, sl].conj(), M[:, :, sl])
-    eng = _engine(dtype, chi=64)
+    eng = _engine(dtype, chi=64 if n <= 64 or blocks == 2 else 128)
     Gd = torch.view_as_real(torch.as_tensor(G)).contiguous().cuda()
     wdt = torch.float64 if dtype == "c128" else torch.float32
     Wi = torch.full((rows, n, n, 2), 7.0, dtype=wdt, device="cuda")
@@ -439,4 +440,41 @@ def test_eigh_degenerate_diagonal_converges(dtype, m):
         assert np.abs(iso - np.eye(cap)).max() < tol, t
         rec = Wa[t].conj().T @ Wa[t] * np.trace(Gk).real     # W_abs is renormalised by the kept weight
         assert np.abs(rec - Gk).max() < tol, (t, np.abs(rec - Gk).max())
+    eng.close()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_exact_move_try_leaves_wide_rows_to_the_eigensolver(dtype):
+    # 65..128 columns without blocks: the pivoted Cholesky is the batch
+    # driver's try before a truncating eigen-decomposition; rows whose rank
+    # at the cutoff exceeds the cap report -1 and leave W untouched, the
+    # others get exact factors (rank at the cutoff <= cap)
+    from paper_2511_05719_amd._abi import lib, check
+    g = np.random.default_rng(11)
+    rows, n, cap, K = 4, 96, 40, 200
+    ranks = [30, 40, 41, 70]
+    M = np.zeros((rows, K, n), complex)
+    for t, r in enumerate(ranks):
+        M[t] = (g.normal(size=(K, r)) + 1j * g.normal(size=(K, r))) @ (g.normal(size=(r, n)) + 1j * g.normal(size=(r, n)))
+        M[t] /= np.linalg.norm(M[t])
+    G = np.einsum("tki,tkj->tij", M.conj(), M)
+    eng = _engine(dtype, chi=128)
+    Gd = torch.view_as_real(torch.as_tensor(G)).contiguous().cuda()
+    wdt = torch.float64 if dtype == "c128" else torch.float32
+    Wi = torch.full((rows, cap, n, 2), 7.0, dtype=wdt, device="cuda")
+    Wa = torch.full((rows, cap, n, 2), 7.0, dtype=wdt, device="cuda")
+    rk = torch.full((rows,), -2, dtype=torch.int32, device="cuda")
+    check(lib().ttn_test_move(eng._ctx, rows, n, cap, cap, 1e-10, Gd.data_ptr(), rows * n * n, Wi.data_ptr(),
+                              Wa.data_ptr(), rows * cap * n, rk.data_ptr(), 1), eng._ctx)
+    Wi, Wa, rk = _host_complex(Wi), _host_complex(Wa), rk.cpu().numpy()
+    tol = 1e-9 if dtype == "c128" else 3e-5
+    for t, r in enumerate(ranks):
+        if r > cap:
+            assert rk[t] == -1 and np.all(Wi[t] == 7 + 7j) and np.all(Wa[t] == 7 + 7j), t
+            continue
+        assert rk[t] == r, (t, rk[t])
+        Q = M[t] @ Wi[t, :r].T
+        assert np.abs(Q.conj().T @ Q - np.eye(r)).max() < 10 * tol
+        assert np.abs(Q @ Wa[t, :r] - M[t]).max() < tol
+        assert np.all(Wi[t, r:] == 0) and np.all(Wa[t, r:] == 0)
     eng.close()
