@@ -1508,20 +1508,22 @@ __global__ void __launch_bounds__(64 * NW) k_pchol(EighDesc d) {
   }
 }
 
-// Problems of 65 to 128 columns (one row, no blocks): the same sweep with
-// the rows in registers.  Eight waves; wave w holds rows i = 8 q + w (q <
-// 16), lane j columns j and j + 64 of each.  At each step the wave owning
-// the pivot row publishes it through LDS (two buffers by the step's parity,
-// one barrier per step), every wave updates its own rows in registers, and
-// the owner then keeps the row's final values in place of the residual.
-// With d.done set (the try before a truncating eigen-decomposition): a
-// problem whose weight above the cutoff needs more than the cap's pivots
-// writes done = 0 and nothing else, the others write their factors and
-// done = 1.  Without it the factorisation stops at the cap.
-template <int NMAX>
-__global__ void __launch_bounds__(512) k_pchol_reg(EighDesc d) {
-  static_assert(NMAX == 128, "two columns per lane, sixteen rows per wave");
-  constexpr int NW = 8, RPW = NMAX / NW, CPL = NMAX / 64;
+// The same sweep with the rows in registers, for problems of 33 to 128
+// columns: NW waves (4 for 64 columns, 8 for 128), wave w holding rows i =
+// NW q + w and lane j columns j + 64 s of each.  At each step the wave
+// owning the pivot row publishes it through LDS (two buffers by the step's
+// parity, one barrier per step), every wave updates its own rows in
+// registers, and the owner then keeps the row's final values in place of
+// the residual.  Block-diagonal problems (blocks = 2, one workgroup per
+// block) as in k_pchol.  With d.done set (the try before a truncating
+// eigen-decomposition, no blocks): a problem whose weight above the cutoff
+// needs more than the cap's pivots writes done = 0 and nothing else, the
+// others write their factors and done = 1.  Without it the factorisation
+// stops at the cap.
+template <int NMAX, int NW>
+__global__ void __launch_bounds__(64 * NW) k_pchol_reg(EighDesc d) {
+  static_assert((NMAX == 64 || NMAX == 128) && NMAX % NW == 0 && 64 % NW == 0, "rows over waves, columns over lanes");
+  constexpr int RPW = NMAX / NW, CPL = NMAX / 64, KB = NMAX;   // KB: index field of the pivot key
   __shared__ int cidx[NMAX], inv[NMAX], wcount[NW];
   __shared__ int pos[NMAX], order[NMAX];
   __shared__ double2 pbuf[2][NMAX];
@@ -1557,15 +1559,17 @@ __global__ void __launch_bounds__(512) k_pchol_reg(EighDesc d) {
   own = wave_sum_d(own);
   if (lane == 0) { red[0][wave] = part; red[1][wave] = own; }
   __syncthreads();
-  double tr = 0.0, mine = 0.0;
+  double tr = 0.0;
 #pragma unroll
   for (int w = 0; w < NW; ++w) tr += red[0][w];
-  // (every wave holds every column's diagonal: the problem's trace once)
-  mine = red[1][0];
+  const double mine = red[1][0];          // (every wave holds every column's diagonal)
   const bool finite = isfinite(tr) && tr > 0.0;
-  const double tol = d.cutoff * mine;
+  const double tot = d.blocks > 1 ? tr : mine;
+  const double tol = d.cutoff * tot;
   const int lim = min(min(d.cap, pb.pad), n);
-  unsigned long long piv[CPL] = {0ull, 0ull};          // pivoted columns (uniform)
+  unsigned long long piv[CPL];                          // pivoted columns (uniform)
+#pragma unroll
+  for (int s = 0; s < CPL; ++s) piv[s] = 0ull;
   int k = 0;
   bool fail = false;
   if (finite) {
@@ -1575,12 +1579,13 @@ __global__ void __launch_bounds__(512) k_pchol_reg(EighDesc d) {
       for (int s = 0; s < CPL; ++s) {
         const int c = lane + 64 * s;
         if (c < n && !((piv[s] >> lane) & 1ull))
-          key = max(key, ((__float_as_uint((float)fmax(dj[s], 0.0)) + 128u) & ~127u) | (unsigned)(127 - c));
+          key = max(key, ((__float_as_uint((float)fmax(dj[s], 0.0)) + (unsigned)KB) & ~(unsigned)(KB - 1)) |
+                             (unsigned)(KB - 1 - c));
       }
       key = wave_max_u32(key);
       if (key == 0u) break;
-      const int p = 127 - (int)(key & 127u);
-      const double dm = readlane_d(p >= 64 ? dj[1] : dj[0], p & 63);
+      const int p = KB - 1 - (int)(key & (unsigned)(KB - 1));
+      const double dm = readlane_d(CPL > 1 && p >= 64 ? dj[CPL - 1] : dj[0], p & 63);
       if (!(dm > tol) || !isfinite(dm)) break;         // (uniform: every wave alike)
       if (k == lim) { fail = true; break; }            // weight above the cutoff beyond the cap
       const double rkk = sqrt(dm);
@@ -1608,8 +1613,9 @@ __global__ void __launch_bounds__(512) k_pchol_reg(EighDesc d) {
         w[s] = colj[s] ? u[s] : z[s];
         if (colj[s]) dj[s] = fma(-u[s].x, u[s].x, fma(-u[s].y, u[s].y, dj[s]));
       }
-      if (p >= 64) piv[1] |= 1ull << (p - 64);
-      else piv[0] |= 1ull << p;
+#pragma unroll
+      for (int s = 0; s < CPL; ++s)
+        if ((p >> 6) == s) piv[s] |= 1ull << (p & 63);
       if (owner) {
 #pragma unroll
         for (int q = 0; q < RPW; ++q)
@@ -1621,10 +1627,11 @@ __global__ void __launch_bounds__(512) k_pchol_reg(EighDesc d) {
       // each remaining row j: A_jc -= conj(u_j) u_c (remaining c), y_j -= u_j z_k
 #pragma unroll
       for (int q = 0; q < RPW; ++q) {
-        const int i = NW * q + wave;                    // (q / 8: the word and register half of row i)
-        if (i < n && !((piv[q / 8] >> (i & 63)) & 1ull)) {
-          const double ujx = readlane_d(arow[q / 8].x, i & 63) * irkk;
-          const double ujy0 = readlane_d(arow[q / 8].y, i & 63) * irkk;
+        const int i = NW * q + wave;
+        const int wi = (q * NW) / 64;                   // (the word and register half of row i)
+        if (i < n && !((piv[wi] >> (i & 63)) & 1ull)) {
+          const double ujx = readlane_d(arow[wi].x, i & 63) * irkk;
+          const double ujy0 = readlane_d(arow[wi].y, i & 63) * irkk;
 #pragma unroll
           for (int s = 0; s < CPL; ++s) {
             const int c = lane + 64 * s;
@@ -1655,37 +1662,53 @@ __global__ void __launch_bounds__(512) k_pchol_reg(EighDesc d) {
   const double kept = fmax(mine - resid, 0.0);
   double scale;
   int kk = r;
-  if (!(kept > 0.0) || !isfinite(kept) || r == 0) {
+  if (d.blocks > 1) {
+    scale = finite ? 1.0 / sqrt(tr) : 0.0;
+  } else if (!(kept > 0.0) || !isfinite(kept) || r == 0) {
     kk = 0;
     scale = 0.0;
   } else {
     scale = 1.0 / sqrt(kept);
   }
   if (threadIdx.x == 0) {
-    if (kk == 0 && d.flags) d.flags[t] |= 1;
-    if (d.disc_acc && mine > 0.0) d.disc_acc[t] += (mine - kept) / mine;
-    if (d.rank_out) d.rank_out[t * d.rank_stride] = kk;
-    if (d.rank_max) d.rank_max[t * d.rank_stride] = max(d.rank_max[t * d.rank_stride], kk);
-    if (d.flops_acc)
-      d.flops_acc[t] += 8.0 * ((double)r * r * (3.0 * n - 2.0 * r) / 3.0 + (double)r * r * r / 3.0);
+    if (d.blocks > 1) {
+      if (!finite && d.flags) atomicOr(d.flags + t, 1);
+      if (d.disc_acc && tot > 0.0) atomicAdd(d.disc_acc + t, (mine - kept) / tot);
+    } else {
+      if (kk == 0 && d.flags) d.flags[t] |= 1;
+      if (d.disc_acc && tot > 0.0) d.disc_acc[t] += (tot - kept) / tot;
+      if (d.rank_out) d.rank_out[t * d.rank_stride] = kk;
+      if (d.rank_max) d.rank_max[t * d.rank_stride] = max(d.rank_max[t * d.rank_stride], kk);
+    }
+    if (d.flops_acc) {
+      const double f = 8.0 * ((double)r * r * (3.0 * n - 2.0 * r) / 3.0 + (double)r * r * r / 3.0);
+      if (d.blocks > 1) atomicAdd(d.flops_acc + t, f);
+      else d.flops_acc[t] += f;
+    }
     if (d.nk_out) {
-      d.nk_out[t * 4] = r;
-      d.nk_out[t * 4 + 1] = kk;
-      d.nk_out[t * 4 + 2] = 0;
-      d.nk_out[t * 4 + 3] = 0;
+      d.nk_out[t * 4 + 2 * pb.k] = r;
+      d.nk_out[t * 4 + 2 * pb.k + 1] = kk;
+      if (d.blocks <= 1) { d.nk_out[t * 4 + 2] = 0; d.nk_out[t * 4 + 3] = 0; }
     }
     if (d.sweeps_out) d.sweeps_out[t] = 0;
   }
   __syncthreads();                                      // pos, order
-  // zeros: rows a >= kk, and the dead columns of the kept rows
+  // zeros: rows a >= kk, the dead columns of the kept rows, and the other
+  // block's columns of every row of this block
   const long long base = t * (long long)d.new_pad * d.n;
   const int nr = pb.n;
   for (int idx = threadIdx.x; idx < pb.pad * nr; idx += blockDim.x) {
     const int a = idx / nr, i = idx - (idx / nr) * nr;
-    if (a < kk && inv[i] >= 0) continue;
-    const long long o = base + (long long)(pb.pad_off + a) * d.n + pb.off + i;
-    if (d.out_c128) { ((double2*)d.W_iso)[o] = make_double2(0, 0); ((double2*)d.W_abs)[o] = make_double2(0, 0); }
-    else { ((float2*)d.W_iso)[o] = make_float2(0, 0); ((float2*)d.W_abs)[o] = make_float2(0, 0); }
+    if (!(a < kk && inv[i] >= 0)) {
+      const long long o = base + (long long)(pb.pad_off + a) * d.n + pb.off + i;
+      if (d.out_c128) { ((double2*)d.W_iso)[o] = make_double2(0, 0); ((double2*)d.W_abs)[o] = make_double2(0, 0); }
+      else { ((float2*)d.W_iso)[o] = make_float2(0, 0); ((float2*)d.W_abs)[o] = make_float2(0, 0); }
+    }
+    if (d.blocks > 1) {
+      const long long o2 = base + (long long)(pb.pad_off + a) * d.n + (1 - pb.k) * pb.n + i;
+      if (d.out_c128) { ((double2*)d.W_iso)[o2] = make_double2(0, 0); ((double2*)d.W_abs)[o2] = make_double2(0, 0); }
+      else { ((float2*)d.W_iso)[o2] = make_float2(0, 0); ((float2*)d.W_abs)[o2] = make_float2(0, 0); }
+    }
   }
   // the kept rows, from the registers of the waves that own their pivots:
   // W_abs row a = R[a] on the columns pivoted at step a or later (scaled),
@@ -1717,10 +1740,10 @@ hipError_t launch_pchol(const EighDesc& d, int batch, hipStream_t st) {
     return hipErrorInvalidValue;
   const int nsub = d.n / nb;
   const dim3 grid((unsigned)((long long)batch * nb));
-  if (nsub > 64) hipLaunchKernelGGL((k_pchol_reg<128>), grid, dim3(512), 0, st, d);
+  if (nsub > 64) hipLaunchKernelGGL((k_pchol_reg<128, 8>), grid, dim3(512), 0, st, d);
   else if (nsub <= 16) hipLaunchKernelGGL((k_pchol<16, 1>), grid, dim3(64), 0, st, d);
   else if (nsub <= 32) hipLaunchKernelGGL((k_pchol<32, 2>), grid, dim3(128), 0, st, d);
-  else hipLaunchKernelGGL((k_pchol<64, 4>), grid, dim3(256), 0, st, d);
+  else hipLaunchKernelGGL((k_pchol_reg<64, 4>), grid, dim3(256), 0, st, d);
   return hipGetLastError();
 }
 
