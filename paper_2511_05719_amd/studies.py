@@ -12,12 +12,16 @@ return plain dicts, and a command line that writes them as JSON.
   Table III), measured on the engine's bonds.
 * threshold_sweep: failure rates over a grid of noise strengths at d = 3, 5
   and the fit of Eq. 8 (threshold tau and exponent nu, Table I).
+* distance7: the d = 7 workload at chi = 128 (73 qubits, 7 rounds, SRX
+  theta = 0.08 and amplitude damping gamma = 3e-3 at every location,
+  clustered layout), run in the largest batches that fit the device: its
+  failure rate, throughput and device memory per trajectory.
 
 Every figure is a logical failure rate of the final-data lookup decoder with
 its 99% Wilson interval; the paper's own decoder and schedule are not
 available, so the values are this schedule's, not Table I's or Fig. 5's.
 
-Usage:  python -m paper_2511_05719_amd.studies {pta,truncation,table3,threshold} [--out FILE]
+Usage:  python -m paper_2511_05719_amd.studies {pta,truncation,table3,threshold,d7} [--out FILE]
 """
 from __future__ import annotations
 
@@ -217,13 +221,58 @@ def threshold_sweep(model: str, strengths, distances=(3, 5), rounds: int = 1, sh
     return out
 
 
+def distance7(shots: int = 4096, rounds: int = 7, theta: float = 0.08, gamma: float = 3e-3, chi: int = 128,
+              batch: int = 96, seed: int = 7) -> dict:
+    """The d = 7 colour code at chi = 128 in batches of `batch` rows: a node
+    buffer holds its largest shape (two legs at 2 chi on a controlled gate's
+    path) for every row, ~2 GB per row here, so a context takes about a
+    hundred rows and the shots run as consecutive batches (trajectory ids
+    continue across batches, so the result does not depend on the split)."""
+    from workload import build_circuit
+    circ = build_circuit(7, rounds, "srx+ad", leaf_of_qubit="optimized")
+    batch = min(batch, shots)
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    eng = TTNEngine(circ.n_qubits, batch, circ.leaf_of_qubit, chi_max=chi, cutoff=1e-10, dtype="c64", seed=seed)
+    free1, _ = torch.cuda.mem_get_info()
+    ol = eng.upload(circ)
+    fails = done = 0
+    disc = 0.0
+    max_rank = 1
+    t0 = time.perf_counter()
+    while done < shots:
+        res = eng.run_circuit(ol, theta=theta, gamma=gamma, traj_offset=done, stats=True)
+        f = eng.decode(res.records, circ.data_rec, circ.code.checks).cpu().numpy()
+        take = min(batch, shots - done)
+        fails += int(f[:take].sum())
+        done += take
+        disc += res.stats["discarded_weight"] * take / batch
+        max_rank = max(max_rank, res.stats["max_rank"])
+        print(f"  {done}/{shots} shots, {fails} failures, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    eng.close()
+    lo, hi = wilson(fails, done)
+    n_ops = len(circ.ops)
+    return {"study": "d = 7 colour code at chi = 128 (config 4 shape)", "d": 7, "qubits": circ.n_qubits,
+            "rounds": rounds, "theta": theta, "gamma": gamma, "chi_max": chi, "layout": "clustered",
+            "dtype": "c64", "batch": batch, "shots": done, "failures": fails, "p_fail": fails / done,
+            "ci99": [lo, hi], "mean_discarded_weight": disc / done, "max_rank": max_rank, "seconds": dt,
+            "shots_per_s": done / dt, "trajectory_gates_per_s": done * n_ops / dt, "ops_per_shot": n_ops,
+            "device_gib": (free0 - free1) / 2 ** 30, "device_mib_per_row": (free0 - free1) / 2 ** 20 / batch}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description="the paper's studies on the batched engine")
-    ap.add_argument("study", choices=("pta", "truncation", "table3", "threshold"))
+    ap.add_argument("study", choices=("pta", "truncation", "table3", "threshold", "d7"))
     ap.add_argument("--out", default=None)
     ap.add_argument("--shots", type=int, default=None)
+    ap.add_argument("--batch", type=int, default=96)
     a = ap.parse_args(argv)
-    if a.study == "pta":
+    if a.study == "d7":
+        res = distance7(shots=a.shots or 4096, batch=a.batch)
+    elif a.study == "pta":
         res = pta_comparison(shots=a.shots or 10000)
     elif a.study == "truncation":
         res = {"studies": [truncation_background(3, (1, 2, 4, 8), a.shots or 10000),
