@@ -340,7 +340,11 @@ int32_t ttn_test_sweep_plan(int32_t k, uint32_t* groups, int32_t cap);
  *  ttn_test_gram: G[t][i][j] = sum over the other legs of
  *    conj(T[..i..]) T[..j..], G float64 [ksplit][rows][n][n][2] (FP64
  *    accumulation): with ksplit > 1 the sum runs in ksplit parts, one per
- *    slice, and G is the sum of the slices.
+ *    slice, and G is the sum of the slices.  G is Hermitian and, as in the
+ *    engine, output tiles wholly below the diagonal are not written: every
+ *    i <= j is (the upper triangle the solvers read).
+ *  ttn_test_eigh, ttn_test_move: read only the upper triangle (i <= j) of
+ *    each row's G.
  *  ttn_test_eigh: the factors of a centre move computed from G (as in
  *    ttn_ctx's hops): W_iso[t][a][i] = V[i][a] / s_a, W_abs[t][a][i] =
  *    conj(V[i][a]) s_a / |s_kept|, a < rank[t] in descending s, zero beyond;

@@ -103,6 +103,12 @@ __device__ inline double2 gram_at(const EighDesc& d, const double2* G, long long
   return v;
 }
 
+// entry (r, c) of a row's Hermitian Gram matrix from its upper triangle
+// (the Gram launch skips the output tiles wholly below the diagonal)
+__device__ inline double2 gram_herm(const EighDesc& d, const double2* G, int r, int c) {
+  return r <= c ? gram_at(d, G, (long long)r * d.n + c) : cconj(gram_at(d, G, (long long)c * d.n + r));
+}
+
 struct Problem {       // one diagonal block of one trajectory's matrix
   long long t;
   int k;               // block index
@@ -1106,7 +1112,7 @@ __global__ void __launch_bounds__(256) k_jacobi_wave(EighDesc d, long long nprob
   double2* V = Vs[wave];
   for (int idx = lane; idx < n2 * n2; idx += 64) {
     const int i = idx / n2, j = idx - (idx / n2) * n2;
-    G[idx] = (i < n && j < n) ? gram_at(d, Gg, (long long)(pb.off + cidx[i]) * d.n + pb.off + cidx[j])
+    G[idx] = (i < n && j < n) ? gram_herm(d, Gg, pb.off + cidx[i], pb.off + cidx[j])
                               : make_double2(0.0, 0.0);
     V[idx] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
@@ -1358,7 +1364,7 @@ __global__ void __launch_bounds__(64 * NW) k_pchol(EighDesc d) {
   // launcher picks NMAX >= pb.n)
   const int n = compact_rows<NW>(d, G, pb, cidx, inv, wcount);
   for (int i = wave; i < n; i += NW)
-    if (lane < n) A[i * LD + lane] = gram_at(d, G, (long long)(pb.off + cidx[i]) * d.n + pb.off + cidx[lane]);
+    if (lane < n) A[i * LD + lane] = gram_herm(d, G, pb.off + cidx[i], pb.off + cidx[lane]);
   if (threadIdx.x < NMAX) pos[threadIdx.x] = -1;
   // trace of the whole matrix (both blocks), and of this problem
   double part = 0.0, own = 0.0;
@@ -1542,7 +1548,7 @@ __global__ void __launch_bounds__(64 * NW) k_pchol_reg(EighDesc d) {
 #pragma unroll
     for (int s = 0; s < CPL; ++s) {
       const int i = NW * q + wave, c = lane + 64 * s;
-      A[q][s] = (i < n && c < n) ? gram_at(d, G, (long long)(pb.off + cidx[i]) * d.n + pb.off + cidx[c])
+      A[q][s] = (i < n && c < n) ? gram_herm(d, G, pb.off + cidx[i], pb.off + cidx[c])
                                  : make_double2(0.0, 0.0);
     }
   double dj[CPL];

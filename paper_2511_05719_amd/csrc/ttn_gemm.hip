@@ -94,12 +94,14 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
   const int tile_m = blockIdx.y;
   const int z = blockIdx.z;
   const int m0 = tile_m * TM, n0 = tile_n * TN;
+  if (d.herm && m0 >= n0 + TN) return;           // (uniform) a tile wholly below the diagonal
 
   const SA* A = (const SA*)d.A + t * d.sAt + h * d.sAh + g * d.sAg;
   const SB* B = (const SB*)d.B + t * d.sBt + h * d.sBh + g * d.sBg;
   SC* C = (SC*)d.C + t * d.sCt + h * d.sCh + g * d.sCg + z * d.sCz;
   const R sgnA = d.conjA ? (R)-1 : (R)1;
   const R sgnB = d.conjB ? (R)-1 : (R)1;
+  const R bsg = sgnA * sgnB;        // staged A's imaginary part as B's (same_ab)
 
   // this trajectory's extents: rows, columns and K terms that can be
   // non-zero; a tile beyond them only writes its zeros.  A split N index
@@ -194,6 +196,10 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
     return __umul24((unsigned)q, s1) + __umul24((unsigned)(gk - q * Kin), s2);
   };
 
+  // a diagonal tile of a Gram matrix reads its B fragments from the staged
+  // A (same rows, the conjugation undone by the sign), so B is neither
+  // fetched nor staged
+  const bool same = TM == TN && d.same_ab && tile_m == tile_n;
   R ra_re[AE], ra_im[AE], rb_re[BE], rb_im[BE];
   auto fetch = [&](int k0) {
 #pragma unroll
@@ -204,6 +210,7 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
       ra_re[r] = (R)re;
       ra_im[r] = (R)im * sgnA;
     }
+    if (same) return;
 #pragma unroll
     for (int r = 0; r < BE; ++r) {
       const int gk = k0 + b_kk[r];
@@ -223,6 +230,7 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
       As0[a_ls[r]] = ra_re[r];
       As1[a_ls[r]] = ra_im[r];
     }
+    if (same) return;
 #pragma unroll
     for (int r = 0; r < BE; ++r) {
       Bs0[b_ls[r]] = rb_re[r];
@@ -246,8 +254,8 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
         const int nj = wn * 32 + s * 16 + li;
         a_re[s] = As[0][kr][mi];
         a_im[s] = As[1][kr][mi];
-        b_re[s] = Bs[0][kr][nj];
-        b_im[s] = Bs[1][kr][nj];
+        b_re[s] = same ? As[0][kr][nj] : Bs[0][kr][nj];
+        b_im[s] = same ? bsg * As[1][kr][nj] : Bs[1][kr][nj];
       }
       // the eight accumulators are independent: issue each of the four real
       // products for all of them before the next, so that consecutive MFMAs

@@ -27,6 +27,10 @@ struct GemmDesc {
   long long sCz;            // element stride between the partial products of C
   int conjA, conjB;
   int a_m_fast, b_n_fast;   // operand dimension that is unit-stride on load
+  int same_ab;              // A and B are one operand with one layout (a Gram matrix): a
+                            // diagonal tile of a square tile shape stages it once
+  int herm;                 // C is Hermitian: output tiles wholly below the diagonal are
+                            // neither computed nor written (readers use the upper triangle)
   int tilesN;               // filled by the launcher
   // Per-trajectory extents (all optional).  A node tensor is stored padded
   // to the batch's largest bond dimensions, and trajectory t's entries are

@@ -356,6 +356,8 @@ static GemmDesc gram_desc(const void* T, std::array<int, 3> d, int leg, double2*
   g.H = 1;
   const long long sT = elems(d);
   g.conjA = 1;
+  g.same_ab = 1;
+  g.herm = 1;
   g.A = T; g.B = T; g.sAt = sT; g.sBt = sT;
   g.C = G; g.sCt = (long long)n * n; g.sCi = n; g.sCj = 1;
   g.M = n; g.N = n;
