@@ -14,7 +14,9 @@
 //
 // Tiling: a 256-thread workgroup (4 wave64).  Each wave owns a 32 x 32
 // output block built from 2 x 2 MFMA 16x16x4 tiles; a complex
-// multiply-accumulate is four real MFMAs (re*re, -im*im, re*im, im*re).  The
+// multiply-accumulate is three real MFMAs with FP32 accumulation (re*re,
+// im*im, (re+im)*(re+im)) and four with FP64 (re*re, -im*im, re*im,
+// im*re).  The
 // waves are arranged WM x WN over the output tile (32 WM x 32 WN), or, for
 // outputs of at most 32 x 32 (KW = 4), all four share one 32 x 32 block and
 // each takes a quarter of every K chunk, reduced through LDS at the end.  K
@@ -52,12 +54,6 @@ template <> struct MfmaAcc<double> {
 // column of 16 staged stores free of bank conflicts; 8-byte elements use 1
 template <typename R> struct Pad { static constexpr int value = 17; };
 template <> struct Pad<double> { static constexpr int value = 1; };
-
-template <typename S> __device__ inline void load_c(const S* p, long long off, double& re, double& im) {
-  S v = p[off];
-  re = (double)v.x;
-  im = (double)v.y;
-}
 
 template <typename SA, typename SB, typename SC, typename R, int WM, int WN, int KW>
 __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
@@ -139,13 +135,22 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
   const int kbeg = z * per * TK;
   const int kend = min(Kt, kbeg + per * TK);
 
-  acc_t acc_re[2][2], acc_im[2][2];
+  // complex64 products accumulated in FP32 take the three-product form of
+  // the complex product (Gauss; Higham, "Stability of a method for
+  // multiplying complex matrices with three real matrix multiplications",
+  // 1992): a quarter fewer MFMAs, an imaginary part with about twice the
+  // conventional rounding bound.  FP64 accumulation (Gram matrices,
+  // complex128) keeps the four-product form: its third accumulator set
+  // would cost a wave per SIMD, which ate the saving.
+  constexpr bool M3 = sizeof(R) == 4;
+  acc_t acc_re[2][2], acc_im[2][2], acc_ii[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       acc_re[a][b] = (acc_t){0, 0, 0, 0};
       acc_im[a][b] = (acc_t){0, 0, 0, 0};
+      acc_ii[a][b] = (acc_t){0, 0, 0, 0};
     }
   const int li = lane & 15, lk = lane >> 4;
 
@@ -200,24 +205,30 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
   // A (same rows, the conjugation undone by the sign), so B is neither
   // fetched nor staged
   const bool same = TM == TN && d.same_ab && tile_m == tile_n;
-  R ra_re[AE], ra_im[AE], rb_re[BE], rb_im[BE];
+  // the fetched elements stay as loaded until they are staged: no
+  // arithmetic on them between the load and the MFMAs of the current chunk,
+  // so the wave does not wait for the next chunk's loads before computing
+  SA ra[AE];
+  SB rb[BE];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < AE; ++r) {
       const int gk = k0 + a_kk[r];
-      double re = 0.0, im = 0.0;
-      if (a_ro[r] >= 0 && gk < kend) load_c(A, (long long)(a_ro[r] + kpart(gk, sA1, sA2)), re, im);
-      ra_re[r] = (R)re;
-      ra_im[r] = (R)im * sgnA;
+      SA v;
+      v.x = 0;
+      v.y = 0;
+      if (a_ro[r] >= 0 && gk < kend) v = A[a_ro[r] + kpart(gk, sA1, sA2)];
+      ra[r] = v;
     }
     if (same) return;
 #pragma unroll
     for (int r = 0; r < BE; ++r) {
       const int gk = k0 + b_kk[r];
-      double re = 0.0, im = 0.0;
-      if (b_co[r] >= 0 && gk < kend) load_c(B, (long long)(b_co[r] + kpart(gk, sB1, sB2)), re, im);
-      rb_re[r] = (R)re;
-      rb_im[r] = (R)im * sgnB;
+      SB v;
+      v.x = 0;
+      v.y = 0;
+      if (b_co[r] >= 0 && gk < kend) v = B[b_co[r] + kpart(gk, sB1, sB2)];
+      rb[r] = v;
     }
   };
   R* As0 = &As[0][0][0];
@@ -227,16 +238,21 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
   auto stage = [&]() {
 #pragma unroll
     for (int r = 0; r < AE; ++r) {
-      As0[a_ls[r]] = ra_re[r];
-      As1[a_ls[r]] = ra_im[r];
+      As0[a_ls[r]] = (R)ra[r].x;
+      As1[a_ls[r]] = (R)ra[r].y * sgnA;
     }
     if (same) return;
 #pragma unroll
     for (int r = 0; r < BE; ++r) {
-      Bs0[b_ls[r]] = rb_re[r];
-      Bs1[b_ls[r]] = rb_im[r];
+      Bs0[b_ls[r]] = (R)rb[r].x;
+      Bs1[b_ls[r]] = (R)rb[r].y * sgnB;
     }
   };
+  // B fragments: from the staged B, or for a diagonal Gram tile from the
+  // staged A with the conjugation undone by the sign (no branch in the loop)
+  const R* Bf = same ? As0 : Bs0;
+  const int bplane = same ? TK * (TM + PADL) : TK * (TN + PADL);
+  const R bfs = same ? bsg : (R)1;
 
   if (kbeg < kend) fetch(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += TK) {
@@ -254,31 +270,62 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
         const int nj = wn * 32 + s * 16 + li;
         a_re[s] = As[0][kr][mi];
         a_im[s] = As[1][kr][mi];
-        b_re[s] = same ? As[0][kr][nj] : Bs[0][kr][nj];
-        b_im[s] = same ? bsg * As[1][kr][nj] : Bs[1][kr][nj];
+        b_re[s] = Bf[kr * (TN + PADL) + nj];
+        b_im[s] = bfs * Bf[bplane + kr * (TN + PADL) + nj];
       }
-      // the eight accumulators are independent: issue each of the four real
-      // products for all of them before the next, so that consecutive MFMAs
-      // never wait on one another's result
-      R na_im[2] = {-a_im[0], -a_im[1]};
+      // the accumulators are independent: issue each real product for all
+      // of them before the next, so that consecutive MFMAs never wait on one
+      // another's result
+      if constexpr (M3) {
+        // three real products: re.re, im.im and (re+im).(re+im)
+        const R sa[2] = {a_re[0] + a_im[0], a_re[1] + a_im[1]};
+        const R sb[2] = {b_re[0] + b_im[0], b_re[1] + b_im[1]};
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc_re[a][b] = MfmaAcc<R>::mma(a_re[a], b_re[b], acc_re[a][b]);
+          for (int b = 0; b < 2; ++b) acc_re[a][b] = MfmaAcc<R>::mma(a_re[a], b_re[b], acc_re[a][b]);
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc_im[a][b] = MfmaAcc<R>::mma(a_re[a], b_im[b], acc_im[a][b]);
+          for (int b = 0; b < 2; ++b) acc_ii[a][b] = MfmaAcc<R>::mma(a_im[a], b_im[b], acc_ii[a][b]);
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc_re[a][b] = MfmaAcc<R>::mma(na_im[a], b_im[b], acc_re[a][b]);
+          for (int b = 0; b < 2; ++b) acc_im[a][b] = MfmaAcc<R>::mma(sa[a], sb[b], acc_im[a][b]);
+      } else {
+        const R na_im[2] = {-a_im[0], -a_im[1]};
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc_im[a][b] = MfmaAcc<R>::mma(a_im[a], b_re[b], acc_im[a][b]);
+          for (int b = 0; b < 2; ++b) acc_re[a][b] = MfmaAcc<R>::mma(a_re[a], b_re[b], acc_re[a][b]);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc_im[a][b] = MfmaAcc<R>::mma(a_re[a], b_im[b], acc_im[a][b]);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc_re[a][b] = MfmaAcc<R>::mma(na_im[a], b_im[b], acc_re[a][b]);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc_im[a][b] = MfmaAcc<R>::mma(a_im[a], b_re[b], acc_im[a][b]);
+      }
     }
     __syncthreads();
+  }
+  if constexpr (M3) {
+    // re = re.re - im.im, im = (re+im).(re+im) - re.re - im.im
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const R p1 = acc_re[a][b][r], p2 = acc_ii[a][b][r];
+          acc_re[a][b][r] = p1 - p2;
+          acc_im[a][b][r] = acc_im[a][b][r] - p1 - p2;
+        }
   }
   if (KW > 1) {
     // waves kw > 0 hand their partial sums to wave 0 (the staging buffers
@@ -322,6 +369,7 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
         const int gj = n0 + wn * 32 + b * 16 + li;
         if (gi < d.M && gj < d.N) {
           double2 v = make_double2((double)acc_re[a][b][r], (double)acc_im[a][b][r]);
+          if (d.herm && gi == gj) v.y = 0.0;    // a Hermitian matrix's real diagonal
           long long oj = (long long)gj * d.sCj;
           if (nsplit) {
             const int q = gj / d.Nin;
