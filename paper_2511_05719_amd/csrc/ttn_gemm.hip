@@ -58,7 +58,8 @@ template <> struct Pad<double> { static constexpr int value = 1; };
 template <typename SA, typename SB, typename SC, typename R, int WM, int WN, int KW>
 __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
   static_assert(WM * WN * KW == 4, "four waves per workgroup");
-  constexpr int TM = 32 * WM, TN = 32 * WN, TK = 16 * KW;
+  constexpr int KPW = 16;                                  // K values per wave and chunk
+  constexpr int TM = 32 * WM, TN = 32 * WN, TK = KPW * KW;
   constexpr int AE = TM * TK / 256, BE = TN * TK / 256;   // staged elements per thread
   constexpr int PADL = Pad<R>::value;
   constexpr int STAGE = 2 * TK * (TM + PADL) + 2 * TK * (TN + PADL);
@@ -154,28 +155,25 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
     }
   const int li = lane & 15, lk = lane >> 4;
 
-  // Per-thread staging coordinates, fixed over the K loop: the in-row offset
-  // of each staged element's row (column) of A (B), -1 beyond the row's
-  // extent, its k within the chunk and its LDS slot.  In-row offsets and
-  // strides fit 24 bits x 24 bits products below 2^31 (checked by the
-  // launcher), so the K loop runs on 32-bit full-rate integer arithmetic.
-  int a_ro[AE], a_kk[AE], a_ls[AE], b_co[BE], b_kk[BE], b_ls[BE];
-#pragma unroll
-  for (int r = 0; r < AE; ++r) {
-    const int e = tid + 256 * r;
-    const int mm = d.a_m_fast ? e % TM : e / TK;
-    const int kk = d.a_m_fast ? e / TM : e % TK;
-    const int gm = m0 + mm;
-    a_ro[r] = gm < Mt ? __umul24((unsigned)gm, (unsigned)d.sAi) : -1;
-    a_kk[r] = kk;
-    a_ls[r] = kk * (TM + PADL) + mm;
-  }
+  // Per-thread staging coordinates.  Element r of this thread's share of a
+  // chunk sits at (row, k) = (base + r * step) of A (B), one of the two steps
+  // zero (TM, TN and TK divide the 256 threads' stride), so row, k and LDS
+  // slot are affine in r and only their bases live in registers; B keeps
+  // each element's column offset (-1 beyond the row's extent), which a split
+  // column index makes non-affine.  In-row offsets and strides fit 24 bits x
+  // 24 bits products below 2^31 (checked by the launcher), so the K loop runs
+  // on 32-bit full-rate integer arithmetic.
+  static_assert(256 % TM == 0 && 256 % TN == 0 && 256 % TK == 0, "affine staging coordinates");
+  const int am0 = d.a_m_fast ? tid % TM : tid / TK, ak0 = d.a_m_fast ? tid / TM : tid % TK;
+  const int adm = d.a_m_fast ? 0 : 256 / TK, adk = d.a_m_fast ? 256 / TM : 0;
+  const int als0 = ak0 * (TM + PADL) + am0, alsd = adk * (TM + PADL) + adm;
+  const int bn0 = d.b_n_fast ? tid % TN : tid / TK, bk0 = d.b_n_fast ? tid / TN : tid % TK;
+  const int bdn = d.b_n_fast ? 0 : 256 / TK, bdk = d.b_n_fast ? 256 / TN : 0;
+  const int bls0 = bk0 * (TN + PADL) + bn0, blsd = bdk * (TN + PADL) + bdn;
+  int b_co[BE];
 #pragma unroll
   for (int r = 0; r < BE; ++r) {
-    const int e = tid + 256 * r;
-    const int nn = d.b_n_fast ? e % TN : e / TK;
-    const int kk = d.b_n_fast ? e / TN : e % TK;
-    const int gn = n0 + nn;
+    const int gn = n0 + bn0 + r * bdn;
     if (nsplit) {
       const int q = gn / d.Nin, rj = gn - q * d.Nin;
       const bool ok = gn < d.N && q < No && rj < Nt &&
@@ -184,9 +182,8 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
     } else {
       b_co[r] = gn < Nt ? __umul24((unsigned)gn, (unsigned)d.sBj) : -1;
     }
-    b_kk[r] = kk;
-    b_ls[r] = kk * (TN + PADL) + nn;
   }
+  const int gm0 = m0 + am0;
   // the K index l splits into (l / Kin, l % Kin); within one leg (Kin >= K
   // range) the quotient is 0; otherwise a float reciprocal and one
   // correction step give the exact quotient (l < 2^22)
@@ -213,17 +210,17 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < AE; ++r) {
-      const int gk = k0 + a_kk[r];
+      const int gk = k0 + ak0 + r * adk, gm = gm0 + r * adm;
       SA v;
       v.x = 0;
       v.y = 0;
-      if (a_ro[r] >= 0 && gk < kend) v = A[a_ro[r] + kpart(gk, sA1, sA2)];
+      if (gm < Mt && gk < kend) v = A[__umul24((unsigned)gm, (unsigned)d.sAi) + kpart(gk, sA1, sA2)];
       ra[r] = v;
     }
     if (same) return;
 #pragma unroll
     for (int r = 0; r < BE; ++r) {
-      const int gk = k0 + b_kk[r];
+      const int gk = k0 + bk0 + r * bdk;
       SB v;
       v.x = 0;
       v.y = 0;
@@ -238,14 +235,14 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
   auto stage = [&]() {
 #pragma unroll
     for (int r = 0; r < AE; ++r) {
-      As0[a_ls[r]] = (R)ra[r].x;
-      As1[a_ls[r]] = (R)ra[r].y * sgnA;
+      As0[als0 + r * alsd] = (R)ra[r].x;
+      As1[als0 + r * alsd] = (R)ra[r].y * sgnA;
     }
     if (same) return;
 #pragma unroll
     for (int r = 0; r < BE; ++r) {
-      Bs0[b_ls[r]] = (R)rb[r].x;
-      Bs1[b_ls[r]] = (R)rb[r].y * sgnB;
+      Bs0[bls0 + r * blsd] = (R)rb[r].x;
+      Bs1[bls0 + r * blsd] = (R)rb[r].y * sgnB;
     }
   };
   // B fragments: from the staged B, or for a diagonal Gram tile from the
@@ -253,16 +250,24 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
   const R* Bf = same ? As0 : Bs0;
   const int bplane = same ? TK * (TM + PADL) : TK * (TN + PADL);
   const R bfs = same ? bsg : (R)1;
+  // A diagonal tile of a Gram matrix conj(X + iY)^T (X + iY) (64 x 64 tiles):
+  // the real part takes both products, the imaginary part X^T Y - Y^T X is
+  // antisymmetric, so only P = X^T Y is accumulated (three MFMAs instead of
+  // four, every product exact) and im = P - P^T is formed through LDS at
+  // the end.  The conjugation must sit on exactly one operand.
+  constexpr bool SYMOK = !M3 && WM == 2 && WN == 2 && KW == 1;
+  const bool sym = SYMOK && same && (d.conjA != d.conjB);
 
   if (kbeg < kend) fetch(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += TK) {
     stage();
     __syncthreads();
     if (k0 + TK < kend) fetch(k0 + TK);      // in flight during the MFMAs below
-    // ---- this wave's 16 k values of the chunk, 4 per MFMA ----
+    // ---- this wave's KPW k values of the chunk, 4 per MFMA ----
 #pragma unroll
-    for (int ks = 0; ks < 16; ks += 4) {
-      const int kr = 16 * kw + ks + lk;
+    for (int ks = 0; ks < KPW; ks += 4) {
+      if (k0 + KPW * kw + ks >= kend) break;  // (uniform) only zeros staged from here on
+      const int kr = KPW * kw + ks + lk;
       R a_re[2], a_im[2], b_re[2], b_im[2];
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
@@ -306,13 +311,37 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
         for (int a = 0; a < 2; ++a)
 #pragma unroll
           for (int b = 0; b < 2; ++b) acc_re[a][b] = MfmaAcc<R>::mma(na_im[a], b_im[b], acc_re[a][b]);
+        if (!sym) {
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+          for (int a = 0; a < 2; ++a)
 #pragma unroll
-          for (int b = 0; b < 2; ++b) acc_im[a][b] = MfmaAcc<R>::mma(a_im[a], b_re[b], acc_im[a][b]);
+            for (int b = 0; b < 2; ++b) acc_im[a][b] = MfmaAcc<R>::mma(a_im[a], b_re[b], acc_im[a][b]);
+        }
       }
     }
     __syncthreads();
+  }
+  if constexpr (SYMOK) {
+    if (sym) {
+      // acc_im holds sgnB P: im[i][j] = acc_im[i][j] - acc_im[j][i]
+      static_assert(TM * TN <= (STAGE > RED ? STAGE : RED), "P tile fits the staging buffer");
+      R* P = smem;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            P[(wm * 32 + a * 16 + MfmaAcc<R>::row(lk, r)) * TN + wn * 32 + b * 16 + li] = acc_im[a][b][r];
+      __syncthreads();
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            acc_im[a][b][r] -= P[(wn * 32 + b * 16 + li) * TN + wm * 32 + a * 16 + MfmaAcc<R>::row(lk, r)];
+    }
   }
   if constexpr (M3) {
     // re = re.re - im.im, im = (re+im).(re+im) - re.re - im.im
