@@ -55,15 +55,16 @@ template <> struct MfmaAcc<double> {
 template <typename R> struct Pad { static constexpr int value = 17; };
 template <> struct Pad<double> { static constexpr int value = 1; };
 
-template <typename SA, typename SB, typename SC, typename R, int WM, int WN, int KW>
+template <typename SA, typename SB, typename SC, typename R, int WM, int WN, int KW, int FA, int FB>
 __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
   static_assert(WM * WN * KW == 4, "four waves per workgroup");
+  static_assert(FA * FB <= 4, "at most four 16 x 16 MFMA tiles per wave");
   constexpr int KPW = 16;                                  // K values per wave and chunk
-  constexpr int TM = 32 * WM, TN = 32 * WN, TK = KPW * KW;
+  constexpr int TM = 16 * FA * WM, TN = 16 * FB * WN, TK = KPW * KW;
   constexpr int AE = TM * TK / 256, BE = TN * TK / 256;   // staged elements per thread
   constexpr int PADL = Pad<R>::value;
   constexpr int STAGE = 2 * TK * (TM + PADL) + 2 * TK * (TN + PADL);
-  constexpr int RED = (KW > 1) ? (KW - 1) * 64 * 32 : 0;   // partial accumulators of waves kw > 0
+  constexpr int RED = (KW > 1) ? (KW - 1) * FA * FB * 8 * 64 : 0;   // partial accumulators of waves kw > 0
   __shared__ R smem[STAGE > RED ? STAGE : RED];
   R (*As)[TK][TM + PADL] = reinterpret_cast<R (*)[TK][TM + PADL]>(smem);                 // [re/im][k][m]
   R (*Bs)[TK][TN + PADL] = reinterpret_cast<R (*)[TK][TN + PADL]>(smem + 2 * TK * (TM + PADL));
@@ -144,11 +145,11 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
   // complex128) keeps the four-product form: its third accumulator set
   // would cost a wave per SIMD, which ate the saving.
   constexpr bool M3 = sizeof(R) == 4;
-  acc_t acc_re[2][2], acc_im[2][2], acc_ii[2][2];
+  acc_t acc_re[FA][FB], acc_im[FA][FB], acc_ii[FA][FB];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < FA; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < FB; ++b) {
       acc_re[a][b] = (acc_t){0, 0, 0, 0};
       acc_im[a][b] = (acc_t){0, 0, 0, 0};
       acc_ii[a][b] = (acc_t){0, 0, 0, 0};
@@ -255,7 +256,7 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
   // antisymmetric, so only P = X^T Y is accumulated (three MFMAs instead of
   // four, every product exact) and im = P - P^T is formed through LDS at
   // the end.  The conjugation must sit on exactly one operand.
-  constexpr bool SYMOK = !M3 && WM == 2 && WN == 2 && KW == 1;
+  constexpr bool SYMOK = !M3 && TM == TN;
   const bool sym = SYMOK && same && (d.conjA != d.conjB);
 
   if (kbeg < kend) fetch(kbeg);
@@ -268,54 +269,63 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
     for (int ks = 0; ks < KPW; ks += 4) {
       if (k0 + KPW * kw + ks >= kend) break;  // (uniform) only zeros staged from here on
       const int kr = KPW * kw + ks + lk;
-      R a_re[2], a_im[2], b_re[2], b_im[2];
+      R a_re[FA], a_im[FA], b_re[FB], b_im[FB];
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const int mi = wm * 32 + s * 16 + li;
-        const int nj = wn * 32 + s * 16 + li;
-        a_re[s] = As[0][kr][mi];
-        a_im[s] = As[1][kr][mi];
-        b_re[s] = Bf[kr * (TN + PADL) + nj];
-        b_im[s] = bfs * Bf[bplane + kr * (TN + PADL) + nj];
+      for (int s = 0; s < (FA > FB ? FA : FB); ++s) {
+        if (s < FA) {
+          const int mi = wm * 16 * FA + s * 16 + li;
+          a_re[s] = As[0][kr][mi];
+          a_im[s] = As[1][kr][mi];
+        }
+        if (s < FB) {
+          const int nj = wn * 16 * FB + s * 16 + li;
+          b_re[s] = Bf[kr * (TN + PADL) + nj];
+          b_im[s] = bfs * Bf[bplane + kr * (TN + PADL) + nj];
+        }
       }
       // the accumulators are independent: issue each real product for all
       // of them before the next, so that consecutive MFMAs never wait on one
       // another's result
       if constexpr (M3) {
         // three real products: re.re, im.im and (re+im).(re+im)
-        const R sa[2] = {a_re[0] + a_im[0], a_re[1] + a_im[1]};
-        const R sb[2] = {b_re[0] + b_im[0], b_re[1] + b_im[1]};
+        R sa[FA], sb[FB];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < FA; ++a) sa[a] = a_re[a] + a_im[a];
 #pragma unroll
-          for (int b = 0; b < 2; ++b) acc_re[a][b] = MfmaAcc<R>::mma(a_re[a], b_re[b], acc_re[a][b]);
+        for (int b = 0; b < FB; ++b) sb[b] = b_re[b] + b_im[b];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < FA; ++a)
 #pragma unroll
-          for (int b = 0; b < 2; ++b) acc_ii[a][b] = MfmaAcc<R>::mma(a_im[a], b_im[b], acc_ii[a][b]);
+          for (int b = 0; b < FB; ++b) acc_re[a][b] = MfmaAcc<R>::mma(a_re[a], b_re[b], acc_re[a][b]);
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < FA; ++a)
 #pragma unroll
-          for (int b = 0; b < 2; ++b) acc_im[a][b] = MfmaAcc<R>::mma(sa[a], sb[b], acc_im[a][b]);
+          for (int b = 0; b < FB; ++b) acc_ii[a][b] = MfmaAcc<R>::mma(a_im[a], b_im[b], acc_ii[a][b]);
+#pragma unroll
+        for (int a = 0; a < FA; ++a)
+#pragma unroll
+          for (int b = 0; b < FB; ++b) acc_im[a][b] = MfmaAcc<R>::mma(sa[a], sb[b], acc_im[a][b]);
       } else {
-        const R na_im[2] = {-a_im[0], -a_im[1]};
+        R na_im[FA];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < FA; ++a) na_im[a] = -a_im[a];
 #pragma unroll
-          for (int b = 0; b < 2; ++b) acc_re[a][b] = MfmaAcc<R>::mma(a_re[a], b_re[b], acc_re[a][b]);
+        for (int a = 0; a < FA; ++a)
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < FB; ++b) acc_re[a][b] = MfmaAcc<R>::mma(a_re[a], b_re[b], acc_re[a][b]);
 #pragma unroll
-          for (int b = 0; b < 2; ++b) acc_im[a][b] = MfmaAcc<R>::mma(a_re[a], b_im[b], acc_im[a][b]);
+        for (int a = 0; a < FA; ++a)
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < FB; ++b) acc_im[a][b] = MfmaAcc<R>::mma(a_re[a], b_im[b], acc_im[a][b]);
 #pragma unroll
-          for (int b = 0; b < 2; ++b) acc_re[a][b] = MfmaAcc<R>::mma(na_im[a], b_im[b], acc_re[a][b]);
+        for (int a = 0; a < FA; ++a)
+#pragma unroll
+          for (int b = 0; b < FB; ++b) acc_re[a][b] = MfmaAcc<R>::mma(na_im[a], b_im[b], acc_re[a][b]);
         if (!sym) {
 #pragma unroll
-          for (int a = 0; a < 2; ++a)
+          for (int a = 0; a < FA; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) acc_im[a][b] = MfmaAcc<R>::mma(a_im[a], b_re[b], acc_im[a][b]);
+            for (int b = 0; b < FB; ++b) acc_im[a][b] = MfmaAcc<R>::mma(a_im[a], b_re[b], acc_im[a][b]);
         }
       }
     }
@@ -323,32 +333,34 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
   }
   if constexpr (SYMOK) {
     if (sym) {
-      // acc_im holds sgnB P: im[i][j] = acc_im[i][j] - acc_im[j][i]
-      static_assert(TM * TN <= (STAGE > RED ? STAGE : RED), "P tile fits the staging buffer");
-      R* P = smem;
+      // acc_im holds sgnB P: im[i][j] = acc_im[i][j] - acc_im[j][i] (with the
+      // K chunk split over the waves, each wave's partial P on its own)
+      static_assert(KW * TM * TN <= (STAGE > RED ? STAGE : RED), "P tiles fit the staging buffer");
+      R* P = smem + (KW > 1 ? kw * TM * TN : 0);
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < FA; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < FB; ++b)
 #pragma unroll
           for (int r = 0; r < 4; ++r)
-            P[(wm * 32 + a * 16 + MfmaAcc<R>::row(lk, r)) * TN + wn * 32 + b * 16 + li] = acc_im[a][b][r];
+            P[(wm * 16 * FA + a * 16 + MfmaAcc<R>::row(lk, r)) * TN + wn * 16 * FB + b * 16 + li] = acc_im[a][b][r];
       __syncthreads();
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < FA; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < FB; ++b)
 #pragma unroll
           for (int r = 0; r < 4; ++r)
-            acc_im[a][b][r] -= P[(wn * 32 + b * 16 + li) * TN + wm * 32 + a * 16 + MfmaAcc<R>::row(lk, r)];
+            acc_im[a][b][r] -= P[(wn * 16 * FB + b * 16 + li) * TN + wm * 16 * FA + a * 16 + MfmaAcc<R>::row(lk, r)];
+      if (KW > 1) __syncthreads();          // the reduction below reuses the buffer
     }
   }
   if constexpr (M3) {
     // re = re.re - im.im, im = (re+im).(re+im) - re.re - im.im
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < FA; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < FB; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const R p1 = acc_re[a][b][r], p2 = acc_ii[a][b][r];
@@ -360,42 +372,42 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
     // waves kw > 0 hand their partial sums to wave 0 (the staging buffers
     // are free after the last barrier of the loop)
     if (kw > 0) {
-      R* red = smem + (kw - 1) * 64 * 32;
+      R* red = smem + (kw - 1) * FA * FB * 8 * 64;
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < FA; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < FB; ++b)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            red[((a * 2 + b) * 8 + r) * 64 + lane] = acc_re[a][b][r];
-            red[((a * 2 + b) * 8 + 4 + r) * 64 + lane] = acc_im[a][b][r];
+            red[((a * FB + b) * 8 + r) * 64 + lane] = acc_re[a][b][r];
+            red[((a * FB + b) * 8 + 4 + r) * 64 + lane] = acc_im[a][b][r];
           }
     }
     __syncthreads();
     if (kw > 0) return;
 #pragma unroll
     for (int w = 0; w < KW - 1; ++w) {
-      const R* red = smem + w * 64 * 32;
+      const R* red = smem + w * FA * FB * 8 * 64;
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < FA; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < FB; ++b)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            acc_re[a][b][r] += red[((a * 2 + b) * 8 + r) * 64 + lane];
-            acc_im[a][b][r] += red[((a * 2 + b) * 8 + 4 + r) * 64 + lane];
+            acc_re[a][b][r] += red[((a * FB + b) * 8 + r) * 64 + lane];
+            acc_im[a][b][r] += red[((a * FB + b) * 8 + 4 + r) * 64 + lane];
           }
     }
   }
   // ---- write back each 16x16 tile in the MFMA's output lane layout ----
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < FA; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < FB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gi = m0 + wm * 32 + a * 16 + MfmaAcc<R>::row(lk, r);
-        const int gj = n0 + wn * 32 + b * 16 + li;
+        const int gi = m0 + wm * 16 * FA + a * 16 + MfmaAcc<R>::row(lk, r);
+        const int gj = n0 + wn * 16 * FB + b * 16 + li;
         if (gi < d.M && gj < d.N) {
           double2 v = make_double2((double)acc_re[a][b][r], (double)acc_im[a][b][r]);
           if (d.herm && gi == gj) v.y = 0.0;    // a Hermitian matrix's real diagonal
@@ -410,13 +422,16 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(GemmDesc d) {
 }
 
 // Output tile shape of a problem by the fixed rule: 64 x 64 in general,
-// 128 x 32 or 32 x 128 when one side is at most 32, 32 x 32 with the K chunk
-// split over the four waves when both are (the runtime's tuner may pick
-// another of the four by measurement).
-enum TileCfg { TILE_64x64 = 0, TILE_128x32 = 1, TILE_32x128 = 2, TILE_32x32 = 3 };
+// 128 x 32 or 32 x 128 when one side is at most 32 (16 x 128 when M is at
+// most 16), and with the K chunk split over the four waves 32 x 32 when both
+// are at most 32, 16 x 16 when both are at most 16 (the runtime's tuner may
+// pick another shape by measurement).
+enum TileCfg { TILE_64x64 = 0, TILE_128x32 = 1, TILE_32x128 = 2, TILE_32x32 = 3, TILE_16x16 = 4, TILE_16x128 = 5 };
 static int tile_cfg(int M, int N) {
+  if (M <= 16 && N <= 16) return TILE_16x16;
   if (M <= 32 && N <= 32) return TILE_32x32;
   if (N <= 32) return TILE_128x32;
+  if (M <= 16) return TILE_16x128;
   if (M <= 32) return TILE_32x128;
   return TILE_64x64;
 }
@@ -425,11 +440,21 @@ static void tile_dims(int cfg, int* tm, int* tn) {
     case TILE_128x32: *tm = 128; *tn = 32; return;
     case TILE_32x128: *tm = 32; *tn = 128; return;
     case TILE_32x32: *tm = 32; *tn = 32; return;
+    case TILE_16x16: *tm = 16; *tn = 16; return;
+    case TILE_16x128: *tm = 16; *tn = 128; return;
     default: *tm = 64; *tn = 64; return;
   }
 }
 
 int zgemm_rule_cfg(const GemmDesc& d) { return tile_cfg(d.M, d.N); }
+
+// the 16-row shapes are only worth measuring for problems of at most 16 rows
+// (and 16 columns for the 16 x 16 one)
+bool zgemm_cfg_useful(const GemmDesc& d, int cfg) {
+  if (cfg == TILE_16x16) return d.M <= 16 && d.N <= 16;
+  if (cfg == TILE_16x128) return d.M <= 16;
+  return cfg >= 0 && cfg < kZgemmCfgs;
+}
 
 long long zgemm_tiles(const GemmDesc& d) {
   int tm, tn;
@@ -437,13 +462,13 @@ long long zgemm_tiles(const GemmDesc& d) {
   return (long long)((d.M + tm - 1) / tm) * ((d.N + tn - 1) / tn);
 }
 
-template <typename SA, typename SB, typename SC, typename R, int WM, int WN, int KW>
+template <typename SA, typename SB, typename SC, typename R, int WM, int WN, int KW, int FA, int FB>
 hipError_t launch_cfg(GemmDesc d, int batch, hipStream_t st) {
-  constexpr int TM = 32 * WM, TN = 32 * WN;
+  constexpr int TM = 16 * FA * WM, TN = 16 * FB * WN;
   d.tilesN = (d.N + TN - 1) / TN;
   const int tilesM = (d.M + TM - 1) / TM;
   dim3 grid((unsigned)((long long)batch * d.G2 * d.H * d.tilesN), (unsigned)tilesM, (unsigned)d.ksplit);
-  hipLaunchKernelGGL((k_zgemm<SA, SB, SC, R, WM, WN, KW>), grid, dim3(256), 0, st, d);
+  hipLaunchKernelGGL((k_zgemm<SA, SB, SC, R, WM, WN, KW, FA, FB>), grid, dim3(256), 0, st, d);
   return hipGetLastError();
 }
 
@@ -474,10 +499,12 @@ hipError_t launch_zgemm_t(GemmDesc d, int batch, hipStream_t st, int cfg) {
   if (d.ext && (d.eM < 0 || d.eN < 0 || d.eH < 0 || d.eKo < 0 || d.eKi < 0) && !d.knew) return hipErrorInvalidValue;
   if (cfg < 0 || cfg >= kZgemmCfgs) cfg = tile_cfg(d.M, d.N);
   switch (cfg) {
-    case TILE_128x32: return launch_cfg<SA, SB, SC, R, 4, 1, 1>(d, batch, st);
-    case TILE_32x128: return launch_cfg<SA, SB, SC, R, 1, 4, 1>(d, batch, st);
-    case TILE_32x32: return launch_cfg<SA, SB, SC, R, 1, 1, 4>(d, batch, st);
-    default: return launch_cfg<SA, SB, SC, R, 2, 2, 1>(d, batch, st);
+    case TILE_128x32: return launch_cfg<SA, SB, SC, R, 4, 1, 1, 2, 2>(d, batch, st);
+    case TILE_32x128: return launch_cfg<SA, SB, SC, R, 1, 4, 1, 2, 2>(d, batch, st);
+    case TILE_32x32: return launch_cfg<SA, SB, SC, R, 1, 1, 4, 2, 2>(d, batch, st);
+    case TILE_16x16: return launch_cfg<SA, SB, SC, R, 1, 1, 4, 1, 1>(d, batch, st);
+    case TILE_16x128: return launch_cfg<SA, SB, SC, R, 1, 4, 1, 1, 2>(d, batch, st);
+    default: return launch_cfg<SA, SB, SC, R, 2, 2, 1, 2, 2>(d, batch, st);
   }
 }
 

@@ -57,12 +57,15 @@ struct GemmDesc {
   int bM0, bM1, bN0, bN1, bH0, bH1, bNo0, bNo1;
 };
 
-// cfg: one of the kZgemmCfgs tile shapes (64x64, 128x32, 32x128, 32x32 with
-// the K chunk split over the waves), or -1 for the fixed rule
-constexpr int kZgemmCfgs = 4;
+// cfg: one of the kZgemmCfgs tile shapes (64x64, 128x32, 32x128, 32x32 and
+// 16x16 with the K chunk split over the waves, 16x128), or -1 for the fixed
+// rule
+constexpr int kZgemmCfgs = 6;
 hipError_t launch_zgemm(const GemmDesc& d, int batch, int kind, hipStream_t st, int cfg = -1);
 // the fixed rule's tile shape for d, and its output tiles per (t, g, h)
 int zgemm_rule_cfg(const GemmDesc& d);
+// whether the tuner should measure tile shape cfg for d
+bool zgemm_cfg_useful(const GemmDesc& d, int cfg);
 long long zgemm_tiles(const GemmDesc& d);
 
 // ---------------------------------------------------------------- EIGH ----

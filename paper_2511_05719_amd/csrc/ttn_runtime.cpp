@@ -441,7 +441,7 @@ static inline void* offset_ptr(const void* p, long long elems, size_t es) {
 
 // One batched GEMM launch of the hot path with its tile shape: the tuned
 // one for this launch shape if the tuner has measured it; with tuning on, a
-// shape not seen before is first run once in each of the four tile shapes on
+// shape not seen before is first run once in each of its tile shapes on
 // its own operands (every shape computes the same product, overwriting C),
 // timed with events on the context's stream, and the fastest is kept.
 static ttn_status run_gemm(ttn_ctx* ctx, const GemmDesc& g, int kind) {
@@ -456,6 +456,7 @@ static ttn_status run_gemm(ttn_ctx* ctx, const GemmDesc& g, int kind) {
     }
     float best_ms = 0.0f;
     for (int c = 0; c < kZgemmCfgs; ++c) {
+      if (!zgemm_cfg_useful(g, c)) continue;
       TTN_CHECK_HIP(launch_zgemm(g, ctx->B, kind, ctx->st, c));          // warm
       TTN_CHECK_HIP(hipEventRecord(ctx->tune_ev[0], ctx->st));
       TTN_CHECK_HIP(launch_zgemm(g, ctx->B, kind, ctx->st, c));
@@ -463,7 +464,7 @@ static ttn_status run_gemm(ttn_ctx* ctx, const GemmDesc& g, int kind) {
       TTN_CHECK_HIP(hipEventSynchronize(ctx->tune_ev[1]));
       float ms = 0.0f;
       TTN_CHECK_HIP(hipEventElapsedTime(&ms, ctx->tune_ev[0], ctx->tune_ev[1]));
-      if (c == 0 || ms < best_ms) {
+      if (cfg < 0 || ms < best_ms) {
         best_ms = ms;
         cfg = c;
       }
