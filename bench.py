@@ -296,16 +296,16 @@ def cpu_oracle(circ, seed, n_ops=10):
 # reads for a 256 MiB device copy, see the profile named), valid for the
 # source file it was measured on: reported only while that file is unchanged
 TRAFFIC = {
-    "profile": "profiles/ttn_d5_chi64_b2048_clustered_hbm_traffic.txt",
-    "batch": 2048,
+    "profile": "profiles/ttn_d5_chi64_b4096_clustered_hbm_traffic.txt",
+    "batch": 4096,
     "layout": "optimized",
     "classes": {
-        # k_zgemm<float2, float2, float2, ...>, all tile shapes: 277.8 MB read + 182.8 MB written
-        "contract": {"bytes_per_launch": 460.6e6, "source": "ttn_gemm.hip",
-                     "sha256": "df0e24b983f08d00be0362e823a71c7ab335629e54e886fbf60a46ef502d37b8"},
-        # k_zgemm<float2, float2, double2, ...>, all tile shapes: 234.3 MB read + 27.6 MB written
-        "gram": {"bytes_per_launch": 261.9e6, "source": "ttn_gemm.hip",
-                 "sha256": "df0e24b983f08d00be0362e823a71c7ab335629e54e886fbf60a46ef502d37b8"},
+        # k_zgemm<float2, float2, float2, float, ...>, all tile shapes: 455.7 MB read + 354.1 MB written
+        "contract": {"bytes_per_launch": 809.8e6, "source": "ttn_gemm.hip",
+                     "sha256": "c7fc7c69676343eab838cfc92b20b8cea6e928249c3e8eac1ebe703f5a6e73de"},
+        # k_zgemm<float2, float2, double2, double, ...>, all tile shapes: 382.1 MB read + 47.9 MB written
+        "gram": {"bytes_per_launch": 430.0e6, "source": "ttn_gemm.hip",
+                 "sha256": "c7fc7c69676343eab838cfc92b20b8cea6e928249c3e8eac1ebe703f5a6e73de"},
     },
 }
 
@@ -365,7 +365,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=2048)
+    ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--rounds", type=int, default=5)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--layout", choices=("optimized", "default"), default="optimized",

@@ -397,7 +397,9 @@ ttn_status ttn_test_move(ttn_ctx* ctx, int32_t rows, int32_t n, int32_t new_pad,
  * per side of the move and per diagonal block.
  * The Gram and contraction ledgers track the actual leg dimensions from the
  * last state reset (ttn_init_product, or the start of a run) on: enable
- * profiling before it.  Enabling resets the counters.  ttn_profile_read
+ * profiling before it.  Enabling resets the counters (the first enable
+ * creates the library's pool of timing events, so that none is created
+ * while a profiled run is timed).  ttn_profile_read
  * [sync] returns, for one class, the summed elapsed milliseconds, the number
  * of launches, the ledgered flops and (alg_bytes may be null) the ledgered
  * bytes (0 for classes without a ledger). */
@@ -418,11 +420,12 @@ ttn_status ttn_profile_read(ttn_ctx* ctx, int32_t cls, double* ms, int64_t* laun
 
 /* Tile-shape tuner for the batched contractions and Gram matrices (no
  * passage of the paper: launch tuning of this library).  Every such launch
- * runs in one of four output-tile shapes (64x64, 128x32, 32x128, 32x32 with
- * the K range split over the wavefronts); by default a fixed rule on the
- * output dimensions picks it.  With on = 1, a launch whose shape (kind,
- * M, N, K, inner/outer K split, batch sizes, split-K, operand layouts) has
- * not been measured yet first runs once in every tile shape on its own
+ * runs in one of six output-tile shapes (64x64, 128x32, 32x128, 16x128, and
+ * 32x32 and 16x16 with the K range split over the wavefronts); by default a
+ * fixed rule on the output dimensions picks it.  With on = 1, a launch whose
+ * shape (kind, M, N, K, inner/outer K split, batch sizes, split-K, operand
+ * layouts) has not been measured yet first runs once in every tile shape
+ * that fits it (the 16-row shapes for at most 16 rows) on its own
  * operands, timed with events on the context's stream (the stream is
  * synchronised: tuning stalls the host), and the fastest is kept for that
  * shape; results do not depend on the choice beyond floating-point

@@ -154,8 +154,13 @@ struct ttn_ctx {
   LeafBatch run{};             // run-level pointers of the pending ops
   // profiling: HIP events around every launch of each kernel class
   bool prof = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[TTN_NCLASS];
-  size_t prof_used[TTN_NCLASS] = {0};
+  // profiling: a ring of event pairs created once and recycled (a slot's
+  // elapsed time is added to its class's total before the slot is reused)
+  struct ProfSlot { hipEvent_t a, b; int cls; bool pending; };
+  std::vector<ProfSlot> prof_ring;
+  size_t prof_pos = 0;
+  double prof_ms[TTN_NCLASS] = {0.0};
+  int64_t prof_n[TTN_NCLASS] = {0};
   double* ledger[TTN_NCLASS] = {nullptr};   // device [B] algorithmic flops per class (or null)
   double* ledger_bytes[TTN_NCLASS] = {nullptr};   // device [B] algorithmic HBM bytes (Gram, contraction)
   double* ledger_mem = nullptr;             // [7][B]: flops of eigh small, eigh large, Gram, contraction,
@@ -264,19 +269,33 @@ static void adopt(ttn_ctx* c, int node, int buf) {
 static inline void* node_ptr(ttn_ctx* c, int node) { return c->bufs[c->node_buf[node]].p; }
 
 // ----------------------------------------------------------- profiling ----
+// Event pairs live in a ring of kProfRing slots created when profiling is
+// first enabled, so that no event is created while a profiled run is timed.
+// Reusing a slot first adds its elapsed time to its class (the host waits
+// on every hop, so the slot's events have long completed by then).
+static constexpr size_t kProfRing = 8192;
+static hipError_t prof_harvest(ttn_ctx* ctx, ttn_ctx::ProfSlot& s) {
+  if (!s.pending) return hipSuccess;
+  s.pending = false;
+  hipError_t e = hipEventSynchronize(s.b);
+  if (e != hipSuccess) return e;
+  float ms = 0.0f;
+  e = hipEventElapsedTime(&ms, s.a, s.b);
+  if (e != hipSuccess) return e;
+  ctx->prof_ms[s.cls] += ms;
+  return hipSuccess;
+}
 static void prof_begin(ttn_ctx* ctx, int cls, hipEvent_t* stop) {
   *stop = nullptr;
-  if (!ctx->prof) return;
-  auto& v = ctx->prof_ev[cls];
-  size_t& u = ctx->prof_used[cls];
-  if (u == v.size()) {
-    hipEvent_t a, b;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
-    v.push_back({a, b});
-  }
-  hipEventRecord(v[u].first, ctx->st);
-  *stop = v[u].second;
-  ++u;
+  if (!ctx->prof || ctx->prof_ring.empty()) return;
+  auto& s = ctx->prof_ring[ctx->prof_pos];
+  if (prof_harvest(ctx, s) != hipSuccess) return;
+  ctx->prof_pos = (ctx->prof_pos + 1) % ctx->prof_ring.size();
+  s.cls = cls;
+  s.pending = true;
+  ++ctx->prof_n[cls];
+  hipEventRecord(s.a, ctx->st);
+  *stop = s.b;
 }
 static void prof_end(ttn_ctx* ctx, hipEvent_t stop) {
   if (stop) hipEventRecord(stop, ctx->st);
@@ -1302,11 +1321,10 @@ ttn_status ttn_destroy(ttn_ctx* ctx) {
   }
   if (ctx->ev_gin) hipEventDestroy(ctx->ev_gin);
   if (ctx->ev_gout) hipEventDestroy(ctx->ev_gout);
-  for (int c = 0; c < TTN_NCLASS; ++c)
-    for (auto& e : ctx->prof_ev[c]) {
-      hipEventDestroy(e.first);
-      hipEventDestroy(e.second);
-    }
+  for (auto& e : ctx->prof_ring) {
+    hipEventDestroy(e.a);
+    hipEventDestroy(e.b);
+  }
   void* ws[] = {ctx->G, ctx->Wi, ctx->Wa, ctx->rot_log, ctx->gpk, ctx->lam_sorted, ctx->order, ctx->kept,
                 ctx->scale_abs, ctx->nsteps, ctx->rank_table, ctx->ext, ctx->rank_max, ctx->ledger_mem,
                 ctx->adim, ctx->nk, ctx->qr_done, ctx->nk_max, ctx->gate4, ctx->d_traj,
@@ -2273,7 +2291,20 @@ ttn_status ttn_profile_enable(ttn_ctx* ctx, int32_t on) {
   if (!ctx) return TTN_EINVAL;
   TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
   ctx->prof = on != 0;
-  for (int c = 0; c < TTN_NCLASS; ++c) ctx->prof_used[c] = 0;
+  for (auto& e : ctx->prof_ring) e.pending = false;
+  for (int c = 0; c < TTN_NCLASS; ++c) {
+    ctx->prof_ms[c] = 0.0;
+    ctx->prof_n[c] = 0;
+  }
+  while (ctx->prof && ctx->prof_ring.size() < kProfRing) {
+    ttn_ctx::ProfSlot e{nullptr, nullptr, 0, false};
+    TTN_CHECK_HIP(hipEventCreate(&e.a));
+    if (hipEventCreate(&e.b) != hipSuccess) {
+      hipEventDestroy(e.a);
+      return fail(ctx, TTN_EDEVICE, "hipEventCreate failed");
+    }
+    ctx->prof_ring.push_back(e);
+  }
   TTN_CHECK_HIP(launch_fill_f64(ctx->ledger_mem, 0.0, 7ll * ctx->B, ctx->st));
   return TTN_OK;
 }
@@ -2283,14 +2314,9 @@ ttn_status ttn_profile_read(ttn_ctx* ctx, int32_t cls, double* ms, int64_t* laun
   if (!ctx) return TTN_EINVAL;
   if (cls < 0 || cls >= TTN_NCLASS || !ms || !launches || !alg_flops) return fail(ctx, TTN_EINVAL, "bad class");
   TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
-  double tot = 0.0;
-  for (size_t i = 0; i < ctx->prof_used[cls]; ++i) {
-    float e = 0.0f;
-    TTN_CHECK_HIP(hipEventElapsedTime(&e, ctx->prof_ev[cls][i].first, ctx->prof_ev[cls][i].second));
-    tot += e;
-  }
-  *ms = tot;
-  *launches = (int64_t)ctx->prof_used[cls];
+  for (auto& e : ctx->prof_ring) TTN_CHECK_HIP(prof_harvest(ctx, e));
+  *ms = ctx->prof_ms[cls];
+  *launches = ctx->prof_n[cls];
   *alg_flops = 0.0;
   if (ctx->ledger[cls]) {
     std::vector<double> f(ctx->B);
