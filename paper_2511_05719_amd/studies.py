@@ -222,10 +222,10 @@ def threshold_sweep(model: str, strengths, distances=(3, 5), rounds: int = 1, sh
 
 
 def distance7(shots: int = 4096, rounds: int = 7, theta: float = 0.08, gamma: float = 3e-3, chi: int = 128,
-              batch: int = 96, seed: int = 7) -> dict:
+              batch: int = 256, seed: int = 7) -> dict:
     """The d = 7 colour code at chi = 128 in batches of `batch` rows: a node
     buffer holds its largest shape (two legs at 2 chi on a controlled gate's
-    path) for every row, ~2 GB per row here, so a context takes about a
+    path) for every row, ~643 MiB per row here, so a context takes a few
     hundred rows and the shots run as consecutive batches (trajectory ids
     continue across batches, so the result does not depend on the split)."""
     from workload import build_circuit
@@ -268,7 +268,7 @@ def main(argv=None):
     ap.add_argument("study", choices=("pta", "truncation", "table3", "threshold", "d7"))
     ap.add_argument("--out", default=None)
     ap.add_argument("--shots", type=int, default=None)
-    ap.add_argument("--batch", type=int, default=96)
+    ap.add_argument("--batch", type=int, default=256)
     a = ap.parse_args(argv)
     if a.study == "d7":
         res = distance7(shots=a.shots or 4096, batch=a.batch)
