@@ -222,7 +222,7 @@ def threshold_sweep(model: str, strengths, distances=(3, 5), rounds: int = 1, sh
 
 
 def distance7(shots: int = 4096, rounds: int = 7, theta: float = 0.08, gamma: float = 3e-3, chi: int = 128,
-              batch: int = 256, seed: int = 7) -> dict:
+              batch: int = 256, seed: int = 3) -> dict:
     """The d = 7 colour code at chi = 128 in batches of `batch` rows: a node
     buffer holds its largest shape (two legs at 2 chi on a controlled gate's
     path) for every row, ~643 MiB per row here, so a context takes a few
