@@ -2297,9 +2297,11 @@ ttn_status ttn_profile_enable(ttn_ctx* ctx, int32_t on) {
     ctx->prof_n[c] = 0;
   }
   while (ctx->prof && ctx->prof_ring.size() < kProfRing) {
+    // timing-only events: no system-scope fence (cache writeback and
+    // invalidation) at each record, which would also slow the work it brackets
     ttn_ctx::ProfSlot e{nullptr, nullptr, 0, false};
-    TTN_CHECK_HIP(hipEventCreate(&e.a));
-    if (hipEventCreate(&e.b) != hipSuccess) {
+    TTN_CHECK_HIP(hipEventCreateWithFlags(&e.a, hipEventDisableSystemFence));
+    if (hipEventCreateWithFlags(&e.b, hipEventDisableSystemFence) != hipSuccess) {
       hipEventDestroy(e.a);
       return fail(ctx, TTN_EDEVICE, "hipEventCreate failed");
     }
