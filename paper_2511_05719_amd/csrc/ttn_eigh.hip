@@ -1634,10 +1634,12 @@ __global__ void __launch_bounds__(64 * NW) k_pchol_reg(EighDesc d) {
 #pragma unroll
       for (int q = 0; q < RPW; ++q) {
         const int i = NW * q + wave;
-        const int wi = (q * NW) / 64;                   // (the word and register half of row i)
+        const int wi = (q * NW) / 64;                   // (the word of row i's pivot bit)
         if (i < n && !((piv[wi] >> (i & 63)) & 1ull)) {
-          const double ujx = readlane_d(arow[wi].x, i & 63) * irkk;
-          const double ujy0 = readlane_d(arow[wi].y, i & 63) * irkk;
+          // u_i from the published pivot row (one broadcast LDS read)
+          const double2 pi = pbuf[k & 1][i];
+          const double ujx = pi.x * irkk;
+          const double ujy0 = pi.y * irkk;
 #pragma unroll
           for (int s = 0; s < CPL; ++s) {
             const int c = lane + 64 * s;
