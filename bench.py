@@ -302,10 +302,10 @@ TRAFFIC = {
     "classes": {
         # k_zgemm<float2, float2, float2, float, ...>, all tile shapes: 455.7 MB read + 354.1 MB written
         "contract": {"bytes_per_launch": 809.8e6, "source": "ttn_gemm.hip",
-                     "sha256": "c7fc7c69676343eab838cfc92b20b8cea6e928249c3e8eac1ebe703f5a6e73de"},
+                     "sha256": "7947118a61490b5cc3877f46a50dbbcdcd637d5e8c5e1061255deaa89beec0b3"},
         # k_zgemm<float2, float2, double2, double, ...>, all tile shapes: 382.1 MB read + 47.9 MB written
         "gram": {"bytes_per_launch": 430.0e6, "source": "ttn_gemm.hip",
-                 "sha256": "c7fc7c69676343eab838cfc92b20b8cea6e928249c3e8eac1ebe703f5a6e73de"},
+                 "sha256": "7947118a61490b5cc3877f46a50dbbcdcd637d5e8c5e1061255deaa89beec0b3"},
     },
 }
 

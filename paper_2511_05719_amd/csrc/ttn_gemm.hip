@@ -12,15 +12,16 @@
 // ksplit > 1 the K range is cut into ksplit slices whose partial products
 // go to ksplit copies of C (stride sCz); the consumer sums them.
 //
-// Tiling: a 256-thread workgroup (4 wave64).  Each wave owns a 32 x 32
-// output block built from 2 x 2 MFMA 16x16x4 tiles; a complex
+// Tiling: a 256-thread workgroup (4 wave64).  Each wave owns a (16 FA) x
+// (16 FB) output block built from FA x FB MFMA 16x16x4 tiles (2 x 2: 32 x 32;
+// 1 x 1 and 1 x 2 for problems of at most 16 rows); a complex
 // multiply-accumulate is three real MFMAs with FP32 accumulation (re*re,
-// im*im, (re+im)*(re+im)) and four with FP64 (re*re, -im*im, re*im,
-// im*re).  The
-// waves are arranged WM x WN over the output tile (32 WM x 32 WN), or, for
-// outputs of at most 32 x 32 (KW = 4), all four share one 32 x 32 block and
-// each takes a quarter of every K chunk, reduced through LDS at the end.  K
-// is staged through LDS in chunks of 16 KW; the next chunk's global loads are
+// im*im, (re+im)*(re+im)) and four with FP64 (re*re, -im*im, re*im, im*re;
+// three on the diagonal tiles of a Gram matrix, whose imaginary part is
+// antisymmetric).  The waves are arranged WM x WN over the output tile, or,
+// for outputs of at most 32 x 32 (KW = 4), all four share one block and each
+// takes a quarter of every K chunk, reduced through LDS at the end.  K is
+// staged through LDS in chunks of 16 KW; the next chunk's global loads are
 // issued before the current chunk's MFMAs, and the contiguous operand
 // dimension is mapped to consecutive lanes on the global load.
 #include "ttn_device.h"
