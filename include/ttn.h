@@ -337,6 +337,8 @@ int32_t ttn_test_sweep_plan(int32_t k, uint32_t* groups, int32_t cap);
  * with TTN_EINVAL if the operation would reach past them.
  *  ttn_test_leg_apply: out[t][..a..] = sum_i W[t][a][i] T[t][..i..] on leg
  *    `leg` (0, 1, 2) of T [rows][d0][d1][d2]; W [rows][newd][n], n = d[leg].
+ *  Both GEMM exports run in the fixed rule's tile shape, or in the one that
+ *  ttn_autotune(ctx, 2 + c, ...) forces.
  *  ttn_test_gram: G[t][i][j] = sum over the other legs of
  *    conj(T[..i..]) T[..j..], G float64 [ksplit][rows][n][n][2] (FP64
  *    accumulation): with ksplit > 1 the sum runs in ksplit parts, one per
@@ -431,6 +433,9 @@ ttn_status ttn_profile_read(ttn_ctx* ctx, int32_t cls, double* ms, int64_t* laun
  * shape; results do not depend on the choice beyond floating-point
  * summation order.  on = 0 stops measuring new shapes but keeps using the
  * measured ones; on = -1 forgets them and returns to the fixed rule.
+ * on = 2 + c (c = 0..5: 64x64, 128x32, 32x128, 32x32, 16x16, 16x128) runs
+ * every launch in tile shape c, whatever it fits, until the next call
+ * (testing each shape on any problem); 0, 1 and -1 end it.
  * shapes / changed (may be null) receive the number of shapes measured and
  * how many of them differ from the fixed rule.  Errors: TTN_EINVAL for
  * other values of on. */

@@ -175,6 +175,7 @@ struct ttn_ctx {
   int last_kb[2] = {0, 0};     // batch-max kept counts of the two blocks of the last block move
   // GEMM tile-shape tuner: per launch shape, the measured fastest tile shape
   int tune_on = 0;
+  int force_cfg = -1;           // >= 0: every GEMM launch in this tile shape (testing)
   std::map<std::array<long long, 14>, int> tune;
   int64_t tuned_shapes = 0, tuned_changed = 0;
   hipEvent_t tune_ev[2] = {nullptr, nullptr};
@@ -467,7 +468,7 @@ static ttn_status run_gemm(ttn_ctx* ctx, const GemmDesc& g, int kind) {
   const std::array<long long, 14> key = {kind, g.M, g.N, g.K, g.Kin, g.H, std::max(g.G2, 1), std::max(g.ksplit, 1),
                                          g.a_m_fast, g.b_n_fast, g.conjA, g.conjB, g.ext != nullptr, ctx->B};
   auto it = ctx->tune.find(key);
-  int cfg = it != ctx->tune.end() ? it->second : -1;
+  int cfg = ctx->force_cfg >= 0 ? ctx->force_cfg : (it != ctx->tune.end() ? it->second : -1);
   if (cfg < 0 && ctx->tune_on && !ctx->capturing) {
     if (!ctx->tune_ev[0]) {
       TTN_CHECK_HIP(hipEventCreate(&ctx->tune_ev[0]));
@@ -1738,7 +1739,7 @@ static ttn_status env_gemm(ttn_ctx* c, const GemmDesc& g, long long capA, long l
   ttn_ctx* ctx = c;
   if (!gemm_fits(g, c->B, capA, capB, capC)) return fail(c, TTN_EINVAL, "internal: environment exceeds its buffers");
   ++c->launches;
-  TTN_CHECK_HIP(launch_zgemm(g, c->B, c->c128 ? GEMM_C128 : GEMM_C64, c->st));
+  TTN_CHECK_HIP(launch_zgemm(g, c->B, c->c128 ? GEMM_C128 : GEMM_C64, c->st, c->force_cfg));
   return TTN_OK;
 }
 
@@ -2273,8 +2274,11 @@ ttn_status ttn_bond_dims(ttn_ctx* ctx, int32_t row, int32_t* dims) {
 
 ttn_status ttn_autotune(ttn_ctx* ctx, int32_t on, int64_t* shapes, int64_t* changed) {
   if (!ctx) return TTN_EINVAL;
-  if (on < -1 || on > 1) return fail(ctx, TTN_EINVAL, "on must be -1, 0 or 1");
-  if (on == -1) {
+  if (on < -1 || on >= 2 + kZgemmCfgs) return fail(ctx, TTN_EINVAL, "on must be -1, 0, 1 or 2 + a tile shape");
+  ctx->force_cfg = on >= 2 ? on - 2 : -1;
+  if (on >= 2) {
+    ctx->tune_on = 0;
+  } else if (on == -1) {
     ctx->tune.clear();
     ctx->tuned_shapes = 0;
     ctx->tuned_changed = 0;
@@ -2356,7 +2360,7 @@ ttn_status ttn_test_leg_apply(ttn_ctx* ctx, int32_t rows, const int32_t* dims3, 
   const bool wA = (leg != 2);
   if (!gemm_fits(g, rows, wA ? w_elems : t_elems, wA ? t_elems : w_elems, out_elems))
     return fail(ctx, TTN_EINVAL, "buffers too small for the contraction");
-  TTN_CHECK_HIP(launch_zgemm(g, rows, ctx->c128 ? GEMM_C128 : GEMM_C64, ctx->st));
+  TTN_CHECK_HIP(launch_zgemm(g, rows, ctx->c128 ? GEMM_C128 : GEMM_C64, ctx->st, ctx->force_cfg));
   TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
   return TTN_OK;
 }
@@ -2403,7 +2407,7 @@ ttn_status ttn_test_gram(ttn_ctx* ctx, int32_t rows, const int32_t* dims3, int32
   g.ksplit = ksplit;
   g.sCz = (long long)rows * d[leg] * d[leg];
   if (!gemm_fits(g, rows, t_elems, t_elems, g_elems)) return fail(ctx, TTN_EINVAL, "buffers too small for the Gram");
-  TTN_CHECK_HIP(launch_zgemm(g, rows, ctx->c128 ? GEMM_GRAM_C128 : GEMM_GRAM_C64, ctx->st));
+  TTN_CHECK_HIP(launch_zgemm(g, rows, ctx->c128 ? GEMM_GRAM_C128 : GEMM_GRAM_C64, ctx->st, ctx->force_cfg));
   TTN_CHECK_HIP(hipStreamSynchronize(ctx->st));
   return TTN_OK;
 }

@@ -264,12 +264,15 @@ class TTNEngine:
     def profile(self, on: bool = True):
         check(lib().ttn_profile_enable(self._ctx, 1 if on else 0), self._ctx)
 
-    def autotune(self, on) -> tuple:
+    def autotune(self, on, force_cfg=None) -> tuple:
         """Tile-shape tuning of the GEMM launches: True measures new shapes,
-        False keeps the measured choices, None forgets them.  Returns
+        False keeps the measured choices, None forgets them; force_cfg = c
+        (0..5) runs every launch in tile shape c instead (testing).  Returns
         (shapes measured, shapes whose choice differs from the fixed rule)."""
         shapes, changed = C.c_int64(0), C.c_int64(0)
         mode = -1 if on is None else (1 if on else 0)
+        if force_cfg is not None:
+            mode = 2 + int(force_cfg)
         check(lib().ttn_autotune(self._ctx, mode, C.byref(shapes), C.byref(changed)), self._ctx)
         return shapes.value, changed.value
 

@@ -93,6 +93,58 @@ def test_leg_contraction(dtype, shape, leg, newd):
     eng.close()
 
 
+# every output-tile shape on every kind of launch, whatever the shape would
+# be chosen for: 64x64, 128x32, 32x128, 32x32 and 16x16 with the K chunk
+# split over the waves, 16x128 (ragged edges in both directions, several
+# tiles, K ranges of one and of several chunks, both operand layouts)
+FORCED_SHAPES = [(3, 5, 7), (20, 33, 17), (1, 70, 40), (40, 6, 130)]
+
+
+@pytest.mark.parametrize("cfg", range(6))
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("shape", FORCED_SHAPES)
+def test_every_tile_shape_contracts_and_grams(cfg, dtype, shape):
+    from paper_2511_05719_amd._abi import lib, check
+    g = np.random.default_rng(zlib.crc32(repr((cfg, dtype, shape)).encode()))
+    rows = 3
+    eng = _engine(dtype)
+    eng.autotune(True, force_cfg=cfg)
+    T = g.normal(size=(rows,) + shape) + 1j * g.normal(size=(rows,) + shape)
+    if dtype == "c64":
+        T = T.astype(np.complex64).astype(np.complex128)
+    Td = _dev_complex(T, dtype)
+    dims = (C.c_int32 * 3)(*shape)
+    tol = 1e-12 if dtype == "c128" else 2e-6
+    for leg in range(3):
+        n = shape[leg]
+        for newd in (3, 37):
+            W = g.normal(size=(rows, newd, n)) + 1j * g.normal(size=(rows, newd, n))
+            if dtype == "c64":
+                W = W.astype(np.complex64).astype(np.complex128)
+            oshape = list(shape)
+            oshape[leg] = newd
+            out = torch.full((rows,) + tuple(oshape) + (2,), float("nan"), dtype=Td.dtype, device="cuda")
+            check(lib().ttn_test_leg_apply(eng._ctx, rows, dims, leg, Td.data_ptr(), T.size,
+                                           _dev_complex(W, dtype).data_ptr(), W.size, newd, out.data_ptr(),
+                                           out.numel() // 2), eng._ctx)
+            sub = {0: "tijk,tai->tajk", 1: "tijk,taj->tiak", 2: "tijk,tak->tija"}[leg]
+            ref = np.einsum(sub, T, W)
+            got = _host_complex(out)
+            assert np.abs(got - ref).max() <= tol * np.sqrt(n) * np.abs(ref).max(), (leg, newd)
+        G = torch.full((1, rows, n, n, 2), float("nan"), dtype=torch.float64, device="cuda")
+        check(lib().ttn_test_gram(eng._ctx, rows, dims, leg, Td.data_ptr(), T.size, G.data_ptr(),
+                                  rows * n * n, 1), eng._ctx)
+        Tm = np.moveaxis(T, 1 + leg, -1).reshape(rows, -1, n)
+        ref = np.einsum("tmi,tmj->tij", Tm.conj(), Tm)
+        got = _host_complex(G)[0]
+        up = np.triu_indices(n)
+        assert np.abs(got[:, up[0], up[1]] - ref[:, up[0], up[1]]).max() <= 1e-13 * np.abs(ref).max(), leg
+        # the diagonal of a Hermitian matrix is written real
+        assert np.all(got[:, np.arange(n), np.arange(n)].imag == 0.0)
+    eng.autotune(None)
+    eng.close()
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("leg", [0, 1, 2])
