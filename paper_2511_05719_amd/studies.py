@@ -16,12 +16,16 @@ return plain dicts, and a command line that writes them as JSON.
   theta = 0.08 and amplitude damping gamma = 3e-3 at every location,
   clustered layout), run in the largest batches that fit the device: its
   failure rate, throughput and device memory per trajectory.
+* srx_grid_vs_twirl: the d = 5, 5-round SRX workload over its theta grid
+  (chi = 64, clustered layout) against the Pauli-twirled version of the same
+  channel on the same random streams, per theta (the twirl as the baseline,
+  Sec. IV.C, Eq. 9).
 
 Every figure is a logical failure rate of the final-data lookup decoder with
 its 99% Wilson interval; the paper's own decoder and schedule are not
 available, so the values are this schedule's, not Table I's or Fig. 5's.
 
-Usage:  python -m paper_2511_05719_amd.studies {pta,truncation,table3,threshold,d7} [--out FILE]
+Usage:  python -m paper_2511_05719_amd.studies {pta,truncation,table3,threshold,d7,grid} [--out FILE]
 """
 from __future__ import annotations
 
@@ -99,6 +103,30 @@ def pta_comparison(distances=(3, 5), shots: int = 10000, theta: float = 2 * math
                 row[tag] = failure_rate(circ, shots, th, ga, chi, seed=seed)
             out["points"].append(row)
             print(json.dumps(row), flush=True)
+    return out
+
+
+def srx_grid_vs_twirl(thetas=tuple(0.02 + i * 0.18 / 7 for i in range(8)), shots: int = 10000, d: int = 5,
+                      rounds: int = 5, chi: int = 64, batch: int = 4096, seed: int = 2) -> dict:
+    """The SRX channel at every theta of the grid against its Pauli twirl
+    (Eq. 9: X flips with p = sin^2(theta / 2)), each on `shots` trajectories
+    of the same random streams, clustered layout, complex64, cutoff 1e-10.
+    The twirled circuit stays a stabilizer state, so chi never binds there;
+    the coherent one is truncated at chi."""
+    from workload import build_circuit
+    out = {"settings": {"d": d, "rounds": rounds, "chi_max": chi, "cutoff": 1e-10, "dtype": "c64",
+                        "layout": "clustered (App. B, Algorithm 1)", "shots_per_point": shots, "seed": seed,
+                        "decoder": "final-data lookup (minimum-weight leader)"},
+           "points": []}
+    circs = {ch: build_circuit(d, rounds, ch, leaf_of_qubit="optimized") for ch in ("srx", "pta_srx")}
+    for j, th in enumerate(thetas):
+        row = {"theta": float(th)}
+        for tag, ch in (("srx", "srx"), ("twirl", "pta_srx")):
+            row[tag] = failure_rate(circs[ch], shots, float(th), 0.0, chi, seed=seed, batch=batch,
+                                    traj_offset=j << 32)
+        out["points"].append(row)
+        print(json.dumps({"theta": row["theta"], "srx": row["srx"]["p_fail"], "twirl": row["twirl"]["p_fail"]}),
+              flush=True)
     return out
 
 
@@ -265,13 +293,15 @@ def distance7(shots: int = 4096, rounds: int = 7, theta: float = 0.08, gamma: fl
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description="the paper's studies on the batched engine")
-    ap.add_argument("study", choices=("pta", "truncation", "table3", "threshold", "d7"))
+    ap.add_argument("study", choices=("pta", "truncation", "table3", "threshold", "d7", "grid"))
     ap.add_argument("--out", default=None)
     ap.add_argument("--shots", type=int, default=None)
-    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--batch", type=int, default=None)
     a = ap.parse_args(argv)
     if a.study == "d7":
-        res = distance7(shots=a.shots or 4096, batch=a.batch)
+        res = distance7(shots=a.shots or 4096, batch=a.batch or 256)
+    elif a.study == "grid":
+        res = srx_grid_vs_twirl(shots=a.shots or 10000, batch=a.batch or 4096)
     elif a.study == "pta":
         res = pta_comparison(shots=a.shots or 10000)
     elif a.study == "truncation":

@@ -54,3 +54,19 @@ def test_exact_bond_dimension_table3_ad():
         assert exact_bond_dimension(3, 3, lay, chi=64, rows=16)["max_rank"] == 16
     r = exact_bond_dimension(5, 1, "optimized", chi=128, rows=8)
     assert r["max_rank"] == 32 and not r["cap_reached"]
+
+
+def test_srx_grid_against_its_twirl_small():
+    # the study's structure on a small sample: both channels on the same
+    # streams per theta, the twirled circuit never above the stabilizer rank
+    # of the clustered layout (16 at d = 5) while the coherent one may reach chi
+    from paper_2511_05719_amd.studies import srx_grid_vs_twirl
+    res = srx_grid_vs_twirl(thetas=(0.05, 0.2), shots=64, batch=64)
+    assert [p["theta"] for p in res["points"]] == [0.05, 0.2]
+    for p in res["points"]:
+        for tag in ("srx", "twirl"):
+            r = p[tag]
+            assert r["shots"] == 64 and 0.0 <= r["p_fail"] <= 1.0 and r["ci99"][0] <= r["p_fail"] <= r["ci99"][1]
+        assert p["twirl"]["max_rank"] <= 16 and p["twirl"]["mean_discarded_weight"] < 1e-6
+        assert p["srx"]["max_rank"] <= 64
+
