@@ -378,7 +378,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the other-layout and gradient legs")
     ap.add_argument("--no-autotune", action="store_true", help="fixed-rule GEMM tile shapes (no measuring "
                     "in the warm-up)")
-    ap.add_argument("--grad-records", type=int, default=64)
+    ap.add_argument("--grad-records", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true", help="only run the 256 MiB copy that "
                     "calibrates the HBM byte counters, then exit")
     args = ap.parse_args()
