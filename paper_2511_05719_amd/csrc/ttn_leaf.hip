@@ -470,23 +470,34 @@ hipError_t launch_ledger_reset(int* adim, int L, int batch, hipStream_t st) {
   return hipGetLastError();
 }
 
-__global__ void __launch_bounds__(256) k_nk_max(const int* nk, int batch, int* out) {
-  __shared__ int red[4][256];
-  int m[4] = {0, 0, 0, 0};
-  for (int t = threadIdx.x; t < batch; t += 256)
-    for (int c = 0; c < 4; ++c) m[c] = max(m[c], nk[(long long)t * 4 + c]);
-  for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = m[c];
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
-      for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = max(red[c][threadIdx.x], red[c][threadIdx.x + w]);
-    __syncthreads();
+// the batch's largest value of each of the four per-row counts: one 16-byte
+// load per row, a wavefront maximum by lane exchange, then across the
+// sixteen wavefronts through LDS
+__global__ void __launch_bounds__(1024) k_nk_max(const int* nk, int batch, int* out) {
+  __shared__ int red[16][4];
+  const int4* v = reinterpret_cast<const int4*>(nk);
+  int m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+  for (int t = threadIdx.x; t < batch; t += 1024) {
+    const int4 x = v[t];
+    m0 = max(m0, x.x); m1 = max(m1, x.y); m2 = max(m2, x.z); m3 = max(m3, x.w);
   }
-  if (threadIdx.x < 4) out[threadIdx.x] = red[threadIdx.x][0];
+  for (int o = 32; o > 0; o >>= 1) {
+    m0 = max(m0, __shfl_xor(m0, o)); m1 = max(m1, __shfl_xor(m1, o));
+    m2 = max(m2, __shfl_xor(m2, o)); m3 = max(m3, __shfl_xor(m3, o));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { red[w][0] = m0; red[w][1] = m1; red[w][2] = m2; red[w][3] = m3; }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    int r = 0;
+    for (int k = 0; k < 16; ++k) r = max(r, red[k][threadIdx.x]);
+    out[threadIdx.x] = r;
+  }
 }
 hipError_t launch_nk_max(const int* nk, int batch, int* out, hipStream_t st) {
   if (batch <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_nk_max, dim3(1), dim3(256), 0, st, nk, batch, out);
+  if (reinterpret_cast<size_t>(nk) & 15) return hipErrorInvalidValue;   // rows are read as int4
+  hipLaunchKernelGGL(k_nk_max, dim3(1), dim3(1024), 0, st, nk, batch, out);
   return hipGetLastError();
 }
 
