@@ -327,6 +327,18 @@ __device__ inline double2 extend_value(const ExtendDesc& d, const S* src, int so
   return cadd(cmul(b0, to_d2(src[so])), cmul(b1, to_d2(src[so2])));
 }
 
+// Extended tensors are written once and read back only by the next launches
+// (far beyond the caches at batch sizes that fill the GPU): non-temporal
+// stores stream them to HBM without allocating in the caches
+__device__ inline void nt_store(float2* p, float2 v) {
+  double w;
+  __builtin_memcpy(&w, &v, 8);
+  __builtin_nontemporal_store(w, reinterpret_cast<double*>(p));
+}
+__device__ inline void nt_store(double2* p, double2 v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+}
 template <typename S>
 __global__ void __launch_bounds__(256) k_extend(ExtendDesc d, int batch, int per) {
   const int r0 = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
@@ -341,10 +353,10 @@ __global__ void __launch_bounds__(256) k_extend(ExtendDesc d, int batch, int per
     const S va = from_d2<S>(extend_value<S>(d, src, a0, a1, ka, rowa));
     if (two) {
       const S vb = from_d2<S>(extend_value<S>(d, src, b0, b1, kb, rowb));
-      dst[r0] = va;
-      dst[r0 + 1] = vb;
+      nt_store(dst + r0, va);
+      nt_store(dst + r0 + 1, vb);
     } else {
-      dst[r0] = va;
+      nt_store(dst + r0, va);
     }
   }
 }
